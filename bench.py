@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput of the fused MRT-LBM step on one MI355X.
+
+Workload: periodic 8192 x 8192 D2Q9 spinodal decomposition in FP32 (phi0 =
+U(-0.05, 0.05) from seed 5, alpha = 0.2, m = 4, Willmore eps = 0.03,
+M = 0.1, interface eps_w = 1.5 -> D = 2 sqrt(2) eps_w, sigma = 0.01).
+One "step" is one lbch_step: pull-stream + phi + all stencils + anisotropic
+chemical potential + equilibrium + source + MRT collision (one kernel).
+
+Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
+(algorithmic 72 B per lattice update in FP32 = 9 populations read + 9
+written) and the oracle's CPU throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_fused_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_03759_amd", "csrc", "lbch_kernels.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(n_nodes: int, precision: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on
+    the current kernel source at this size; else None."""
+    try:
+        rec = json.load(open(PROFILE_TRAFFIC))
+    except Exception:
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash() or rec.get("nodes") != n_nodes or rec.get("precision") != precision:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The oracle (NumPy, FP64, single thread) on a bounded sample of the same workload:
+    a 256 x 256 periodic window of the spinodal field with the workload's parameters."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lbm
+    from paper_2501_03759_amd import inputs
+    d = inputs.C5
+    n = 256
+    width = inputs.width_from_eps(d["eps_w"])
+    kappa, beta = lbm.kappa_beta_from_sigma_width(inputs.SIGMA_PAPER, width)
+    p = lbm.Params(nx=n, ny=n, kappa=kappa, beta=beta, mobility=d["mobility"], alpha=d["alpha"],
+                   aniso_m=d["m"], eps_reg=d["eps_reg"])
+    phi0 = inputs.spinodal(d["n"], d["n"], seed=d["seed"], amp=d["amp"])[:n, :n].copy()
+    with threadpool_limits(limits=1):
+        f = lbm.initial_populations(phi0, p)
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < seconds_target:
+            f = lbm.step(f, p)
+            steps += 1
+        dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of a {n}x{n} window of the workload (FP64 NumPy oracle, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=8192, help="grid side (default: the 8192^2 workload)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2501_03759_amd import inputs, lbch
+
+    d = inputs.C5
+    n = args.n
+    prec = lbch.FP32 if args.precision == "fp32" else lbch.FP64
+    esize = 4 if prec == lbch.FP32 else 8
+    p = lbch.default_params(nx=n, ny=n, precision=prec, sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"])),
+                            mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sim = lbch.Sim(p, stream)
+    if args.tiling:
+        bt, rows = (int(v) for v in args.tiling.split(","))
+        sim.set_tiling(bt, rows)
+    phi0 = inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"])
+    sim.init(phi0)
+    del phi0
+    sim.step(args.warmup)
+    sim.synchronize()
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    ms_step = ms_total / args.steps
+    _, mass, lo, hi = sim.moments(want_phi=False)
+    tiling = sim.tiling()
+    sim.close()
+
+    nodes = n * n
+    mlups = nodes * args.steps / (ms_total * 1e-3) / 1e6
+    alg_bytes = 18 * esize * nodes                     # 9 populations read + 9 written per node
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(nodes, args.precision)}
+    out = {
+        "metric": "MLUPS (lattice updates per second / 1e6), fused MRT-LBM step, 1 GPU",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == lbch.FP32 else "f64",
+        "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
+        "config": {"workload": f"spinodal-{n}x{n}-{args.precision}", "grid": [n, n], "lattice": "D2Q9",
+                   "alpha": d["alpha"], "m": d["m"], "regularization": "willmore", "eps_reg": d["eps_reg"],
+                   "mobility": d["mobility"], "tiling": list(tiling)},
+        "roofline": roofline,
+        "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * lbch.h — C ABI of the MI355X (gfx950) lattice Boltzmann solver for the
+ * anisotropic Cahn–Hilliard equation of Liu, Wang & Liu, "Modelling
+ * anisotropic Cahn-Hilliard equation with the lattice Boltzmann method"
+ * (arXiv 2501.03759).
+ *
+ * One simulation = one periodic D2Q9 grid whose populations live in HBM in
+ * the library's own buffers.  Every call returns an lbch_status (0 = OK,
+ * < 0 = error); no C++ exception crosses the ABI and lbch_last_error()
+ * returns a thread-local message describing the last failure.
+ *
+ * Units: lattice spacing dx and time step dt are parameters (default 1);
+ * c = dx/dt and c_s^2 = c^2/3 (Section 3, below eq 21).
+ *
+ * Ownership: the library owns all device memory it allocates; host arrays
+ * passed in are copied and never retained; device pointers passed in must
+ * stay valid until the work queued on the simulation's stream completes.
+ *
+ * Streams: each simulation is bound to one HIP stream (NULL = the null
+ * stream).  Calls that only enqueue work return before it completes;
+ * calls that return host data synchronise that stream.  A simulation must
+ * not be used from two threads at once; distinct simulations are
+ * independent.
+ */
+#ifndef LBCH_H
+#define LBCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBCH_ABI_VERSION 1
+
+typedef enum lbch_status {
+    LBCH_OK = 0,
+    LBCH_E_INVALID = -1,      /* bad argument or parameter */
+    LBCH_E_UNSUPPORTED = -2,  /* valid in the paper but not built (3D lattice, non-periodic) */
+    LBCH_E_OOM = -3,          /* device or host allocation failed */
+    LBCH_E_DEVICE = -4,       /* HIP runtime error */
+    LBCH_E_NONFINITE = -5,    /* the state holds NaN/Inf (results still written) */
+    LBCH_E_STATE = -6         /* call out of order (e.g. step before init) */
+} lbch_status;
+
+enum { LBCH_D2Q9 = 0, LBCH_D3Q15 = 1 /* eq 21: reserved, returns LBCH_E_UNSUPPORTED */ };
+enum { LBCH_FP64 = 0, LBCH_FP32 = 1 };
+enum { LBCH_BC_PERIODIC = 0 /* Section 4: periodic boundaries */ };
+enum {
+    LBCH_REG_NONE = 0,
+    LBCH_REG_LINEAR = 1,      /* eq 8 / eq 12: eps * Delta^2 phi                     */
+    LBCH_REG_WILLMORE = 2     /* eq 9 / eq 13: eps (Delta - f')(Delta phi - f)        */
+};
+enum {
+    LBCH_Q_DERIVED = 0,       /* Q = kappa (gamma grad phi + |grad phi| P grad_n gamma):
+                                 eq 14 with F ~ kappa |grad phi|^2 / 2 (default)      */
+    LBCH_Q_LITERAL = 1        /* Q = gamma kappa grad phi + |grad phi| P grad_n gamma:
+                                 eq 15 exactly as printed                             */
+};
+
+/*
+ * Problem statement (Sections 2-3).  Fill with lbch_params_default() and
+ * override fields.
+ *   nx, ny        grid nodes (>= 1 each, nx*ny*9 < 2^31), row-major [ny][nx].
+ *   dx, dt        lattice spacing and time step (> 0).
+ *   mobility      M of eq 10 (> 0); sets s_3 = s_5 = 1/(M/(c_s^2 dt) + 1/2)
+ *                 (relation stated after eq 38), which must lie in (0, 2).
+ *   s[9]          relaxation rates of eq 25 for the other moments; s[0] is
+ *                 irrelevant (phi is conserved), s[3] and s[5] are ignored.
+ *                 The paper does not give them; default 1.  Each in (0, 2).
+ *   kappa, beta   gradient and double-well coefficients (eq 1, eq 4), > 0.
+ *                 lbch_params_from_sigma_width() sets them from eq 5.
+ *   alpha         anisotropy strength of eq 6 (>= 0).
+ *   aniso_m       fold of the anisotropy, 1..8 (eq 6 is m = 4): gamma =
+ *                 1 + alpha cos(m (theta - theta0)).
+ *   aniso_theta0  orientation of the anisotropy (eq 6 is theta0 = 0).
+ *   regularization, eps_reg   eq 7-9 and eqs 12/13; eps_reg >= 0.
+ *   q_form        LBCH_Q_DERIVED or LBCH_Q_LITERAL (see above).
+ *   grad_floor    |grad phi| <= grad_floor  =>  gamma = 1 and no tangential
+ *                 term (the normal of eq 2 is undefined); >= 0.
+ */
+typedef struct lbch_params {
+    int32_t abi_version;      /* must equal LBCH_ABI_VERSION */
+    int32_t lattice;          /* LBCH_D2Q9 */
+    int32_t precision;        /* LBCH_FP64 (verification) or LBCH_FP32 (production) */
+    int32_t boundary;         /* LBCH_BC_PERIODIC */
+    int32_t nx, ny;
+    double dx, dt;
+    double mobility;
+    double s[9];
+    double kappa, beta;
+    double alpha;
+    int32_t aniso_m;
+    int32_t regularization;
+    double aniso_theta0;
+    double eps_reg;
+    int32_t q_form;
+    int32_t reserved0;        /* must be 0 */
+    double grad_floor;
+} lbch_params;
+
+typedef struct lbch_sim lbch_sim;   /* opaque; owned by the caller until lbch_destroy */
+
+/* Host-only helpers (no GPU needed). ---------------------------------------- */
+
+/* Paper defaults of eq 39: M = 0.1, eps = 0.03 (Willmore), D = 5, sigma = 0.01
+ * (kappa = 0.01875, beta = 0.0015), 100 x 100 grid, alpha = 0, FP64, free
+ * rates 1.  NULL -> LBCH_E_INVALID. */
+lbch_status lbch_params_default(lbch_params* p);
+
+/* kappa and beta from surface tension sigma and interface width D by
+ * inverting eq 5: kappa = 3 sigma D / 8, beta = 3 sigma / (4 D).
+ * sigma, D > 0 and finite, else LBCH_E_INVALID (p unchanged). */
+lbch_status lbch_params_from_sigma_width(lbch_params* p, double sigma, double width);
+
+/* Checks every field; LBCH_OK, LBCH_E_INVALID or LBCH_E_UNSUPPORTED with the
+ * reason in lbch_last_error(). */
+lbch_status lbch_params_validate(const lbch_params* p);
+
+/* The nine relaxation rates actually used (s_3 = s_5 from the mobility). */
+lbch_status lbch_relaxation_rates(const lbch_params* p, double s_out[9]);
+
+/* Library ABI version (LBCH_ABI_VERSION it was built with). */
+int32_t lbch_abi_version(void);
+
+/* Thread-local description of the last error ("" if none).  Valid until the
+ * next failing call on this thread. */
+const char* lbch_last_error(void);
+
+/* Simulation lifecycle. ------------------------------------------------------ */
+
+/* Validates p, allocates two population buffers (9 planes each, structure of
+ * arrays, rows padded) plus reduction scratch on the current HIP device and
+ * binds the simulation to hip_stream (a hipStream_t; NULL = null stream).
+ * *out is set only on success. */
+lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_sim** out);
+
+/* Frees everything the simulation owns (waits for its stream first). NULL is
+ * accepted. */
+lbch_status lbch_destroy(lbch_sim* sim);
+
+/* Sets the populations to the equilibrium of eq 18 at the initial order
+ * parameter phi0 (host, float64, row-major [ny][nx], n = nx*ny entries),
+ * with mu_alpha of eq 16 evaluated by the eq 26b stencil and no source term
+ * (the paper does not state the initial populations).  Resets the step
+ * counter to 0.  Non-finite phi0 -> LBCH_E_INVALID.  Synchronises. */
+lbch_status lbch_init(lbch_sim* sim, const double* phi0, int64_t n);
+
+/* Same from device memory: phi0_dev holds nx*ny values of dtype LBCH_FP64
+ * or LBCH_FP32, dense row-major.  Stream-ordered, does not synchronise and
+ * does not inspect the values (a non-finite input surfaces as
+ * LBCH_E_NONFINITE from the next lbch_moments). */
+lbch_status lbch_init_device(lbch_sim* sim, const void* phi0_dev, int32_t dtype, int64_t n);
+
+/* Advances nsteps (>= 0) time steps of eq 17: per node phi (eq 22), the
+ * eq 26 stencils, the anisotropic chemical potential (eqs 13/15/16), the
+ * modified equilibrium (eq 18), the source (eq 19), the MRT collision in
+ * moment space (eqs 17, 23, 25) and periodic streaming.  One fused kernel
+ * launch per step, enqueued on the simulation's stream; returns without
+ * waiting.  Before init -> LBCH_E_STATE. */
+lbch_status lbch_step(lbch_sim* sim, int64_t nsteps);
+
+/* Steps taken since the last init / load. */
+lbch_status lbch_get_step(const lbch_sim* sim, int64_t* step);
+
+/* Waits for all work queued on the simulation's stream. */
+lbch_status lbch_synchronize(lbch_sim* sim);
+
+/* Reductions (synchronise). -------------------------------------------------- */
+
+/* phi = sum_i f_i (eq 22) of the current state.  phi_out (host, nullable)
+ * receives nx*ny float64 values row-major; mass = sum phi dx^2 (conserved,
+ * eq 34); phi_min / phi_max.  Sums are accumulated in float64 in a fixed
+ * order (deterministic).  Any pointer may be NULL.  A non-finite value in
+ * the state -> LBCH_E_NONFINITE (outputs still written). */
+lbch_status lbch_moments(lbch_sim* sim, double* phi_out, double* mass,
+                         double* phi_min, double* phi_max);
+
+/* Discrete free energy of eq 7 at the current phi: sum over nodes of
+ * dx^2 [gamma (kappa/2 |grad phi|^2 + F(phi)) + eps/2 G(phi)] with the
+ * eq 26 stencils, F of eq 4 and G of eq 8 / eq 9.  terms4 (nullable)
+ * receives {gradient, bulk, regularisation, total}.  float64 throughout.
+ * Non-finite -> LBCH_E_NONFINITE. */
+lbch_status lbch_free_energy(lbch_sim* sim, double* energy, double* terms4);
+
+/* Writes phi of the current state to device memory (dtype LBCH_FP64 or
+ * LBCH_FP32, nx*ny dense row-major).  Stream-ordered, no synchronisation. */
+lbch_status lbch_phi_device(lbch_sim* sim, void* dst_dev, int32_t dtype);
+
+/* Checkpoint / resume. ------------------------------------------------------- */
+
+/* Size in bytes of a saved state: a fixed header (magic, ABI version, grid,
+ * precision, step, parameters) followed by the pre-collision populations
+ * f_i(x, t) of eq 17 as 9 dense planes [9][ny][nx] in the simulation's
+ * precision. */
+lbch_status lbch_state_bytes(const lbch_sim* sim, int64_t* bytes);
+
+/* Saves to dst (host memory if dst_is_device == 0, else device memory), which
+ * must hold lbch_state_bytes() bytes.  Synchronises. */
+lbch_status lbch_save_state(lbch_sim* sim, void* dst, int32_t dst_is_device);
+
+/* Restores a state saved from a simulation with the same grid and precision;
+ * the step counter is restored; other parameters are those of sim (so a run
+ * can be resumed with changed physics).  Mismatch -> LBCH_E_INVALID.
+ * Synchronises. */
+lbch_status lbch_load_state(lbch_sim* sim, const void* src, int32_t src_is_device);
+
+/* Launch shape of the fused step kernel. -------------------------------------- */
+
+/* block_threads in {64, 128, 256, 512}: each workgroup owns a strip of
+ * block_threads - 6 columns; rows_per_block >= 1 rows of that strip are
+ * swept per workgroup.  The result is bitwise independent of the choice.
+ * 0 for either argument restores the built-in default for the grid. */
+lbch_status lbch_set_tiling(lbch_sim* sim, int32_t block_threads, int32_t rows_per_block);
+lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t* rows_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBCH_H */

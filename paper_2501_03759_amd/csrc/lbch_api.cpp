@@ -1,0 +1,533 @@
+// C-ABI layer of liblbch: parameter handling, buffers, launches, reductions,
+// checkpointing.  See include/lbch.h for the contract of every entry point.
+#include "../../include/lbch.h"
+#include "lbch_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lbch;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbch_status fail(lbch_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+lbch_status fail(lbch_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+lbch_status ok() { return LBCH_OK; }
+
+#define HIP_TRY(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(LBCH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool isfin(double v) { return std::isfinite(v); }
+
+double s_j_of(const lbch_params* p) {
+    const double c = p->dx / p->dt;
+    const double cs2 = c * c / 3.0;
+    return 1.0 / (p->mobility / (cs2 * p->dt) + 0.5);
+}
+
+}  // namespace
+
+struct lbch_sim {
+    lbch_params p{};
+    int precision = 0;
+    size_t esize = 8;
+    Grid g{};
+    Tiling t{};
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    hipStream_t stream = nullptr;
+    int64_t step = 0;
+    bool initialized = false;
+    double* phi64 = nullptr;         // nx*ny float64 scratch for reductions
+    double* partials = nullptr;      // kRedBlocks * 4
+    double* result = nullptr;        // 8 doubles (device)
+    unsigned* bad = nullptr;         // non-finite counter of init_device
+    StepCoef<double> cd{};
+    StepCoef<float> cf{};
+    RedCoef rc{};
+    int user_nt = 0, user_hc = 0;
+};
+
+// ------------------------------------------------------------ host helpers
+extern "C" int32_t lbch_abi_version(void) { return LBCH_ABI_VERSION; }
+
+extern "C" const char* lbch_last_error(void) { return g_err.c_str(); }
+
+extern "C" lbch_status lbch_params_default(lbch_params* p) {
+    if (!p) return fail(LBCH_E_INVALID, "params pointer is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->abi_version = LBCH_ABI_VERSION;
+    p->lattice = LBCH_D2Q9;
+    p->precision = LBCH_FP64;
+    p->boundary = LBCH_BC_PERIODIC;
+    p->nx = 100;
+    p->ny = 100;
+    p->dx = 1.0;
+    p->dt = 1.0;
+    p->mobility = 0.1;
+    for (double& s : p->s) s = 1.0;
+    p->alpha = 0.0;
+    p->aniso_m = 4;
+    p->aniso_theta0 = 0.0;
+    p->regularization = LBCH_REG_WILLMORE;
+    p->eps_reg = 0.03;
+    p->q_form = LBCH_Q_DERIVED;
+    p->grad_floor = 1e-10;
+    return lbch_params_from_sigma_width(p, 0.01, 5.0);
+}
+
+extern "C" lbch_status lbch_params_from_sigma_width(lbch_params* p, double sigma, double width) {
+    if (!p) return fail(LBCH_E_INVALID, "params pointer is NULL");
+    if (!(sigma > 0) || !(width > 0) || !isfin(sigma) || !isfin(width))
+        return fail(LBCH_E_INVALID, "sigma and width must be positive and finite (got %g, %g)", sigma, width);
+    // eq 5 inverted: sigma D = 8 kappa / 3 and sigma / D = 4 beta / 3
+    p->kappa = 3.0 * sigma * width / 8.0;
+    p->beta = 3.0 * sigma / (4.0 * width);
+    return ok();
+}
+
+extern "C" lbch_status lbch_params_validate(const lbch_params* p) {
+    if (!p) return fail(LBCH_E_INVALID, "params pointer is NULL");
+    if (p->abi_version != LBCH_ABI_VERSION)
+        return fail(LBCH_E_INVALID, "abi_version %d != %d", p->abi_version, LBCH_ABI_VERSION);
+    if (p->lattice == LBCH_D3Q15) return fail(LBCH_E_UNSUPPORTED, "D3Q15 (eq 21) is not built");
+    if (p->lattice != LBCH_D2Q9) return fail(LBCH_E_INVALID, "unknown lattice %d", p->lattice);
+    if (p->boundary != LBCH_BC_PERIODIC) return fail(LBCH_E_UNSUPPORTED, "only periodic boundaries are built");
+    if (p->precision != LBCH_FP64 && p->precision != LBCH_FP32)
+        return fail(LBCH_E_INVALID, "unknown precision %d", p->precision);
+    if (p->nx < 1 || p->ny < 1) return fail(LBCH_E_INVALID, "grid %d x %d must be >= 1 x 1", p->nx, p->ny);
+    const long long pitch = ((long long)p->nx + 63) / 64 * 64;
+    if (pitch * (long long)p->ny * 9 >= (1LL << 31))
+        return fail(LBCH_E_INVALID, "grid %d x %d exceeds 2^31 population entries", p->nx, p->ny);
+    if (!(p->dx > 0) || !(p->dt > 0) || !isfin(p->dx) || !isfin(p->dt))
+        return fail(LBCH_E_INVALID, "dx, dt must be positive and finite");
+    if (!(p->mobility > 0) || !isfin(p->mobility)) return fail(LBCH_E_INVALID, "mobility must be > 0");
+    const double sj = s_j_of(p);
+    if (!(sj > 0 && sj < 2)) return fail(LBCH_E_INVALID, "s_3 = s_5 = %g outside (0, 2)", sj);
+    for (int k = 1; k < 9; ++k) {
+        if (k == 3 || k == 5) continue;
+        if (!(p->s[k] > 0 && p->s[k] < 2)) return fail(LBCH_E_INVALID, "s[%d] = %g outside (0, 2)", k, p->s[k]);
+    }
+    if (!(p->kappa > 0) || !isfin(p->kappa) || !(p->beta > 0) || !isfin(p->beta))
+        return fail(LBCH_E_INVALID, "kappa, beta must be positive and finite");
+    if (!(p->alpha >= 0) || !isfin(p->alpha)) return fail(LBCH_E_INVALID, "alpha must be >= 0");
+    if (p->aniso_m < 1 || p->aniso_m > 8) return fail(LBCH_E_INVALID, "aniso_m %d outside 1..8", p->aniso_m);
+    if (!isfin(p->aniso_theta0)) return fail(LBCH_E_INVALID, "aniso_theta0 not finite");
+    if (p->regularization < LBCH_REG_NONE || p->regularization > LBCH_REG_WILLMORE)
+        return fail(LBCH_E_INVALID, "unknown regularization %d", p->regularization);
+    if (!(p->eps_reg >= 0) || !isfin(p->eps_reg)) return fail(LBCH_E_INVALID, "eps_reg must be >= 0");
+    if (p->q_form != LBCH_Q_DERIVED && p->q_form != LBCH_Q_LITERAL)
+        return fail(LBCH_E_INVALID, "unknown q_form %d", p->q_form);
+    if (!(p->grad_floor >= 0) || !isfin(p->grad_floor)) return fail(LBCH_E_INVALID, "grad_floor must be >= 0");
+    if (p->reserved0 != 0) return fail(LBCH_E_INVALID, "reserved0 must be 0");
+    return ok();
+}
+
+extern "C" lbch_status lbch_relaxation_rates(const lbch_params* p, double s_out[9]) {
+    if (!p || !s_out) return fail(LBCH_E_INVALID, "NULL argument");
+    for (int k = 0; k < 9; ++k) s_out[k] = p->s[k];
+    s_out[3] = s_out[5] = s_j_of(p);
+    return ok();
+}
+
+// ---------------------------------------------------------------- helpers
+namespace {
+
+template <typename T>
+void fill_coef(const lbch_params* p, StepCoef<T>& c) {
+    const double dx = p->dx, dt = p->dt, cc = dx / dt;
+    double s[9];
+    lbch_relaxation_rates(p, s);
+    c.g3 = (T)(1.0 / 3.0 / dx);
+    c.g12 = (T)(1.0 / 12.0 / dx);
+    c.l23 = (T)(2.0 / 3.0 / (dx * dx));
+    c.l16 = (T)(1.0 / 6.0 / (dx * dx));
+    c.l103 = (T)(10.0 / 3.0 / (dx * dx));
+    c.kappa = (T)p->kappa;
+    c.beta4 = (T)(4.0 * p->beta);
+    c.eps = (T)(p->regularization == LBCH_REG_NONE ? 0.0 : p->eps_reg);
+    c.alpha = (T)p->alpha;
+    c.floor2 = (T)(p->grad_floor * p->grad_floor);
+    c.rot_c = (T)std::cos(p->aniso_m * p->aniso_theta0);
+    c.rot_s = (T)std::sin(p->aniso_m * p->aniso_theta0);
+    c.alpha_m = (T)(p->alpha * p->aniso_m);
+    const double nrm[9] = {9, 36, 36, 6, 12, 6, 12, 4, 4};
+    c.cs1 = (T)(s[1] / nrm[1]);
+    c.cs2 = (T)(s[2] / nrm[2]);
+    c.cs3 = (T)(s[3] / nrm[3]);
+    c.cs4 = (T)(s[4] / nrm[4]);
+    c.cs5 = (T)(s[5] / nrm[5]);
+    c.cs6 = (T)(s[6] / nrm[6]);
+    c.cs7 = (T)(s[7] / nrm[7]);
+    c.cs8 = (T)(s[8] / nrm[8]);
+    // F_m = (c/3) (0,0,0,-gx,gx,-gy,gy,0,0); Delta_k = s_k (m_k - meq_k) - dt (1 - s_k/2) F_k
+    c.cf3 = (T)(dt * (1.0 - s[3] / 2.0) * (cc / 3.0) / nrm[3]);
+    c.cf4 = (T)(dt * (1.0 - s[4] / 2.0) * (cc / 3.0) / nrm[4]);
+    c.cf5 = (T)(dt * (1.0 - s[5] / 2.0) * (cc / 3.0) / nrm[5]);
+    c.cf6 = (T)(dt * (1.0 - s[6] / 2.0) * (cc / 3.0) / nrm[6]);
+    c.m = p->aniso_m;
+    c.reg = p->regularization;
+    c.qform = p->q_form;
+    c.pad_ = 0;
+}
+
+void fill_red(const lbch_params* p, RedCoef& r) {
+    const double dx = p->dx;
+    r.g3 = 1.0 / 3.0 / dx;
+    r.g12 = 1.0 / 12.0 / dx;
+    r.l23 = 2.0 / 3.0 / (dx * dx);
+    r.l16 = 1.0 / 6.0 / (dx * dx);
+    r.l103 = 10.0 / 3.0 / (dx * dx);
+    r.kappa = p->kappa;
+    r.beta = p->beta;
+    r.eps = p->regularization == LBCH_REG_NONE ? 0.0 : p->eps_reg;
+    r.alpha = p->alpha;
+    r.floor2 = p->grad_floor * p->grad_floor;
+    r.rot_c = std::cos(p->aniso_m * p->aniso_theta0);
+    r.rot_s = std::sin(p->aniso_m * p->aniso_theta0);
+    r.area = dx * dx;
+    r.m = p->aniso_m;
+    r.reg = p->regularization;
+}
+
+Tiling make_tiling(int nx, int ny, int nt, int hc) {
+    if (nt == 0) {
+        // smallest lane count over the row, ties to the larger block
+        const int cand[4] = {64, 128, 256, 512};
+        long long best = -1;
+        for (int k = 0; k < 4; ++k) {
+            const int W = cand[k] - 6;
+            const long long cost = (long long)((nx + W - 1) / W) * cand[k];
+            if (best < 0 || cost <= best) {
+                best = cost;
+                nt = cand[k];
+            }
+        }
+    }
+    Tiling t{};
+    t.nt = nt;
+    t.W = nt - 6;
+    t.strips = (nx + t.W - 1) / t.W;
+    if (hc == 0) {
+        long long want = (long long)t.strips * ny / 2048;
+        hc = (int)(want < 16 ? 16 : (want > 256 ? 256 : want));
+    }
+    t.hc = hc < ny ? hc : ny;
+    t.chunks = (ny + t.hc - 1) / t.hc;
+    t.ntiles = t.strips * t.chunks;
+    t.per_xcd = (t.ntiles + 7) / 8;
+    t.nblocks = 8 * t.per_xcd;
+    return t;
+}
+
+const void* coef_ptr(const lbch_sim* s) {
+    return s->precision == LBCH_FP64 ? (const void*)&s->cd : (const void*)&s->cf;
+}
+
+lbch_status check_sim(const lbch_sim* s) {
+    if (!s) return fail(LBCH_E_INVALID, "simulation handle is NULL");
+    return ok();
+}
+
+lbch_status check_init(const lbch_sim* s) {
+    if (!s) return fail(LBCH_E_INVALID, "simulation handle is NULL");
+    if (!s->initialized) return fail(LBCH_E_STATE, "simulation not initialised (call lbch_init first)");
+    return ok();
+}
+
+void free_all(lbch_sim* s) {
+    if (s->f[0]) (void)hipFree(s->f[0]);
+    if (s->f[1]) (void)hipFree(s->f[1]);
+    if (s->phi64) (void)hipFree(s->phi64);
+    if (s->partials) (void)hipFree(s->partials);
+    if (s->result) (void)hipFree(s->result);
+    if (s->bad) (void)hipFree(s->bad);
+}
+
+struct StateHeader {
+    char magic[8];            // "LBCHST01"
+    int32_t abi_version;
+    int32_t precision;
+    int32_t nx, ny;
+    int64_t step;
+    lbch_params params;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------- lifecycle
+extern "C" lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_sim** out) {
+    if (!out) return fail(LBCH_E_INVALID, "out pointer is NULL");
+    lbch_status st = lbch_params_validate(p);
+    if (st != LBCH_OK) return st;
+    lbch_sim* s = new (std::nothrow) lbch_sim();
+    if (!s) return fail(LBCH_E_OOM, "host allocation failed");
+    s->p = *p;
+    s->precision = p->precision;
+    s->esize = p->precision == LBCH_FP64 ? 8 : 4;
+    s->stream = (hipStream_t)hip_stream;
+    s->g.nx = p->nx;
+    s->g.ny = p->ny;
+    s->g.pitch = (p->nx + 63) / 64 * 64;
+    s->g.pad_ = 0;
+    // planes padded by 256 elements so that the nine planes do not alias in
+    // the same DRAM channel at power-of-two sizes
+    s->g.plane = (long long)s->g.pitch * p->ny + 256;
+    s->t = make_tiling(p->nx, p->ny, 0, 0);
+    fill_coef<double>(p, s->cd);
+    fill_coef<float>(p, s->cf);
+    fill_red(p, s->rc);
+    const size_t fbytes = (size_t)s->g.plane * 9 * s->esize;
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc(&s->f[0], fbytes)) != hipSuccess || (e = hipMalloc(&s->f[1], fbytes)) != hipSuccess ||
+        (e = hipMalloc((void**)&s->phi64, (size_t)p->nx * p->ny * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&s->partials, (size_t)kRedBlocks * 4 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&s->result, 8 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&s->bad, sizeof(unsigned))) != hipSuccess) {
+        free_all(s);
+        delete s;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? LBCH_E_OOM : LBCH_E_DEVICE, "device allocation failed: %s",
+                    hipGetErrorString(e));
+    }
+    *out = s;
+    return ok();
+}
+
+extern "C" lbch_status lbch_destroy(lbch_sim* s) {
+    if (!s) return ok();
+    (void)hipStreamSynchronize(s->stream);
+    free_all(s);
+    delete s;
+    return ok();
+}
+
+extern "C" lbch_status lbch_init_device(lbch_sim* s, const void* phi0_dev, int32_t dtype, int64_t n) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (!phi0_dev) return fail(LBCH_E_INVALID, "phi0 pointer is NULL");
+    if (dtype != LBCH_FP64 && dtype != LBCH_FP32) return fail(LBCH_E_INVALID, "unknown dtype %d", dtype);
+    if (n != (int64_t)s->g.nx * s->g.ny)
+        return fail(LBCH_E_INVALID, "n = %lld but the grid has %lld nodes", (long long)n,
+                    (long long)s->g.nx * s->g.ny);
+    HIP_TRY(hipMemsetAsync(s->bad, 0, sizeof(unsigned), s->stream));
+    HIP_TRY(launch_init(s->precision, phi0_dev, dtype, s->f[0], s->g, coef_ptr(s), s->bad, s->stream));
+    s->cur = 0;
+    s->step = 0;
+    s->initialized = true;
+    return ok();
+}
+
+extern "C" lbch_status lbch_init(lbch_sim* s, const double* phi0, int64_t n) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (!phi0) return fail(LBCH_E_INVALID, "phi0 pointer is NULL");
+    const int64_t nn = (int64_t)s->g.nx * s->g.ny;
+    if (n != nn) return fail(LBCH_E_INVALID, "n = %lld but the grid has %lld nodes", (long long)n, (long long)nn);
+    for (int64_t i = 0; i < nn; ++i)
+        if (!std::isfinite(phi0[i])) return fail(LBCH_E_INVALID, "phi0[%lld] is not finite", (long long)i);
+    // stage through the reduction scratch (float64, nx*ny)
+    HIP_TRY(hipMemcpyAsync(s->phi64, phi0, (size_t)nn * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    st = lbch_init_device(s, s->phi64, LBCH_FP64, n);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return ok();
+}
+
+extern "C" lbch_status lbch_step(lbch_sim* s, int64_t nsteps) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    if (nsteps < 0) return fail(LBCH_E_INVALID, "nsteps = %lld < 0", (long long)nsteps);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        HIP_TRY(launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t, coef_ptr(s), s->stream));
+        s->cur ^= 1;
+        s->step += 1;
+    }
+    return ok();
+}
+
+extern "C" lbch_status lbch_get_step(const lbch_sim* s, int64_t* step) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (!step) return fail(LBCH_E_INVALID, "step pointer is NULL");
+    *step = s->step;
+    return ok();
+}
+
+extern "C" lbch_status lbch_synchronize(lbch_sim* s) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return ok();
+}
+
+// ------------------------------------------------------------ reductions
+namespace {
+
+// phi (float64) into s->phi64 and {sum, min, max, nonfinite} into host out4.
+lbch_status phi_reduce(lbch_sim* s, double out4[4]) {
+    HIP_TRY(launch_moments(s->precision, s->f[s->cur], s->g, s->phi64, 0, s->partials, kRedBlocks, s->stream));
+    const int kinds[4] = {0, 1, 2, 0};
+    HIP_TRY(launch_finalize(s->partials, kRedBlocks, 4, kinds, s->result, s->stream));
+    HIP_TRY(hipMemcpyAsync(out4, s->result, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    unsigned bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, s->bad, sizeof bad, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (bad) out4[3] += bad;
+    return ok();
+}
+
+}  // namespace
+
+extern "C" lbch_status lbch_moments(lbch_sim* s, double* phi_out, double* mass, double* phi_min, double* phi_max) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    double r[4];
+    st = phi_reduce(s, r);
+    if (st != LBCH_OK) return st;
+    if (phi_out)
+        HIP_TRY(hipMemcpy(phi_out, s->phi64, (size_t)s->g.nx * s->g.ny * sizeof(double), hipMemcpyDeviceToHost));
+    if (mass) *mass = r[0] * s->p.dx * s->p.dx;
+    if (phi_min) *phi_min = r[1];
+    if (phi_max) *phi_max = r[2];
+    if (r[3] != 0.0) return fail(LBCH_E_NONFINITE, "state holds %.0f non-finite phi values", r[3]);
+    return ok();
+}
+
+extern "C" lbch_status lbch_free_energy(lbch_sim* s, double* energy, double* terms4) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    double r[4];
+    st = phi_reduce(s, r);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(launch_energy(s->phi64, s->g, s->rc, s->partials, kRedBlocks, s->stream));
+    const int kinds[4] = {0, 0, 0, 0};
+    HIP_TRY(launch_finalize(s->partials, kRedBlocks, 4, kinds, s->result, s->stream));
+    double e[4];
+    HIP_TRY(hipMemcpyAsync(e, s->result, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double a = s->rc.area;
+    const double tg = e[0] * a, tb = e[1] * a, tr = e[2] * a;
+    if (energy) *energy = tg + tb + tr;
+    if (terms4) {
+        terms4[0] = tg;
+        terms4[1] = tb;
+        terms4[2] = tr;
+        terms4[3] = tg + tb + tr;
+    }
+    if (r[3] != 0.0 || e[3] != 0.0) return fail(LBCH_E_NONFINITE, "free energy of a non-finite state");
+    return ok();
+}
+
+extern "C" lbch_status lbch_phi_device(lbch_sim* s, void* dst, int32_t dtype) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    if (!dst) return fail(LBCH_E_INVALID, "dst is NULL");
+    if (dtype != LBCH_FP64 && dtype != LBCH_FP32) return fail(LBCH_E_INVALID, "unknown dtype %d", dtype);
+    HIP_TRY(launch_moments(s->precision, s->f[s->cur], s->g, dst, dtype, s->partials, kRedBlocks, s->stream));
+    return ok();
+}
+
+// ---------------------------------------------------------- checkpointing
+extern "C" lbch_status lbch_state_bytes(const lbch_sim* s, int64_t* bytes) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (!bytes) return fail(LBCH_E_INVALID, "bytes pointer is NULL");
+    *bytes = (int64_t)sizeof(StateHeader) + (int64_t)9 * s->g.nx * s->g.ny * (int64_t)s->esize;
+    return ok();
+}
+
+extern "C" lbch_status lbch_save_state(lbch_sim* s, void* dst, int32_t dst_is_device) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    if (!dst) return fail(LBCH_E_INVALID, "dst is NULL");
+    StateHeader h{};
+    std::memcpy(h.magic, "LBCHST01", 8);
+    h.abi_version = LBCH_ABI_VERSION;
+    h.precision = s->precision;
+    h.nx = s->g.nx;
+    h.ny = s->g.ny;
+    h.step = s->step;
+    h.params = s->p;
+    const size_t body = (size_t)9 * s->g.nx * s->g.ny * s->esize;
+    // the idle population buffer holds the dense copy
+    void* tmp = s->f[s->cur ^ 1];
+    HIP_TRY(launch_gather(s->precision, s->f[s->cur], s->g, tmp, s->stream));
+    if (dst_is_device) {
+        HIP_TRY(hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync((char*)dst + sizeof h, tmp, body, hipMemcpyDeviceToDevice, s->stream));
+    } else {
+        std::memcpy(dst, &h, sizeof h);
+        HIP_TRY(hipMemcpyAsync((char*)dst + sizeof h, tmp, body, hipMemcpyDeviceToHost, s->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return ok();
+}
+
+extern "C" lbch_status lbch_load_state(lbch_sim* s, const void* src, int32_t src_is_device) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (!src) return fail(LBCH_E_INVALID, "src is NULL");
+    StateHeader h{};
+    if (src_is_device) HIP_TRY(hipMemcpy(&h, src, sizeof h, hipMemcpyDeviceToHost));
+    else std::memcpy(&h, src, sizeof h);
+    if (std::memcmp(h.magic, "LBCHST01", 8) != 0) return fail(LBCH_E_INVALID, "not an lbch state (bad magic)");
+    if (h.abi_version != LBCH_ABI_VERSION) return fail(LBCH_E_INVALID, "state ABI %d", h.abi_version);
+    if (h.precision != s->precision || h.nx != s->g.nx || h.ny != s->g.ny)
+        return fail(LBCH_E_INVALID, "state is %dx%d precision %d, simulation is %dx%d precision %d", h.nx, h.ny,
+                    h.precision, s->g.nx, s->g.ny, s->precision);
+    const size_t body = (size_t)9 * s->g.nx * s->g.ny * s->esize;
+    void* tmp = s->f[s->cur ^ 1];
+    HIP_TRY(hipMemcpyAsync(tmp, (const char*)src + sizeof h, body,
+                           src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_scatter(s->precision, tmp, s->g, s->f[s->cur], s->stream));
+    HIP_TRY(hipMemsetAsync(s->bad, 0, sizeof(unsigned), s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->step = h.step;
+    s->initialized = true;
+    return ok();
+}
+
+// ---------------------------------------------------------------- tiling
+extern "C" lbch_status lbch_set_tiling(lbch_sim* s, int32_t block_threads, int32_t rows_per_block) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256 &&
+        block_threads != 512)
+        return fail(LBCH_E_INVALID, "block_threads %d not in {64, 128, 256, 512}", block_threads);
+    if (rows_per_block < 0) return fail(LBCH_E_INVALID, "rows_per_block %d < 0", rows_per_block);
+    s->user_nt = block_threads;
+    s->user_hc = rows_per_block;
+    s->t = make_tiling(s->g.nx, s->g.ny, block_threads, rows_per_block);
+    return ok();
+}
+
+extern "C" lbch_status lbch_get_tiling(const lbch_sim* s, int32_t* block_threads, int32_t* rows_per_block) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (block_threads) *block_threads = s->t.nt;
+    if (rows_per_block) *rows_per_block = s->t.hc;
+    return ok();
+}

@@ -1,0 +1,66 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbch {
+
+// Geometry of one periodic grid as stored in HBM: 9 population planes
+// (structure of arrays), each ny rows of `pitch` elements (pitch >= nx).
+struct Grid {
+    int nx, ny, pitch;
+    int pad_;
+    long long plane;      // elements between consecutive population planes
+};
+
+// Decomposition of the fused step: strips of W = NT - 6 columns, chunks of
+// `hc` rows; tiles are strip-fastest; blocks are dealt to the 8 XCDs in
+// contiguous tile ranges of `per_xcd`.
+struct Tiling {
+    int nt, W, strips, hc, chunks, ntiles, per_xcd, nblocks;
+};
+
+// Per-step constants in the working precision T (lattice units folded in).
+template <typename T>
+struct StepCoef {
+    T g3, g12;            // gradient eq 26a: (1/3)/dx, (1/12)/dx
+    T l23, l16, l103;     // Laplacian eq 26b: (2/3)/dx^2, (1/6)/dx^2, (10/3)/dx^2
+    T kappa, beta4, eps, alpha, floor2;
+    T rot_c, rot_s;       // cos(m theta0), sin(m theta0)
+    T alpha_m;            // alpha * m
+    T cs1, cs2, cs3, cs4, cs5, cs6, cs7, cs8;   // s_k / |row k of M|^2
+    T cf3, cf4, cf5, cf6;                       // dt (1 - s_k/2) (c/3) / |row k|^2
+    int m, reg, qform, pad_;
+};
+
+// Reduction constants (always float64).
+struct RedCoef {
+    double g3, g12, l23, l16, l103;
+    double kappa, beta, eps, alpha, floor2, rot_c, rot_s, area;
+    int m, reg;
+};
+
+enum { REG_NONE = 0, REG_LINEAR = 1, REG_WILLMORE = 2 };
+
+// Launchers (lbch_kernels.hip).  All are stream-ordered and return the
+// launch status.
+hipError_t launch_step(int precision, const void* fin, void* fout, const Grid& g, const Tiling& t,
+                       const void* coef, hipStream_t s);
+hipError_t launch_init(int precision, const void* phi0, int phi_dtype, void* fout, const Grid& g,
+                       const void* coef, unsigned* bad_count, hipStream_t s);
+// phi of the current state (float64 math) -> optional dense output + partial sums
+hipError_t launch_moments(int precision, const void* fin, const Grid& g, void* phi_out, int out_dtype,
+                          double* partials, int nparts, hipStream_t s);
+hipError_t launch_energy(const double* phi, const Grid& g, const RedCoef& c, double* partials,
+                         int nparts, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nparts, int nvals, const int* kinds,
+                           double* out, hipStream_t s);
+hipError_t launch_gather(int precision, const void* fin, const Grid& g, void* dense, hipStream_t s);
+hipError_t launch_scatter(int precision, const void* dense, const Grid& g, void* fout, hipStream_t s);
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+
+constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
+constexpr int kRedThreads = 256;
+
+}  // namespace lbch

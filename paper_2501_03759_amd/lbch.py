@@ -1,0 +1,242 @@
+"""Thin ctypes binding of liblbch (include/lbch.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels.  PyTorch is
+imported first so that the process holds one HIP runtime (the library links
+against the same soname); torch is used only to hand device pointers and
+streams to the library.  If the library is missing this module raises: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # one HIP runtime per process: torch's, loaded before the library
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbch.so")
+
+OK, E_INVALID, E_UNSUPPORTED, E_OOM, E_DEVICE, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5, -6
+D2Q9, D3Q15 = 0, 1
+FP64, FP32 = 0, 1
+BC_PERIODIC = 0
+REG_NONE, REG_LINEAR, REG_WILLMORE = 0, 1, 2
+Q_DERIVED, Q_LITERAL = 0, 1
+ABI_VERSION = 1
+
+
+class LbchError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func} -> {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("lattice", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("boundary", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("mobility", ctypes.c_double),
+        ("s", ctypes.c_double * 9),
+        ("kappa", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("aniso_m", ctypes.c_int32),
+        ("regularization", ctypes.c_int32),
+        ("aniso_theta0", ctypes.c_double),
+        ("eps_reg", ctypes.c_double),
+        ("q_form", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("grad_floor", ctypes.c_double),
+    ]
+
+
+_SIGNATURES = {
+    "lbch_abi_version": (ctypes.c_int32, []),
+    "lbch_last_error": (ctypes.c_char_p, []),
+    "lbch_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "lbch_params_from_sigma_width": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double]),
+    "lbch_params_validate": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "lbch_relaxation_rates": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_double)]),
+    "lbch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "lbch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbch_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
+    "lbch_init_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+    "lbch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "lbch_get_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "lbch_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbch_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "lbch_free_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "lbch_phi_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_state_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "lbch_save_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_load_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "lbch_get_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads liblbch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2501_03759_amd.build); there is no CPU fallback")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status: int, func: str):
+    if status != OK:
+        raise LbchError(status, func, lib().lbch_last_error().decode())
+
+
+def _dp(x):
+    return ctypes.cast(x, ctypes.POINTER(ctypes.c_double)) if x is not None else None
+
+
+def default_params(**overrides) -> Params:
+    """Eq 39 defaults, then keyword overrides (s may be a 9-sequence)."""
+    p = Params()
+    _check(lib().lbch_params_default(ctypes.byref(p)), "lbch_params_default")
+    sigma_width = overrides.pop("sigma_width", None)
+    if sigma_width is not None:
+        _check(lib().lbch_params_from_sigma_width(ctypes.byref(p), *sigma_width), "lbch_params_from_sigma_width")
+    for k, v in overrides.items():
+        if k == "s":
+            for i, sv in enumerate(v):
+                p.s[i] = sv
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def validate(p: Params) -> int:
+    return lib().lbch_params_validate(ctypes.byref(p))
+
+
+def relaxation_rates(p: Params) -> np.ndarray:
+    out = (ctypes.c_double * 9)()
+    _check(lib().lbch_relaxation_rates(ctypes.byref(p), out), "lbch_relaxation_rates")
+    return np.array(out[:])
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        return ctypes.c_void_p(None)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)      # torch.cuda.Stream
+
+
+class Sim:
+    """One periodic grid (lbch_sim)."""
+
+    def __init__(self, params: Params, stream=None):
+        self.params = params
+        self._h = ctypes.c_void_p()
+        _check(lib().lbch_create(ctypes.byref(params), _stream_handle(stream), ctypes.byref(self._h)), "lbch_create")
+        self.nx, self.ny = params.nx, params.ny
+
+    def close(self):
+        if self._h:
+            lib().lbch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def init(self, phi0: np.ndarray):
+        a = np.ascontiguousarray(phi0, dtype=np.float64)
+        _check(lib().lbch_init(self._h, _dp(a.ctypes.data), a.size), "lbch_init")
+
+    def init_device(self, ptr: int, dtype: int, n: int):
+        _check(lib().lbch_init_device(self._h, ctypes.c_void_p(ptr), dtype, n), "lbch_init_device")
+
+    def step(self, n: int = 1):
+        _check(lib().lbch_step(self._h, int(n)), "lbch_step")
+
+    @property
+    def nstep(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().lbch_get_step(self._h, ctypes.byref(v)), "lbch_get_step")
+        return v.value
+
+    def synchronize(self):
+        _check(lib().lbch_synchronize(self._h), "lbch_synchronize")
+
+    def moments(self, want_phi: bool = True, check: bool = True):
+        phi = np.empty((self.ny, self.nx), dtype=np.float64) if want_phi else None
+        mass, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = lib().lbch_moments(self._h, _dp(phi.ctypes.data) if want_phi else None, ctypes.byref(mass),
+                                ctypes.byref(lo), ctypes.byref(hi))
+        if check:
+            _check(st, "lbch_moments")
+        return phi, mass.value, lo.value, hi.value
+
+    def phi(self) -> np.ndarray:
+        return self.moments(True)[0]
+
+    def free_energy(self):
+        e = ctypes.c_double()
+        terms = (ctypes.c_double * 4)()
+        _check(lib().lbch_free_energy(self._h, ctypes.byref(e), terms), "lbch_free_energy")
+        return e.value, list(terms)
+
+    def phi_device(self, ptr: int, dtype: int):
+        _check(lib().lbch_phi_device(self._h, ctypes.c_void_p(ptr), dtype), "lbch_phi_device")
+
+    def state_bytes(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().lbch_state_bytes(self._h, ctypes.byref(v)), "lbch_state_bytes")
+        return v.value
+
+    def save_state(self) -> bytes:
+        buf = ctypes.create_string_buffer(self.state_bytes())
+        _check(lib().lbch_save_state(self._h, buf, 0), "lbch_save_state")
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().lbch_load_state(self._h, buf, 0), "lbch_load_state")
+
+    def set_tiling(self, block_threads: int, rows_per_block: int):
+        _check(lib().lbch_set_tiling(self._h, block_threads, rows_per_block), "lbch_set_tiling")
+
+    def tiling(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbch_get_tiling(self._h, ctypes.byref(a), ctypes.byref(b)), "lbch_get_tiling")
+        return a.value, b.value

@@ -1,0 +1,60 @@
+"""Test helpers: the same workload handed to the HIP path (through the C-ABI binding)
+and to the oracle.  Only configuration is translated here; no method arithmetic."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import lbm
+from paper_2501_03759_amd import inputs
+
+REG_NAMES = {0: "none", 1: "linear", 2: "willmore"}
+QFORM_NAMES = {0: "derived", 1: "literal"}
+
+
+def gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def make_params(nx, ny, precision, sigma=0.01, width=None, eps_w=None, **kw):
+    """lbch.Params with kappa, beta from (sigma, D) via the library's eq 5 helper."""
+    from paper_2501_03759_amd import lbch
+    if width is None:
+        width = inputs.width_from_eps(eps_w) if eps_w is not None else 5.0
+    return lbch.default_params(nx=nx, ny=ny, precision=precision, sigma_width=(sigma, width), **kw)
+
+
+def oracle_params(p) -> lbm.Params:
+    """The same problem for the oracle (kappa, beta re-derived by the oracle's own eq 5)."""
+    return lbm.Params(nx=p.nx, ny=p.ny, kappa=p.kappa, beta=p.beta, mobility=p.mobility, alpha=p.alpha,
+                      aniso_m=p.aniso_m, theta0=p.aniso_theta0, reg=REG_NAMES[p.regularization],
+                      eps_reg=p.eps_reg, q_form=QFORM_NAMES[p.q_form], grad_floor=p.grad_floor,
+                      dx=p.dx, dt=p.dt, s_free=tuple(p.s[i] for i in range(9)))
+
+
+def oracle_phi(phi0, p, nsteps) -> np.ndarray:
+    return lbm.phi_of(lbm.run(phi0, oracle_params(p), nsteps))
+
+
+def sampled_oracle_phi(phi0: np.ndarray, p, nsteps: int, points) -> np.ndarray:
+    """phi after nsteps at the given (y, x) nodes of a large periodic grid, each from an
+    oracle run on a periodic window around the node.  A node's value after k steps depends
+    on the initial field within Chebyshev radius 4k + 2 (radius-3 stencils of phi plus the
+    pull, and the init stencil), so a half-width of 4k + 3 makes the window's own wrap
+    irrelevant at its centre."""
+    h = 4 * nsteps + 3
+    ny, nx = phi0.shape
+    out = []
+    for (y, x) in points:
+        rows = np.arange(y - h, y + h + 1) % ny
+        cols = np.arange(x - h, x + h + 1) % nx
+        win = phi0[np.ix_(rows, cols)]
+        op = oracle_params(p)
+        op.nx = op.ny = 2 * h + 1
+        out.append(lbm.phi_of(lbm.run(win, op, nsteps))[h, h])
+    return np.array(out)

@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, on seeded inputs.
+
+Tolerances: FP64 mode max|d phi| <= 1e-11; FP32 mode <= 1e-4 after 1000 steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2501_03759_amd import inputs
+from tests import common
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11
+FP32_TOL = 1e-4
+
+
+def lb():
+    from paper_2501_03759_amd import lbch
+    return lbch
+
+
+def c1_params(precision=0, **kw):
+    d = inputs.C1
+    return common.make_params(64, 64, precision, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
+                              aniso_m=4, eps_reg=d["eps_reg"], **kw)
+
+
+def run_gpu(p, phi0, nsteps, tiling=None):
+    L = lb()
+    with L.Sim(p) as s:
+        if tiling:
+            s.set_tiling(*tiling)
+        s.init(phi0)
+        s.step(nsteps)
+        return s.phi()
+
+
+@pytest.mark.parametrize("rates", ["unit", "distinct"])
+def test_c1_droplet_fp64_2000_steps(rates):
+    kw = {} if rates == "unit" else {"s": inputs.C1_RATES_DISTINCT}
+    p = c1_params(0, **kw)
+    phi0 = inputs.droplet(64, 64, 16.0, 2.0)
+    print(f"case c1 rates={rates}", flush=True)
+    got = run_gpu(p, phi0, 2000)
+    want = common.oracle_phi(phi0, p, 2000)
+    assert np.abs(got - want).max() <= FP64_TOL
+
+
+def test_c2_parameters_at_128_fp64():
+    d = inputs.C2
+    p = common.make_params(128, 128, 0, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
+                           eps_reg=d["eps_reg"])
+    phi0 = inputs.spinodal(128, 128, seed=11, amp=0.05)
+    got = run_gpu(p, phi0, 400)
+    want = common.oracle_phi(phi0, p, 400)
+    assert np.abs(got - want).max() <= FP64_TOL
+
+
+VARIANTS = [
+    dict(nx=67, ny=45, regularization=1, alpha=0.2),                      # linear reg, ragged
+    dict(nx=67, ny=45, regularization=0, alpha=0.05),                     # no reg
+    dict(nx=70, ny=33, q_form=1, alpha=0.1),                              # literal eq 15
+    dict(nx=61, ny=64, aniso_m=6, alpha=0.1),                             # 6-fold
+    dict(nx=64, ny=50, aniso_m=4, aniso_theta0=0.35, alpha=0.25),          # rotated
+    dict(nx=40, ny=40, dx=0.5, dt=0.25, alpha=0.3),                       # non-unit lattice units
+    dict(nx=5, ny=7, alpha=0.3),                                          # tiny grid
+    dict(nx=1, ny=9, alpha=0.3),
+    dict(nx=130, ny=3, alpha=0.3, s=inputs.C1_RATES_DISTINCT),
+    dict(nx=300, ny=20, alpha=0.3),                                       # several strips
+]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("var", VARIANTS, ids=[str(i) for i in range(len(VARIANTS))])
+def test_variants_against_oracle(var, precision):
+    var = dict(var)
+    nx, ny = var.pop("nx"), var.pop("ny")
+    p = common.make_params(nx, ny, precision, width=4.0, **var)
+    phi0 = inputs.spinodal(nx, ny, seed=nx * 31 + ny, amp=0.3, mean=0.1)
+    nsteps = 150
+    print(f"case variant {nx}x{ny} {var} precision={precision}", flush=True)
+    got = run_gpu(p, phi0, nsteps)
+    want = common.oracle_phi(phi0, p, nsteps)
+    tol = FP64_TOL if precision == 0 else 2e-5
+    assert np.abs(got - want).max() <= tol
+
+
+def test_fp32_c2_parameters_1000_steps_at_128():
+    d = inputs.C2
+    p = common.make_params(128, 128, 1, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
+                           eps_reg=d["eps_reg"])
+    phi0 = inputs.spinodal(128, 128, seed=3, amp=0.05)
+    got = run_gpu(p, phi0, 1000)
+    want = common.oracle_phi(phi0, p, 1000)
+    assert np.abs(got - want).max() <= FP32_TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tiling_is_bitwise_invariant(precision):
+    p = common.make_params(300, 130, precision, width=4.0, alpha=0.3, s=inputs.C1_RATES_DISTINCT)
+    phi0 = inputs.spinodal(300, 130, seed=5, amp=0.3)
+    ref = None
+    for tiling in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 130), (512, 33), (128, 1000)]:
+        got = run_gpu(p, phi0, 60, tiling)
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref), tiling
+
+
+def test_reductions_against_oracle():
+    from oracle import lbm
+    p = c1_params(0, alpha=0.2)
+    phi0 = inputs.droplet(64, 64, 16.0, 2.0)
+    L = lb()
+    with L.Sim(p) as s:
+        s.init(phi0)
+        s.step(100)
+        phi, mass, lo, hi = s.moments()
+        E, terms = s.free_energy()
+    op = common.oracle_params(p)
+    f = lbm.run(phi0, op, 100)
+    ph = lbm.phi_of(f)
+    t = lbm.free_energy_terms(ph, op)
+    assert abs(mass - lbm.mass(f, op)) <= 1e-10
+    assert abs(lo - ph.min()) <= FP64_TOL and abs(hi - ph.max()) <= FP64_TOL
+    for got, key in zip(terms, ["grad", "bulk", "reg", "total"]):
+        assert abs(got - t[key]) <= 1e-11 * max(1.0, abs(t[key])), key
+    assert abs(E - t["total"]) <= 1e-11 * abs(t["total"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_resume_is_bitwise(precision):
+    p = common.make_params(96, 80, precision, width=4.0, alpha=0.3)
+    phi0 = inputs.spinodal(96, 80, seed=9, amp=0.2)
+    L = lb()
+    with L.Sim(p) as a:
+        a.init(phi0)
+        a.step(50)
+        blob = a.save_state()
+        a.step(50)
+        want = a.phi()
+        assert a.nstep == 100
+    with L.Sim(p) as b:
+        b.load_state(blob)
+        assert b.nstep == 50
+        b.step(50)
+        got = b.phi()
+    assert np.array_equal(got, want)
+
+
+def test_saved_state_is_oracle_populations():
+    from oracle import lbm
+    p = c1_params(0, alpha=0.3)
+    phi0 = inputs.droplet(64, 64, 16.0, 2.0)
+    L = lb()
+    with L.Sim(p) as s:
+        s.init(phi0)
+        s.step(20)
+        blob = s.save_state()
+    body = np.frombuffer(blob[len(blob) - 9 * 64 * 64 * 8:], dtype=np.float64).reshape(9, 64, 64)
+    want = lbm.run(phi0, common.oracle_params(p), 20)
+    assert np.abs(body - want).max() <= FP64_TOL
+
+
+def test_state_errors():
+    L = lb()
+    p = c1_params(0)
+    with L.Sim(p) as s:
+        with pytest.raises(L.LbchError) as ei:
+            s.step(1)
+        assert ei.value.status == L.E_STATE
+        bad = inputs.droplet(64, 64, 16.0, 2.0)
+        bad[3, 4] = np.nan
+        with pytest.raises(L.LbchError) as ei:
+            s.init(bad)
+        assert ei.value.status == L.E_INVALID
+        with pytest.raises(L.LbchError) as ei:
+            s.init(np.zeros(10))
+        assert ei.value.status == L.E_INVALID
+        s.init(inputs.droplet(64, 64, 16.0, 2.0))
+        with pytest.raises(L.LbchError):
+            s.step(-1)
+    q = c1_params(0)
+    q.nx = 32
+    with L.Sim(q) as other, L.Sim(p) as s:
+        s.init(inputs.droplet(64, 64, 16.0, 2.0))
+        blob = s.save_state()
+        with pytest.raises(L.LbchError) as ei:
+            other.load_state(blob)
+        assert ei.value.status == L.E_INVALID
+
+
+def test_literal_reading_reports_nonfinite():
+    L = lb()
+    p = c1_params(0)
+    p.kappa, p.beta = 4.0, 0.25
+    with L.Sim(p) as s:
+        s.init(inputs.droplet(64, 64, 16.0, 2.0))
+        s.step(60)
+        _, _, _, _ = s.moments(want_phi=False, check=False)
+        with pytest.raises(L.LbchError) as ei:
+            s.moments(want_phi=False)
+        assert ei.value.status == L.E_NONFINITE
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_init_device_and_phi_device(dtype):
+    import torch
+    L = lb()
+    p = c1_params(0, alpha=0.3)
+    phi0 = inputs.spinodal(64, 64, seed=2, amp=0.4)
+    if dtype == "float32":
+        phi0 = phi0.astype(np.float32).astype(np.float64)
+    t = torch.tensor(phi0, dtype=getattr(torch, dtype), device="cuda")
+    with L.Sim(p) as a, L.Sim(p) as b:
+        a.init(phi0)
+        torch.cuda.synchronize()
+        b.init_device(t.data_ptr(), L.FP64 if dtype == "float64" else L.FP32, t.numel())
+        a.step(10)
+        b.step(10)
+        pa, pb = a.phi(), b.phi()
+        assert np.array_equal(pa, pb)
+        out = torch.empty((64, 64), dtype=torch.float64, device="cuda")
+        b.phi_device(out.data_ptr(), L.FP64)
+        b.synchronize()
+        assert np.array_equal(out.cpu().numpy(), pb)
+
+
+def test_init_device_nonfinite_surfaces_at_moments():
+    import torch
+    L = lb()
+    p = c1_params(0)
+    t = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    t[5, 5] = float("inf")
+    with L.Sim(p) as s:
+        s.init_device(t.data_ptr(), L.FP64, t.numel())
+        with pytest.raises(L.LbchError) as ei:
+            s.moments(want_phi=False)
+        assert ei.value.status == L.E_NONFINITE
+
+
+def test_fp32_vs_fp64_c2_full_size_1000_steps():
+    # C2 size (1024^2): FP32 production mode against the FP64 mode after 1000 steps.
+    d = inputs.C2
+    phi0 = inputs.spinodal(1024, 1024, seed=d["seed"], amp=d["amp"])
+    out = {}
+    for prec in (0, 1):
+        p = common.make_params(1024, 1024, prec, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
+                               eps_reg=d["eps_reg"])
+        out[prec] = run_gpu(p, phi0, 1000)
+    assert np.abs(out[1] - out[0]).max() <= FP32_TOL
+
+
+@pytest.mark.parametrize("n,precision,seed", [(1024, 0, 0), (1024, 1, 0), (8192, 1, 5)])
+def test_full_size_sampled_against_oracle(n, precision, seed):
+    # Full-size grids in the default launch shape: sampled nodes against oracle windows.
+    d = inputs.C5 if n == 8192 else inputs.C2
+    p = common.make_params(n, n, precision, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
+                           eps_reg=d["eps_reg"])
+    phi0 = inputs.spinodal(n, n, seed=seed, amp=d["amp"])
+    k = 3
+    print(f"case full-size n={n} precision={precision}", flush=True)
+    got = run_gpu(p, phi0, k)
+    rng = np.random.default_rng(77)
+    pts = [(int(y), int(x)) for y, x in rng.integers(0, n, size=(24, 2))]
+    pts += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (n // 2, 249), (n // 2, 250), (131, 500)]
+    want = common.sampled_oracle_phi(phi0, p, k, pts)
+    gv = np.array([got[y, x] for (y, x) in pts])
+    tol = FP64_TOL if precision == 0 else 2e-6
+    assert np.abs(gv - want).max() <= tol
+
+
+def test_full_size_mass_conservation_fp32():
+    d = inputs.C5
+    n = 8192
+    p = common.make_params(n, n, 1, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
+                           eps_reg=d["eps_reg"])
+    phi0 = inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"])
+    L = lb()
+    with L.Sim(p) as s:
+        s.init(phi0)
+        _, m0, _, _ = s.moments(want_phi=False)
+        s.step(100)
+        _, m1, lo, hi = s.moments(want_phi=False)
+    scale = np.abs(phi0).sum()
+    assert abs(m1 - m0) / scale <= 1e-6
+    assert -1.5 < lo < hi < 1.5
