@@ -14,7 +14,6 @@ written) and the oracle's CPU throughput on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,19 +25,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_fused_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2501_03759_amd", "csrc", "lbch_kernels.hip")
-
-
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
 def measured_traffic(n_nodes: int, precision: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
     the current kernel source at this size; else None."""
+    from paper_2501_03759_amd.profiling import kernel_hash
+    side = int(round(n_nodes ** 0.5))
+    path = os.path.join(ROOT, "profiles", f"step_fused_spinodal{side}_{precision}.json")
     try:
-        rec = json.load(open(PROFILE_TRAFFIC))
+        rec = json.load(open(path))
     except Exception:
         return None
     if rec.get("kernel_sha256_16") != kernel_hash() or rec.get("nodes") != n_nodes or rec.get("precision") != precision:
@@ -72,10 +68,30 @@ def cpu_baseline(seconds_target: float = 15.0):
             "sample": f"{steps} steps of a {n}x{n} window of the workload (FP64 NumPy oracle, 1 thread)"}
 
 
+def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=5):
+    """Practical HBM copy bandwidth (read + write bytes / time) of the library's plain copy kernel."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    lbch.diag_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lbch.diag_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    ok = bool(torch.equal(src, dst))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "bytes_per_launch": 2 * nbytes, "ms": round(ms, 4),
+            "verified": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=8192, help="grid side (default: the 8192^2 workload)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -100,6 +116,7 @@ def main():
                             mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    copy = copy_ceiling(torch, lbch, stream)
     sim = lbch.Sim(p, stream)
     if args.tiling:
         bt, rows = (int(v) for v in args.tiling.split(","))
@@ -148,6 +165,7 @@ def main():
                    "mobility": d["mobility"], "tiling": list(tiling)},
         "roofline": roofline,
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
+        "hbm_copy": copy,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -208,11 +208,25 @@ lbch_status lbch_load_state(lbch_sim* sim, const void* src, int32_t src_is_devic
 /* Launch shape of the fused step kernel. -------------------------------------- */
 
 /* block_threads in {64, 128, 256, 512}: each workgroup owns a strip of
- * block_threads - 6 columns; rows_per_block >= 1 rows of that strip are
+ * block_threads - 8 columns; rows_per_block >= 1 rows of that strip are
  * swept per workgroup.  The result is bitwise independent of the choice.
  * 0 for either argument restores the built-in default for the grid. */
 lbch_status lbch_set_tiling(lbch_sim* sim, int32_t block_threads, int32_t rows_per_block);
 lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t* rows_per_block);
+
+/* Times the step kernel over the launch shapes block_threads in {64, 128,
+ * 256, 512} x rows_per_block in {8, ..., 256} (steps_per_trial launches each,
+ * reading the current state and writing the idle buffer, so the state and
+ * the step counter are unchanged), keeps the fastest and returns it.
+ * Synchronises.  Before init -> LBCH_E_STATE. */
+lbch_status lbch_autotune(lbch_sim* sim, int32_t steps_per_trial, int32_t* block_threads,
+                          int32_t* rows_per_block, double* ms_per_step);
+
+/* How the step kernel reads a row of populations: 0 = automatic (FP32 grids
+ * with nx % 4 == 0 fetch aligned 16-byte chunks into LDS and read the pulled
+ * values from there; otherwise one load per population and lane), 1 = always
+ * the per-lane loads.  Results are bitwise identical either way. */
+lbch_status lbch_set_row_loader(lbch_sim* sim, int32_t mode);
 
 #ifdef __cplusplus
 }

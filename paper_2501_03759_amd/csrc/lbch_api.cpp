@@ -1,6 +1,7 @@
 // C-ABI layer of liblbch: parameter handling, buffers, launches, reductions,
 // checkpointing.  See include/lbch.h for the contract of every entry point.
 #include "../../include/lbch.h"
+#include "../../include/lbch_diag.h"
 #include "lbch_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -67,7 +68,7 @@ struct lbch_sim {
     StepCoef<double> cd{};
     StepCoef<float> cf{};
     RedCoef rc{};
-    int user_nt = 0, user_hc = 0;
+    int user_nt = 0, user_hc = 0, user_loader = 0;
 };
 
 // ------------------------------------------------------------ host helpers
@@ -187,10 +188,16 @@ void fill_coef(const lbch_params* p, StepCoef<T>& c) {
     c.cf4 = (T)(dt * (1.0 - s[4] / 2.0) * (cc / 3.0) / nrm[4]);
     c.cf5 = (T)(dt * (1.0 - s[5] / 2.0) * (cc / 3.0) / nrm[5]);
     c.cf6 = (T)(dt * (1.0 - s[6] / 2.0) * (cc / 3.0) / nrm[6]);
+    c.u3 = (T)((1.0 - s[3]) / nrm[3]);
+    c.u5 = (T)((1.0 - s[5]) / nrm[5]);
+    c.v4 = (T)(dt * 0.5 * (cc / 3.0) / nrm[4]);
+    c.v6 = (T)(dt * 0.5 * (cc / 3.0) / nrm[6]);
     c.m = p->aniso_m;
     c.reg = p->regularization;
     c.qform = p->q_form;
-    c.pad_ = 0;
+    c.unit = 1;
+    for (int k : {1, 2, 4, 6, 7, 8})
+        if (s[k] != 1.0) c.unit = 0;
 }
 
 void fill_red(const lbch_params* p, RedCoef& r) {
@@ -218,7 +225,7 @@ Tiling make_tiling(int nx, int ny, int nt, int hc) {
         const int cand[4] = {64, 128, 256, 512};
         long long best = -1;
         for (int k = 0; k < 4; ++k) {
-            const int W = cand[k] - 6;
+            const int W = cand[k] - 8;
             const long long cost = (long long)((nx + W - 1) / W) * cand[k];
             if (best < 0 || cost <= best) {
                 best = cost;
@@ -228,10 +235,12 @@ Tiling make_tiling(int nx, int ny, int nt, int hc) {
     }
     Tiling t{};
     t.nt = nt;
-    t.W = nt - 6;
+    t.W = nt - 8;          // multiple of 8: strips start on 32-byte boundaries
     t.strips = (nx + t.W - 1) / t.W;
     if (hc == 0) {
-        long long want = (long long)t.strips * ny / 2048;
+        // short sweeps measured fastest on 8192^2 (more resident workgroups;
+        // the extra halo rows mostly hit L2): about 8 tiles per CU, >= 16 rows
+        long long want = (long long)t.strips * ny / 8192;
         hc = (int)(want < 16 ? 16 : (want > 256 ? 256 : want));
     }
     t.hc = hc < ny ? hc : ny;
@@ -239,6 +248,7 @@ Tiling make_tiling(int nx, int ny, int nt, int hc) {
     t.ntiles = t.strips * t.chunks;
     t.per_xcd = (t.ntiles + 7) / 8;
     t.nblocks = 8 * t.per_xcd;
+    t.staged = 1;
     return t;
 }
 
@@ -521,6 +531,16 @@ extern "C" lbch_status lbch_set_tiling(lbch_sim* s, int32_t block_threads, int32
     s->user_nt = block_threads;
     s->user_hc = rows_per_block;
     s->t = make_tiling(s->g.nx, s->g.ny, block_threads, rows_per_block);
+    s->t.staged = s->user_loader == 0;
+    return ok();
+}
+
+extern "C" lbch_status lbch_set_row_loader(lbch_sim* s, int32_t mode) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (mode != 0 && mode != 1) return fail(LBCH_E_INVALID, "row loader mode %d not in {0, 1}", mode);
+    s->user_loader = mode;
+    s->t.staged = mode == 0;
     return ok();
 }
 
@@ -529,5 +549,66 @@ extern "C" lbch_status lbch_get_tiling(const lbch_sim* s, int32_t* block_threads
     if (st != LBCH_OK) return st;
     if (block_threads) *block_threads = s->t.nt;
     if (rows_per_block) *rows_per_block = s->t.hc;
+    return ok();
+}
+
+// ------------------------------------------------------------ diagnostics
+extern "C" lbch_status lbch_diag_copy(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+    if (!src || !dst) return fail(LBCH_E_INVALID, "NULL pointer");
+    if (bytes <= 0 || bytes % 16 != 0) return fail(LBCH_E_INVALID, "bytes = %lld must be a positive multiple of 16",
+                                                   (long long)bytes);
+    if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return fail(LBCH_E_INVALID, "pointers must be 16-byte aligned");
+    HIP_TRY(launch_copy16(src, dst, bytes / 16, (hipStream_t)hip_stream));
+    return ok();
+}
+
+// ------------------------------------------------------------- autotuner
+extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32_t* block_threads,
+                                     int32_t* rows_per_block, double* ms_per_step) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    if (steps_per_trial < 1) return fail(LBCH_E_INVALID, "steps_per_trial %d < 1", steps_per_trial);
+    // Trials read the current state and write the idle buffer, so the state is untouched.
+    const int nts[4] = {64, 128, 256, 512};
+    const int hcs[6] = {8, 16, 32, 64, 128, 256};
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    float best = -1.0f;
+    Tiling best_t = s->t;
+    const Tiling saved = s->t;
+    for (int nt : nts) {
+        if (nt > 128 && s->g.nx < nt / 2) continue;          // mostly idle lanes
+        for (int hc : hcs) {
+            if (hc > s->g.ny && hc != hcs[0]) continue;
+            Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc);
+            t.staged = saved.staged;
+            hipError_t e = launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
+            if (e == hipSuccess) e = hipEventRecord(a, s->stream);
+            for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k)
+                e = launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
+            if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                return fail(LBCH_E_DEVICE, "autotune trial failed: %s", hipGetErrorString(e));
+            }
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->t = best_t;
+    s->user_nt = best_t.nt;
+    s->user_hc = best_t.hc;
+    if (block_threads) *block_threads = best_t.nt;
+    if (rows_per_block) *rows_per_block = best_t.hc;
+    if (ms_per_step) *ms_per_step = best / steps_per_trial;
     return ok();
 }

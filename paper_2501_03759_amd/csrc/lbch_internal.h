@@ -14,11 +14,12 @@ struct Grid {
     long long plane;      // elements between consecutive population planes
 };
 
-// Decomposition of the fused step: strips of W = NT - 6 columns, chunks of
+// Decomposition of the fused step: strips of W = NT - 8 columns, chunks of
 // `hc` rows; tiles are strip-fastest; blocks are dealt to the 8 XCDs in
 // contiguous tile ranges of `per_xcd`.
 struct Tiling {
     int nt, W, strips, hc, chunks, ntiles, per_xcd, nblocks;
+    int staged;           // FP32 row loader through LDS (used when nx % 4 == 0)
 };
 
 // Per-step constants in the working precision T (lattice units folded in).
@@ -31,7 +32,9 @@ struct StepCoef {
     T alpha_m;            // alpha * m
     T cs1, cs2, cs3, cs4, cs5, cs6, cs7, cs8;   // s_k / |row k of M|^2
     T cf3, cf4, cf5, cf6;                       // dt (1 - s_k/2) (c/3) / |row k|^2
-    int m, reg, qform, pad_;
+    T u3, u5, v4, v6;     // unit free rates: (1 - s_j)/6 and dt (c/3) / (2 * 12)
+    int m, reg, qform;
+    int unit;             // every free rate (k != 0, 3, 5) equals 1
 };
 
 // Reduction constants (always float64).
@@ -59,6 +62,7 @@ hipError_t launch_finalize(const double* partials, int nparts, int nvals, const 
 hipError_t launch_gather(int precision, const void* fin, const Grid& g, void* dense, hipStream_t s);
 hipError_t launch_scatter(int precision, const void* dense, const Grid& g, void* fout, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
 constexpr int kRedThreads = 256;

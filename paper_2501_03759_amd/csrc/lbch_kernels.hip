@@ -103,6 +103,34 @@ __device__ __forceinline__ void collide(const T (&f)[9], T mua, T gx, T gy, cons
     o[8] = f[8] - (dg + p34 - p56 - d8);
 }
 
+// Collision when every free rate (k != 0, 3, 5) is 1: those moments relax to
+// m_eq + dt F/2, so f* = M^-1 m* needs only phi, j_x = m_3, j_y = m_5 of f:
+// m* = (phi, 2mu_a - 4phi, 4phi - 3mu_a, (1-s_j) j_x - dt(1-s_j/2)(c/3)gx,
+//       dt(c/3)gx/2, (1-s_j) j_y - dt(1-s_j/2)(c/3)gy, dt(c/3)gy/2, 0, 0).
+template <typename T>
+__device__ __forceinline__ void collide_unit(T phi, T jx, T jy, T mua, T gx, T gy, const StepCoef<T>& c,
+                                             T (&o)[9]) {
+    const T e0 = phi * T(1.0 / 9.0);
+    const T e1 = (T(2) * mua - T(4) * phi) * T(1.0 / 36.0);
+    const T e2 = (T(4) * phi - T(3) * mua) * T(1.0 / 36.0);
+    const T e3 = c.u3 * jx - c.cf3 * gx;
+    const T e4 = c.v4 * gx;
+    const T e5 = c.u5 * jy - c.cf5 * gy;
+    const T e6 = c.v6 * gy;
+    const T ax = e0 - e1 - T(2) * e2;        // axis directions
+    const T dg = e0 + T(2) * e1 + e2;        // diagonal directions
+    const T p34 = e3 + e4, p56 = e5 + e6;
+    o[0] = e0 + T(4) * (e2 - e1);
+    o[1] = ax + e3 - T(2) * e4;
+    o[2] = ax + e5 - T(2) * e6;
+    o[3] = ax - e3 + T(2) * e4;
+    o[4] = ax - e5 + T(2) * e6;
+    o[5] = dg + p34 + p56;
+    o[6] = dg - p34 + p56;
+    o[7] = dg - p34 - p56;
+    o[8] = dg + p34 - p56;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -114,87 +142,220 @@ __device__ __forceinline__ void collide(const T (&f)[9], T mua, T gx, T gy, cons
 //   B(row r-1) : grad phi, lap phi (eq 26), gamma, Q (eq 15), w (eq 9), mu_alpha (eq 16)
 //   C(row r-2) : div Q, lap w -> mu_beta (eqs 13, 16)
 //   D(row r-3) : grad mu_beta, source (eq 19), collision (eq 17), store
-// Stage outputs live in 3-row LDS rings; the populations of a row stay in
-// registers from A until D three iterations later.  The next row's loads
-// are issued before the stencil stages so their latency overlaps compute.
+// Stage outputs live in 3-row LDS rings; what D needs of a row's populations
+// stays in registers from A until D three iterations later (all nine
+// populations in general; only phi, j_x, j_y when every free relaxation
+// rate is 1, because those moments then relax fully to m_eq + F/2 and the
+// collision needs no other moment of f).  Rows are loaded PF iterations
+// ahead, so their latency overlaps the stencil stages of the current row.
+// The loop is unrolled by U so that every register ring index is static.
 // ---------------------------------------------------------------------------
+#ifndef LBCH_PF
+#define LBCH_PF 1
+#endif
+
+// Native 16-byte vectors (not HIP_vector_type: arrays of those are not split
+// into registers and end up in scratch memory).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = f32x4; };
+template <> struct Vec16<double> { using type = f64x2; };
+
+// Row loader.  Direct form: each lane pulls its nine populations with one
+// 4- or 8-byte load per plane (shifted by the pull, so unaligned to the row).
+// Staged form: the lanes of the workgroup fetch the nine plane-rows the strip
+// needs as aligned 16-byte chunks (full cache lines, one wide load per chunk),
+// park them in LDS and each lane then reads its shifted values from there.
+template <typename T, int NT, bool STAGED>
+struct RowLoader;
+
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* __restrict__ fout,
-                                                 const Grid g, const Tiling tl, const StepCoef<T> c) {
-    __shared__ T s_phi[3][NT];
-    __shared__ T s_qx[3][NT];
-    __shared__ T s_qy[3][NT];
-    __shared__ T s_w[3][NT];
-    __shared__ T s_mb[3][NT];
-
-    const int bid = blockIdx.x;
-    const int tile = (bid & 7) * tl.per_xcd + (bid >> 3);
-    if (tile >= tl.ntiles) return;
-    const int strip = tile % tl.strips;
-    const int chunk = tile / tl.strips;
-    const int nx = g.nx, ny = g.ny, pitch = g.pitch;
-    const int x0 = strip * tl.W;
-    const int wlen = min(tl.W, nx - x0);
-    const int y0 = chunk * tl.hc;
-    const int niter = min(tl.hc, ny - y0) + 6;
-    const int t = threadIdx.x;
-
-    int xc = (x0 - 3 + t) % nx;
-    if (xc < 0) xc += nx;
-    const int cm = (xc == 0) ? nx - 1 : xc - 1;
-    const int cp = (xc == nx - 1) ? 0 : xc + 1;
-
-    const T* __restrict__ P0 = fin;
-    const T* __restrict__ P1 = fin + g.plane;
-    const T* __restrict__ P2 = fin + 2 * g.plane;
-    const T* __restrict__ P3 = fin + 3 * g.plane;
-    const T* __restrict__ P4 = fin + 4 * g.plane;
-    const T* __restrict__ P5 = fin + 5 * g.plane;
-    const T* __restrict__ P6 = fin + 6 * g.plane;
-    const T* __restrict__ P7 = fin + 7 * g.plane;
-    const T* __restrict__ P8 = fin + 8 * g.plane;
-
-    int rA = (y0 - 3) % ny;   // row of the next stage-A load (wrapped)
-    if (rA < 0) rA += ny;
-
-    T fr[5][9];               // register ring of pulled populations
-    T mua[5];                 // mu_alpha ring (B -> D, two iterations)
-    T tloc[5];                // local part of mu_beta (B -> C, one iteration)
-
-    auto load_row = [&](int r, T (&f)[9]) {
+struct RowLoader<T, NT, false> {
+    using Buf = T[9];
+    const T* P[9];
+    int xc, cm, cp, nx, ny, pitch;
+    __device__ __forceinline__ void setup(const T* fin, const Grid& g, int x0, T* /*s_f*/) {
+        nx = g.nx;
+        ny = g.ny;
+        pitch = g.pitch;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) P[i] = fin + i * g.plane;
+        xc = (x0 - 3 + (int)threadIdx.x) % nx;
+        if (xc < 0) xc += nx;
+        cm = (xc == 0) ? nx - 1 : xc - 1;
+        cp = (xc == nx - 1) ? 0 : xc + 1;
+    }
+    __device__ __forceinline__ void issue(int r, Buf& f) const {
         const int rm = (r == 0) ? ny - 1 : r - 1;
         const int rp = (r == ny - 1) ? 0 : r + 1;
         const int o0 = r * pitch, om = rm * pitch, op = rp * pitch;
-        f[0] = P0[o0 + xc];
-        f[1] = P1[o0 + cm];
-        f[2] = P2[om + xc];
-        f[3] = P3[o0 + cp];
-        f[4] = P4[op + xc];
-        f[5] = P5[om + cm];
-        f[6] = P6[om + cp];
-        f[7] = P7[op + cp];
-        f[8] = P8[op + cm];
-    };
-
-    load_row(rA, fr[0]);
-
-    for (int jb = 0; jb < niter; jb += 5) {
+        f[0] = P[0][o0 + xc];
+        f[1] = P[1][o0 + cm];
+        f[2] = P[2][om + xc];
+        f[3] = P[3][o0 + cp];
+        f[4] = P[4][op + xc];
+        f[5] = P[5][om + cm];
+        f[6] = P[6][om + cp];
+        f[7] = P[7][op + cp];
+        f[8] = P[8][op + cm];
+    }
+    // no LDS staging: the lane's values are the loaded ones
+    __device__ __forceinline__ void park(const Buf&, T*) const {}
+    __device__ __forceinline__ void fetch(const Buf& b, const T*, T (&f)[9]) const {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int i = 0; i < 9; ++i) f[i] = b[i];
+    }
+    static constexpr bool kNeedsBarrier = false;
+};
+
+template <typename T, int NT>
+struct RowLoader<T, NT, true> {
+    using V = typename Vec16<T>::type;
+    static constexpr int VEC = 16 / sizeof(T);
+    static constexpr int SPAN = NT + 4;             // staged columns x0-4 .. x0+NT-1
+    static constexpr int CPR = SPAN / VEC;          // chunks per plane-row
+    static constexpr int NCH = 9 * CPR;
+    static constexpr int M = (NCH + NT - 1) / NT;   // chunks per lane
+    using Buf = V[M];
+    const T* fin;
+    int off[M];            // element offset of the chunk: plane + first column (wrapped)
+    int dy[M];             // row offset of the plane's pull: -1, 0, +1
+    unsigned live;         // bit m: chunk m exists
+    int nx, ny, pitch;
+    __device__ __forceinline__ void setup(const T* f, const Grid& g, int x0, T* /*s_f*/) {
+        fin = f;
+        nx = g.nx;
+        ny = g.ny;
+        pitch = g.pitch;
+        live = 0u;
+        // requires nx % VEC == 0 (checked by the launcher): a chunk that starts
+        // on a VEC boundary then never straddles the periodic seam, so even the
+        // wrapped chunks of the first and last strips are single aligned loads
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int ch = (int)threadIdx.x + m * NT;
+            const int i = ch / CPR;
+            const int q = ch - i * CPR;
+            const int ii = i < 9 ? i : 0;
+            // c_iy of eq 20a: the pull of plane i reads row r - c_iy
+            dy[m] = (ii == 2 || ii == 5 || ii == 6) ? -1 : ((ii == 4 || ii == 7 || ii == 8) ? 1 : 0);
+            int cw = (x0 - 4 + q * VEC) % nx;
+            if (cw < 0) cw += nx;
+            off[m] = ii * (int)g.plane + cw;
+            if (ch < NCH) live |= 1u << m;
+        }
+    }
+    __device__ __forceinline__ void issue(int r, Buf& b) const {
+        const int rm = (r == 0) ? ny - 1 : r - 1;
+        const int rp = (r == ny - 1) ? 0 : r + 1;
+        const int o0 = r * pitch, om = rm * pitch, op = rp * pitch;
+        // unconditional (lanes past the last chunk re-read a valid chunk of
+        // plane 0 and discard it): no branch around the loads, so they stay
+        // in flight until park()
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int o = off[m] + (dy[m] < 0 ? om : (dy[m] > 0 ? op : o0));
+            b[m] = *reinterpret_cast<const V*>(fin + o);
+        }
+    }
+    __device__ __forceinline__ void park(const Buf& b, T* s_f) const {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (live & (1u << m)) {
+                const int ch = (int)threadIdx.x + m * NT;
+                *reinterpret_cast<V*>(s_f + ch * VEC) = b[m];
+            }
+        }
+    }
+    __device__ __forceinline__ void fetch(const Buf&, const T* s_f, T (&f)[9]) const {
+        const int t = threadIdx.x;
+        // staged index of the lane's column is t + 1; the pull of direction i reads column x - c_ix
+        f[0] = s_f[0 * SPAN + t + 1];
+        f[1] = s_f[1 * SPAN + t];
+        f[2] = s_f[2 * SPAN + t + 1];
+        f[3] = s_f[3 * SPAN + t + 2];
+        f[4] = s_f[4 * SPAN + t + 1];
+        f[5] = s_f[5 * SPAN + t];
+        f[6] = s_f[6 * SPAN + t + 2];
+        f[7] = s_f[7 * SPAN + t + 2];
+        f[8] = s_f[8 * SPAN + t];
+    }
+    static constexpr bool kNeedsBarrier = true;
+};
+
+template <typename T, int NT, bool STAGED>
+struct StageLds {
+    static constexpr int kF = STAGED ? 9 * (NT + 4) : 1;
+};
+
+template <typename T, int NT, bool UNIT, bool STAGED>
+__device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __restrict__ fout, const Grid& g,
+                                            const int x0, const int wlen, const int y0, const int hlen,
+                                            const StepCoef<T>& c, T (*s_phi)[NT], T (*s_qx)[NT], T (*s_qy)[NT],
+                                            T (*s_w)[NT], T (*s_mb)[NT], T* s_f) {
+    constexpr int U = 4;
+    constexpr int PF = LBCH_PF;
+    static_assert(PF >= 1 && PF <= 2, "prefetch distance");
+    using Loader = RowLoader<T, NT, STAGED>;
+    const int nx = g.nx, ny = g.ny, pitch = g.pitch;
+    const int niter = hlen + 6;
+    const int t = threadIdx.x;
+
+    Loader ld;
+    ld.setup(fin, g, x0, s_f);
+    int xc = (x0 - 3 + t) % nx;      // the lane's column (wrapped)
+    if (xc < 0) xc += nx;
+
+    int rA = (y0 - 3) % ny;          // row of the next load (wrapped)
+    if (rA < 0) rA += ny;
+
+    typename Loader::Buf buf[U];     // rows in flight
+    T pop[U][9];                     // general path: pulled populations kept until D
+    T red[U][3];                     // unit-rate path: phi, j_x, j_y kept until D
+    T mua[U];                        // mu_alpha (B -> D, two iterations)
+    T tloc[U];                       // local part of mu_beta (B -> C, one iteration)
+
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        if (q < niter) {
+            ld.issue(rA, buf[q]);
+            rA = (rA == ny - 1) ? 0 : rA + 1;
+        }
+    }
+
+    for (int jb = 0; jb < niter; jb += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
             const int j = jb + k;
             if (j < niter) {
                 const int sN = j % 3, sC = (j + 2) % 3, sS = (j + 1) % 3;
-                // ---- A: phi of row r (same summation order as collide()) ----
+                // ---- A: populations of row r, phi (same summation order as the collision) ----
+                if (Loader::kNeedsBarrier) {
+                    ld.park(buf[k], s_f);
+                    lds_barrier();
+                }
                 {
-                    const T(&f)[9] = fr[k];
+                    T f[9];
+                    ld.fetch(buf[k], s_f, f);
                     const T a = (f[1] + f[2]) + (f[3] + f[4]);
                     const T b = (f[5] + f[6]) + (f[7] + f[8]);
-                    s_phi[sN][t] = f[0] + a + b;
+                    const T phi = f[0] + a + b;
+                    s_phi[sN][t] = phi;
+                    if (UNIT) {
+                        red[k][0] = phi;
+                        red[k][1] = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));   // j_x = m_3
+                        red[k][2] = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));   // j_y = m_5
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) pop[k][i] = f[i];
+                    }
                 }
-                if (j + 1 < niter) {
-                    rA = (rA == ny - 1) ? 0 : rA + 1;
-                    load_row(rA, fr[(k + 1) % 5]);
-                }
+                // unconditional: past the last row of the sweep this fetches a
+                // (wrapped, valid) row that is never used; a branch here would
+                // force the loads to complete before the join
+                ld.issue(rA, buf[(k + PF) % U]);
+                rA = (rA == ny - 1) ? 0 : rA + 1;
                 lds_barrier();
                 // ---- B: row r-1 ----
                 if (j >= 2 && t >= 1 && t < NT - 1) {
@@ -241,7 +402,7 @@ __global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* _
                         c.g12 * ((s_qx[sN][t + 1] - s_qx[sS][t - 1]) + (s_qx[sS][t + 1] - s_qx[sN][t - 1])) +
                         c.g3 * (s_qy[sN][t] - s_qy[sS][t]) +
                         c.g12 * ((s_qy[sN][t + 1] - s_qy[sS][t - 1]) + (s_qy[sN][t - 1] - s_qy[sS][t + 1]));
-                    T mb = tloc[(k + 4) % 5] - divq;
+                    T mb = tloc[(k + U - 1) % U] - divq;
                     if (c.reg != REG_NONE) {
                         const T lw = c.l23 * ((s_w[sC][t + 1] + s_w[sC][t - 1]) + (s_w[sN][t] + s_w[sS][t])) +
                                      c.l16 * ((s_w[sN][t + 1] + s_w[sS][t - 1]) + (s_w[sN][t - 1] + s_w[sS][t + 1])) -
@@ -257,17 +418,42 @@ __global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* _
                                  c.g12 * ((s_mb[sN][t + 1] - s_mb[sS][t - 1]) + (s_mb[sS][t + 1] - s_mb[sN][t - 1]));
                     const T gy = c.g3 * (s_mb[sN][t] - s_mb[sS][t]) +
                                  c.g12 * ((s_mb[sN][t + 1] - s_mb[sS][t - 1]) + (s_mb[sN][t - 1] - s_mb[sS][t + 1]));
+                    const T mu_a = mua[(k + U - 2) % U];
                     T o[9];
-                    collide<T>(fr[(k + 2) % 5], mua[(k + 3) % 5], gx, gy, c, o);
+                    if (UNIT) {
+                        const T(&rr)[3] = red[(k + U - 3) % U];
+                        collide_unit<T>(rr[0], rr[1], rr[2], mu_a, gx, gy, c, o);
+                    } else {
+                        collide<T>(pop[(k + U - 3) % U], mu_a, gx, gy, c, o);
+                    }
                     const int rd = y0 - 6 + j;
-                    const long long base = (long long)rd * pitch + xc;
-                    T* __restrict__ q = fout + base;
+                    T* __restrict__ q = fout + ((long long)rd * pitch + xc);
 #pragma unroll
                     for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i];
                 }
             }
         }
     }
+}
+
+template <typename T, int NT, bool UNIT, bool STAGED>
+__global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* __restrict__ fout,
+                                                 const Grid g, const Tiling tl, const StepCoef<T> c) {
+    __shared__ T s_phi[3][NT];
+    __shared__ T s_qx[3][NT];
+    __shared__ T s_qy[3][NT];
+    __shared__ T s_w[3][NT];
+    __shared__ T s_mb[3][NT];
+    __shared__ __align__(16) T s_f[StageLds<T, NT, STAGED>::kF];
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * tl.per_xcd + (bid >> 3);
+    if (tile >= tl.ntiles) return;
+    const int strip = tile % tl.strips;
+    const int chunk = tile / tl.strips;
+    const int x0 = strip * tl.W;
+    const int y0 = chunk * tl.hc;
+    sweep_strip<T, NT, UNIT, STAGED>(fin, fout, g, x0, min(tl.W, g.nx - x0), y0, min(tl.hc, g.ny - y0), c, s_phi,
+                                     s_qx, s_qy, s_w, s_mb, s_f);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,18 +657,33 @@ int elementwise_blocks(long long n) {
 }
 }  // namespace
 
-template <typename T>
-static hipError_t launch_step_t(const T* fin, T* fout, const Grid& g, const Tiling& t, const StepCoef<T>& c,
+template <typename T, bool UNIT, bool STAGED>
+static hipError_t launch_step_v(const T* fin, T* fout, const Grid& g, const Tiling& t, const StepCoef<T>& c,
                                 hipStream_t s) {
     dim3 grid(t.nblocks);
     switch (t.nt) {
-        case 64: step_fused<T, 64><<<grid, 64, 0, s>>>(fin, fout, g, t, c); break;
-        case 128: step_fused<T, 128><<<grid, 128, 0, s>>>(fin, fout, g, t, c); break;
-        case 256: step_fused<T, 256><<<grid, 256, 0, s>>>(fin, fout, g, t, c); break;
-        case 512: step_fused<T, 512><<<grid, 512, 0, s>>>(fin, fout, g, t, c); break;
+        case 64: step_fused<T, 64, UNIT, STAGED><<<grid, 64, 0, s>>>(fin, fout, g, t, c); break;
+        case 128: step_fused<T, 128, UNIT, STAGED><<<grid, 128, 0, s>>>(fin, fout, g, t, c); break;
+        case 256: step_fused<T, 256, UNIT, STAGED><<<grid, 256, 0, s>>>(fin, fout, g, t, c); break;
+        case 512: step_fused<T, 512, UNIT, STAGED><<<grid, 512, 0, s>>>(fin, fout, g, t, c); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// FP32 grids whose width is a multiple of 4 use the LDS-staged row loader
+// (aligned 16-byte loads); other FP32 widths and FP64 (whose pulls are
+// 8-byte loads already) pull directly.
+template <typename T>
+static hipError_t launch_step_t(const T* fin, T* fout, const Grid& g, const Tiling& t, const StepCoef<T>& c,
+                                hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (g.nx % 4 == 0 && t.staged)
+            return c.unit ? launch_step_v<T, true, true>(fin, fout, g, t, c, s)
+                          : launch_step_v<T, false, true>(fin, fout, g, t, c, s);
+    }
+    return c.unit ? launch_step_v<T, true, false>(fin, fout, g, t, c, s)
+                  : launch_step_v<T, false, false>(fin, fout, g, t, c, s);
 }
 
 hipError_t launch_step(int precision, const void* fin, void* fout, const Grid& g, const Tiling& t, const void* coef,
@@ -544,6 +745,25 @@ hipError_t launch_scatter(int precision, const void* dense, const Grid& g, void*
 
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
     fill_zero_k<<<elementwise_blocks(n), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbch
+
+// ---------------------------------------------------------------------------
+// Streaming copy used only to measure the HBM ceiling and calibrate counters.
+// ---------------------------------------------------------------------------
+namespace lbch {
+
+__global__ __launch_bounds__(256) void copy16_k(const float4* __restrict__ src, float4* __restrict__ dst, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t s) {
+    long long b = (n16 + 255) / 256;
+    const int nb = (int)(b < 16384 ? (b < 1 ? 1 : b) : 16384);
+    copy16_k<<<nb, 256, 0, s>>>((const float4*)src, (float4*)dst, n16);
     return hipGetLastError();
 }
 

@@ -85,6 +85,10 @@ _SIGNATURES = {
     "lbch_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbch_get_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
+    "lbch_set_row_loader": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "lbch_diag_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -236,7 +240,23 @@ class Sim:
     def set_tiling(self, block_threads: int, rows_per_block: int):
         _check(lib().lbch_set_tiling(self._h, block_threads, rows_per_block), "lbch_set_tiling")
 
+    def autotune(self, steps_per_trial: int = 5):
+        """Picks the fastest launch shape for this grid; returns (block_threads, rows, ms_per_step)."""
+        a, r, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().lbch_autotune(self._h, steps_per_trial, ctypes.byref(a), ctypes.byref(r), ctypes.byref(ms)),
+               "lbch_autotune")
+        return a.value, r.value, ms.value
+
+    def set_row_loader(self, mode: int):
+        _check(lib().lbch_set_row_loader(self._h, mode), "lbch_set_row_loader")
+
     def tiling(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().lbch_get_tiling(self._h, ctypes.byref(a), ctypes.byref(b)), "lbch_get_tiling")
         return a.value, b.value
+
+
+def diag_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream=None):
+    """Plain streaming copy (measurement helper of include/lbch_diag.h)."""
+    _check(lib().lbch_diag_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), nbytes,
+                                _stream_handle(stream)), "lbch_diag_copy")

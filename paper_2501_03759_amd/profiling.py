@@ -1,0 +1,118 @@
+"""Turns rocprofv3 output of bench.py runs into the committed summaries under profiles/.
+
+Usage (after the three profiled runs named in the summary header):
+    python -m paper_2501_03759_amd.profiling --trace DIR --fetch DIR --write DIR \
+        --nodes N --precision fp32 --command "..." --out profiles/<name>
+
+FETCH_SIZE / WRITE_SIZE are read per dispatch (KiB) and scaled by what the
+same counter reads for the library's plain copy kernel, which moves a known
+number of bytes in the same process (read = write = its buffer size).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_03759_amd", "csrc", "lbch_kernels.hip")
+STEP_KERNEL = "step_fused"
+COPY_KERNEL = "copy16_k"
+COPY_BYTES = 1 << 30          # bench.py's copy_ceiling buffer
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def _one(pattern):
+    files = glob.glob(pattern, recursive=True)
+    if not files:
+        raise FileNotFoundError(pattern)
+    return files[0]
+
+
+def counter_values(d, counter, kernel_substr):
+    path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+    vals = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter and kernel_substr in r["Kernel_Name"]:
+            vals.append(float(r["Counter_Value"]))
+    return vals
+
+
+def kernel_stats(d):
+    path = _one(os.path.join(d, "**", "*kernel_stats.csv"))
+    out = []
+    for r in csv.DictReader(open(path)):
+        out.append({"name": r["Name"][:120], "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                    "pct": float(r["Percentage"])})
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--nodes", type=int, required=True)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--command", required=True, help="the profiled command lines (for the summary header)")
+    ap.add_argument("--out", required=True, help="output prefix, e.g. profiles/step_fused_spinodal8192_fp32")
+    args = ap.parse_args()
+
+    esize = 4 if args.precision == "fp32" else 8
+    kib = 1024.0
+    f_copy = statistics.median(counter_values(args.fetch, "FETCH_SIZE", COPY_KERNEL)) * kib
+    w_copy = statistics.median(counter_values(args.write, "WRITE_SIZE", COPY_KERNEL)) * kib
+    fetch_scale = COPY_BYTES / f_copy
+    write_scale = COPY_BYTES / w_copy
+    f_step = statistics.median(counter_values(args.fetch, "FETCH_SIZE", STEP_KERNEL)) * kib * fetch_scale
+    w_step = statistics.median(counter_values(args.write, "WRITE_SIZE", STEP_KERNEL)) * kib * write_scale
+    stats = kernel_stats(args.trace)
+    step = [s for s in stats if STEP_KERNEL in s["name"]][0]
+    alg = 18 * esize * args.nodes
+    rec = {
+        "kernel": step["name"],
+        "kernel_sha256_16": kernel_hash(),
+        "nodes": args.nodes,
+        "precision": args.precision,
+        "avg_duration_ms": step["avg_ns"] / 1e6,
+        "fetch_scale_from_copy": fetch_scale,
+        "write_scale_from_copy": write_scale,
+        "fetch_bytes_per_launch": f_step,
+        "write_bytes_per_launch": w_step,
+        "bytes_per_launch": f_step + w_step,
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_over_algorithmic": (f_step + w_step) / alg,
+        "achieved_alg_GBs": alg / (step["avg_ns"] * 1e-9) / 1e9,
+        "achieved_traffic_GBs": (f_step + w_step) / (step["avg_ns"] * 1e-9) / 1e9,
+    }
+    with open(args.out + ".json", "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = [f"# rocprofv3 summary: {step['name']}", "", "Commands:", ""]
+    lines += ["    " + c for c in args.command.split(";;")]
+    lines += ["", "Kernel statistics (--kernel-trace --stats):", "",
+              "| kernel | calls | avg ms | % time |", "|---|---|---|---|"]
+    for s in stats[:8]:
+        lines.append(f"| {s['name'][:90]} | {s['calls']} | {s['avg_ns'] / 1e6:.4f} | {s['pct']:.1f} |")
+    lines += ["", "HBM traffic of the step kernel (--pmc FETCH_SIZE, then --pmc WRITE_SIZE):", "",
+              f"- copy-kernel calibration: FETCH_SIZE x {fetch_scale:.3f}, WRITE_SIZE x {write_scale:.3f} "
+              f"(the copy moves {COPY_BYTES} B each way)",
+              f"- fetched {f_step / 1e9:.3f} GB, written {w_step / 1e9:.3f} GB per launch; "
+              f"algorithmic {alg / 1e9:.3f} GB (72 B/node FP32, 144 B/node FP64); "
+              f"ratio {rec['traffic_over_algorithmic']:.3f}",
+              f"- average duration {rec['avg_duration_ms']:.4f} ms -> {rec['achieved_alg_GBs']:.0f} GB/s algorithmic, "
+              f"{rec['achieved_traffic_GBs']:.0f} GB/s measured traffic (8000 GB/s peak)",
+              f"- kernel source sha256[:16] = {rec['kernel_sha256_16']}"]
+    with open(args.out + ".md", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

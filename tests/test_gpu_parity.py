@@ -21,13 +21,15 @@ def lb():
 
 def c1_params(precision=0, **kw):
     d = inputs.C1
-    return common.make_params(64, 64, precision, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
-                              aniso_m=4, eps_reg=d["eps_reg"], **kw)
+    args = dict(eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"], aniso_m=4, eps_reg=d["eps_reg"])
+    args.update(kw)
+    return common.make_params(64, 64, precision, **args)
 
 
-def run_gpu(p, phi0, nsteps, tiling=None):
+def run_gpu(p, phi0, nsteps, tiling=None, loader=0):
     L = lb()
     with L.Sim(p) as s:
+        s.set_row_loader(loader)
         if tiling:
             s.set_tiling(*tiling)
         s.init(phi0)
@@ -100,11 +102,12 @@ def test_tiling_is_bitwise_invariant(precision):
     p = common.make_params(300, 130, precision, width=4.0, alpha=0.3, s=inputs.C1_RATES_DISTINCT)
     phi0 = inputs.spinodal(300, 130, seed=5, amp=0.3)
     ref = None
-    for tiling in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 130), (512, 33), (128, 1000)]:
-        got = run_gpu(p, phi0, 60, tiling)
-        if ref is None:
-            ref = got
-        assert np.array_equal(got, ref), tiling
+    for loader in (0, 1):
+        for tiling in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 130), (512, 33), (128, 1000)]:
+            got = run_gpu(p, phi0, 60, tiling, loader)
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), (tiling, loader)
 
 
 def test_reductions_against_oracle():
@@ -285,3 +288,19 @@ def test_full_size_mass_conservation_fp32():
     scale = np.abs(phi0).sum()
     assert abs(m1 - m0) / scale <= 1e-6
     assert -1.5 < lo < hi < 1.5
+
+
+def test_autotune_keeps_state_and_results():
+    L = lb()
+    p = common.make_params(200, 120, 1, width=4.0, alpha=0.3)
+    phi0 = inputs.spinodal(200, 120, seed=21, amp=0.3)
+    want = run_gpu(p, phi0, 40)
+    with L.Sim(p) as s:
+        s.init(phi0)
+        s.step(10)
+        before = s.phi()
+        nt, hc, ms = s.autotune(2)
+        assert nt in (64, 128, 256, 512) and hc >= 1 and ms > 0
+        assert s.nstep == 10 and np.array_equal(s.phi(), before)
+        s.step(30)
+        assert np.array_equal(s.phi(), want)
