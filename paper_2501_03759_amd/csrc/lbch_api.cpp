@@ -17,11 +17,10 @@
 
 using namespace lbch;
 
-namespace {
+namespace lbch {
 
 thread_local std::string g_err;
 
-lbch_status fail(lbch_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 lbch_status fail(lbch_status code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -31,6 +30,10 @@ lbch_status fail(lbch_status code, const char* fmt, ...) {
     g_err = buf;
     return code;
 }
+
+}  // namespace lbch
+
+namespace {
 
 lbch_status ok() { return LBCH_OK; }
 
@@ -154,7 +157,7 @@ extern "C" lbch_status lbch_relaxation_rates(const lbch_params* p, double s_out[
 }
 
 // ---------------------------------------------------------------- helpers
-namespace {
+namespace lbch {
 
 template <typename T>
 void fill_coef(const lbch_params* p, StepCoef<T>& c) {
@@ -252,6 +255,13 @@ Tiling make_tiling(int nx, int ny, int nt, int hc) {
     return t;
 }
 
+template void fill_coef<double>(const lbch_params*, StepCoef<double>&);
+template void fill_coef<float>(const lbch_params*, StepCoef<float>&);
+
+}  // namespace lbch
+
+namespace {
+
 const void* coef_ptr(const lbch_sim* s) {
     return s->precision == LBCH_FP64 ? (const void*)&s->cd : (const void*)&s->cf;
 }
@@ -342,7 +352,7 @@ extern "C" lbch_status lbch_init_device(lbch_sim* s, const void* phi0_dev, int32
     if (n != (int64_t)s->g.nx * s->g.ny)
         return fail(LBCH_E_INVALID, "n = %lld but the grid has %lld nodes", (long long)n,
                     (long long)s->g.nx * s->g.ny);
-    HIP_TRY(hipMemsetAsync(s->bad, 0, sizeof(unsigned), s->stream));
+    HIP_TRY(launch_zero_u32(s->bad, 1, s->stream));
     HIP_TRY(launch_init(s->precision, phi0_dev, dtype, s->f[0], s->g, coef_ptr(s), s->bad, s->stream));
     s->cur = 0;
     s->step = 0;
@@ -513,7 +523,7 @@ extern "C" lbch_status lbch_load_state(lbch_sim* s, const void* src, int32_t src
     HIP_TRY(hipMemcpyAsync(tmp, (const char*)src + sizeof h, body,
                            src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_scatter(s->precision, tmp, s->g, s->f[s->cur], s->stream));
-    HIP_TRY(hipMemsetAsync(s->bad, 0, sizeof(unsigned), s->stream));
+    HIP_TRY(launch_zero_u32(s->bad, 1, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->step = h.step;
     s->initialized = true;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/lbch.h"
+
 namespace lbch {
 
 // Geometry of one periodic grid as stored in HBM: 9 population planes
@@ -62,7 +64,32 @@ hipError_t launch_finalize(const double* partials, int nparts, int nvals, const 
 hipError_t launch_gather(int precision, const void* fin, const Grid& g, void* dense, hipStream_t s);
 hipError_t launch_scatter(int precision, const void* dense, const Grid& g, void* fout, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t s);
+
+// Ensemble (lbch_batch): one descriptor per member; the members' populations
+// live at `base` elements into two shared buffers.
+template <typename T>
+struct BatchMember {
+    Grid g;
+    long long base;
+    StepCoef<T> c;
+    int strips, hc, chunks, tile_begin;
+};
+
+hipError_t launch_batch_step(int precision, int nt, bool unit_all, const void* fin, void* fout, const void* members,
+                             const int* tile_member, int total_tiles, int nblocks, unsigned long long* ctr,
+                             hipStream_t s);
+// resident workgroups per CU of the batch kernel (for sizing its persistent grid)
+int batch_blocks_per_cu(int precision, int nt, bool unit_all);
+
+// Host helpers shared by the C-ABI files (lbch_api.cpp).
+lbch_status fail(lbch_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+template <typename T>
+void fill_coef(const lbch_params* p, StepCoef<T>& c);
+void fill_red(const lbch_params* p, RedCoef& r);
+Tiling make_tiling(int nx, int ny, int nt, int hc);
 
 constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
 constexpr int kRedThreads = 256;

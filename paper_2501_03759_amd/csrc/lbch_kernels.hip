@@ -457,6 +457,54 @@ __global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* _
 }
 
 // ---------------------------------------------------------------------------
+// Ensemble step: every strip-tile of every member of a batch, one persistent
+// launch.  Workgroups take tiles from a work queue: a 64-bit counter that
+// only ever grows; in one launch the counter passes through exactly
+// total_tiles + gridDim.x values (each workgroup's last take is the one past
+// the end), so taking `counter mod (total_tiles + gridDim.x)` needs no reset
+// between launches and works unchanged inside a captured graph.  Every
+// workgroup leaves the loop after its first take past the end.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool UNIT_ALL>
+__global__ __launch_bounds__(NT) void batch_step(const T* __restrict__ fin, T* __restrict__ fout,
+                                                 const BatchMember<T>* __restrict__ members,
+                                                 const int* __restrict__ tile_member, const int total_tiles,
+                                                 unsigned long long* __restrict__ counter) {
+    __shared__ T s_phi[3][NT];
+    __shared__ T s_qx[3][NT];
+    __shared__ T s_qy[3][NT];
+    __shared__ T s_w[3][NT];
+    __shared__ T s_mb[3][NT];
+    __shared__ int s_tile;
+    const unsigned long long period = (unsigned long long)total_tiles + gridDim.x;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)(atomicAdd(counter, 1ull) % period);
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= total_tiles) break;
+        const BatchMember<T>& d = members[tile_member[tile]];
+        const Grid g = d.g;
+        const StepCoef<T> c = d.c;
+        const int local = tile - d.tile_begin;
+        const int strip = local % d.strips;
+        const int chunk = local / d.strips;
+        const int W = NT - 8;
+        const int x0 = strip * W;
+        const int y0 = chunk * d.hc;
+        const T* mfin = fin + d.base;
+        T* mfout = fout + d.base;
+        if (UNIT_ALL || c.unit)
+            sweep_strip<T, NT, true, false>(mfin, mfout, g, x0, min(W, g.nx - x0), y0, min(d.hc, g.ny - y0), c,
+                                            s_phi, s_qx, s_qy, s_w, s_mb, nullptr);
+        else
+            sweep_strip<T, NT, false, false>(mfin, mfout, g, x0, min(W, g.nx - x0), y0, min(d.hc, g.ny - y0), c,
+                                             s_phi, s_qx, s_qy, s_w, s_mb, nullptr);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Initialisation at equilibrium (eq 18 with mu_alpha of eq 16 at phi0), stored
 // in the post-collision layout consumed by the pull of step_fused: population
 // i at node x is written where the next step will pull it from, x - c_i.
@@ -644,6 +692,16 @@ __global__ __launch_bounds__(256) void scatter_k(const T* __restrict__ dense, co
     }
 }
 
+__global__ void zero_u64_k(unsigned long long* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void zero_u32_k(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 __global__ void fill_zero_k(double* p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -693,6 +751,52 @@ hipError_t launch_step(int precision, const void* fin, void* fout, const Grid& g
     return launch_step_t<float>((const float*)fin, (float*)fout, g, t, *(const StepCoef<float>*)coef, s);
 }
 
+
+template <typename T, bool UA>
+static hipError_t launch_batch_t(int nt, const T* fin, T* fout, const BatchMember<T>* m, const int* tm, int total,
+                                 int nblocks, unsigned long long* ctr, hipStream_t s) {
+    switch (nt) {
+        case 64: batch_step<T, 64, UA><<<nblocks, 64, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        case 128: batch_step<T, 128, UA><<<nblocks, 128, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        case 256: batch_step<T, 256, UA><<<nblocks, 256, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        case 512: batch_step<T, 512, UA><<<nblocks, 512, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int precision, int nt, bool unit_all, const void* fin, void* fout, const void* members,
+                             const int* tile_member, int total_tiles, int nblocks, unsigned long long* ctr,
+                             hipStream_t s) {
+    if (precision == 0) {
+        auto f = unit_all ? launch_batch_t<double, true> : launch_batch_t<double, false>;
+        return f(nt, (const double*)fin, (double*)fout, (const BatchMember<double>*)members, tile_member,
+                 total_tiles, nblocks, ctr, s);
+    }
+    auto f = unit_all ? launch_batch_t<float, true> : launch_batch_t<float, false>;
+    return f(nt, (const float*)fin, (float*)fout, (const BatchMember<float>*)members, tile_member, total_tiles,
+             nblocks, ctr, s);
+}
+
+template <typename T, bool UA>
+static int occ_t(int nt) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+    switch (nt) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 64, UA>, 64, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 128, UA>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 256, UA>, 256, 0); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 512, UA>, 512, 0); break;
+        default: return 1;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int batch_blocks_per_cu(int precision, int nt, bool unit_all) {
+    if (precision == 0) return unit_all ? occ_t<double, true>(nt) : occ_t<double, false>(nt);
+    return unit_all ? occ_t<float, true>(nt) : occ_t<float, false>(nt);
+}
+
 hipError_t launch_init(int precision, const void* phi0, int phi_dtype, void* fout, const Grid& g, const void* coef,
                        unsigned* bad, hipStream_t s) {
     const int nb = elementwise_blocks((long long)g.nx * g.ny);
@@ -740,6 +844,16 @@ hipError_t launch_scatter(int precision, const void* dense, const Grid& g, void*
     const int nb = elementwise_blocks((long long)g.nx * g.ny);
     if (precision == 0) scatter_k<double><<<nb, 256, 0, s>>>((const double*)dense, g, (double*)fout);
     else scatter_k<float><<<nb, 256, 0, s>>>((const float*)dense, g, (float*)fout);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+    zero_u64_k<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s) {
+    zero_u32_k<<<(n + 255) / 256, 256, 0, s>>>(p, n);
     return hipGetLastError();
 }
 

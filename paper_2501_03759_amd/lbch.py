@@ -88,6 +88,27 @@ _SIGNATURES = {
     "lbch_set_row_loader": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "lbch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "lbch_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "lbch_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbch_batch_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_int64]),
+    "lbch_batch_init_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                              ctypes.c_int64]),
+    "lbch_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "lbch_batch_get_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "lbch_batch_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "lbch_batch_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
+    "lbch_batch_free_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
+    "lbch_batch_phi_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_batch_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbch_batch_get_tiling": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int32)] * 4),
+    "lbch_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "lbch_batch_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "lbch_diag_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }
 
@@ -260,3 +281,94 @@ def diag_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream=None):
     """Plain streaming copy (measurement helper of include/lbch_diag.h)."""
     _check(lib().lbch_diag_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), nbytes,
                                 _stream_handle(stream)), "lbch_diag_copy")
+
+
+class Batch:
+    """An ensemble of independent periodic grids advanced together (lbch_batch)."""
+
+    def __init__(self, members, stream=None):
+        arr = (Params * len(members))(*members)
+        self._h = ctypes.c_void_p()
+        _check(lib().lbch_batch_create(arr, len(members), _stream_handle(stream), ctypes.byref(self._h)),
+               "lbch_batch_create")
+        self.shapes = [(m.ny, m.nx) for m in members]
+
+    def close(self):
+        if self._h:
+            lib().lbch_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def init(self, member: int, phi0: np.ndarray):
+        a = np.ascontiguousarray(phi0, dtype=np.float64)
+        _check(lib().lbch_batch_init(self._h, member, _dp(a.ctypes.data), a.size), "lbch_batch_init")
+
+    def init_device(self, member: int, ptr: int, dtype: int, n: int):
+        _check(lib().lbch_batch_init_device(self._h, member, ctypes.c_void_p(ptr), dtype, n), "lbch_batch_init_device")
+
+    def step(self, n: int = 1):
+        _check(lib().lbch_batch_step(self._h, int(n)), "lbch_batch_step")
+
+    @property
+    def nstep(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().lbch_batch_get_step(self._h, ctypes.byref(v)), "lbch_batch_get_step")
+        return v.value
+
+    def synchronize(self):
+        _check(lib().lbch_batch_synchronize(self._h), "lbch_batch_synchronize")
+
+    def moments(self, member: int, want_phi: bool = True):
+        ny, nx = self.shapes[member]
+        phi = np.empty((ny, nx), dtype=np.float64) if want_phi else None
+        mass, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().lbch_batch_moments(self._h, member, _dp(phi.ctypes.data) if want_phi else None,
+                                        ctypes.byref(mass), ctypes.byref(lo), ctypes.byref(hi)), "lbch_batch_moments")
+        return phi, mass.value, lo.value, hi.value
+
+    def phi(self, member: int) -> np.ndarray:
+        return self.moments(member)[0]
+
+    def free_energy(self, member: int):
+        e = ctypes.c_double()
+        terms = (ctypes.c_double * 4)()
+        _check(lib().lbch_batch_free_energy(self._h, member, ctypes.byref(e), terms), "lbch_batch_free_energy")
+        return e.value, list(terms)
+
+    def phi_device(self, member: int, ptr: int, dtype: int):
+        _check(lib().lbch_batch_phi_device(self._h, member, ctypes.c_void_p(ptr), dtype), "lbch_batch_phi_device")
+
+    def set_tiling(self, block_threads: int, rows_per_block: int = 0, persistent_blocks: int = 0):
+        _check(lib().lbch_batch_set_tiling(self._h, block_threads, rows_per_block, persistent_blocks),
+               "lbch_batch_set_tiling")
+
+    def tiling(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().lbch_batch_get_tiling(self._h, *[ctypes.byref(x) for x in v]), "lbch_batch_get_tiling")
+        return tuple(x.value for x in v)
+
+    def autotune(self, steps_per_trial: int = 3):
+        a, r, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().lbch_batch_autotune(self._h, steps_per_trial, ctypes.byref(a), ctypes.byref(r),
+                                         ctypes.byref(ms)), "lbch_batch_autotune")
+        return a.value, r.value, ms.value
+
+    @property
+    def nodes(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().lbch_batch_nodes(self._h, ctypes.byref(v)), "lbch_batch_nodes")
+        return v.value
