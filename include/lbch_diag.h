@@ -22,6 +22,25 @@ extern "C" {
  * Does not synchronise.  Bad arguments -> LBCH_E_INVALID. */
 lbch_status lbch_diag_copy(const void* src, void* dst, int64_t bytes, void* hip_stream);
 
+/* Single-operator checks of the surrogate's matrix-core kernels (used by the
+ * tests; FP32 host-side values are rounded to BF16 on the device first).
+ * All pointers are device pointers, channels-last; H, W multiples of 16,
+ * Ci, Co multiples of 32.  Allocate their own scratch; synchronise. */
+
+/* y[N][H][W][Co] = act(bias + conv3(x[N][H][W][Ci], w[Co][Ci][3][3])), periodic;
+ * act = ReLU if relu != 0; bias nullable.  y is the kernel's BF16 output widened. */
+lbch_status lbsg_diag_conv3(const float* x, const float* w, const float* bias, float* y, int32_t n, int32_t h,
+                            int32_t wd, int32_t ci, int32_t co, int32_t relu);
+
+/* dx[N][H][W][Ci] = data gradient of conv3 for dy[N][H][W][Co] (flipped,
+ * transposed weights through the forward kernel). */
+lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, float* dx, int32_t n, int32_t h, int32_t wd,
+                                  int32_t ci, int32_t co);
+
+/* dw[Co][Ci][3][3] = sum over pixels of dy[p][co] x[p + tap][ci] (FP32). */
+lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, float* dw, int32_t n, int32_t h, int32_t wd,
+                                  int32_t ci, int32_t co);
+
 #ifdef __cplusplus
 }
 #endif

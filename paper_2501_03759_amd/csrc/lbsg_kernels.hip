@@ -1,0 +1,574 @@
+// Kernels of the convolutional surrogate (periodic U-Net) for gfx950:
+// BF16 activations and weights, FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), NHWC layout with channels padded to 32.
+#include "lbsg_internal.h"
+
+namespace lbsg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kPadC = 40;   // LDS stride (bf16) of one pixel's 32-channel chunk: 80 bytes
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// 3x3 periodic convolution as an implicit GEMM on the matrix cores.
+//   Y[n,y,x,co] = act(bias[co] + sum_{tap,ci} W[co][tap][ci] X[n, y+dy, x+dx, ci])
+// GEMM view per workgroup: M = TC output channels, N = a 16x16 pixel tile,
+// K = 9 taps x Ci.  The A operand (weights, 8 consecutive ci per lane) and
+// the B operand (pixels, 8 consecutive ci per lane) are both read from LDS:
+// the pixel tile with its periodic 1-pixel halo is staged once per 32-channel
+// chunk, the weights one tap row (3 taps) at a time.  Each wave owns 4 pixel
+// rows x TC channels (4 x TC/16 MFMA tiles); the result fragment of a lane is
+// 4 consecutive output channels of one pixel (one 8-byte store).
+// ---------------------------------------------------------------------------
+template <int TC, bool RELU>
+__global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ Wt,
+                                                   const float* __restrict__ bias, __bf16* __restrict__ Y, int H,
+                                                   int Wd, int Ci, int Co) {
+    __shared__ __align__(16) __bf16 sx[18 * 18 * kPadC];
+    __shared__ __align__(16) __bf16 sw[3 * TC * kPadC];
+    constexpr int CB = TC / 16;
+    const int tiles_x = Wd / 16, tiles_y = H / 16;
+    int b = blockIdx.x;
+    const int tx0 = (b % tiles_x) * 16;
+    b /= tiles_x;
+    const int ty0 = (b % tiles_y) * 16;
+    const int n = b / tiles_y;
+    const int co0 = blockIdx.y * TC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, kb = lane >> 4;
+    f32x4 acc[4][CB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int cc = 0; cc < Ci; cc += 32) {
+        for (int q = threadIdx.x; q < 18 * 18 * 4; q += 256) {
+            const int px = q >> 2, part = q & 3;
+            const int py = px / 18, pxx = px - py * 18;
+            const int y = wrap(ty0 - 1 + py, H), x = wrap(tx0 - 1 + pxx, Wd);
+            *reinterpret_cast<bf16x8*>(sx + px * kPadC + part * 8) =
+                *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + cc + part * 8);
+        }
+        for (int ky = 0; ky < 3; ++ky) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < 3 * TC * 4; q += 256) {
+                const int row = q >> 2, part = q & 3;
+                const int kx = row / TC, co = row - kx * TC;
+                *reinterpret_cast<bf16x8*>(sw + row * kPadC + part * 8) = *reinterpret_cast<const bf16x8*>(
+                    Wt + ((size_t)(co0 + co) * 9 + ky * 3 + kx) * Ci + cc + part * 8);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                bf16x8 bfr[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    bfr[r] = *reinterpret_cast<const bf16x8*>(sx + ((wave * 4 + r + ky) * 18 + l16 + kx) * kPadC + kb * 8);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const bf16x8 afr = *reinterpret_cast<const bf16x8*>(sw + (kx * TC + c * 16 + l16) * kPadC + kb * 8);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(afr, bfr[r], acc[r][c]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int y = ty0 + wave * 4 + r, x = tx0 + l16;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int co = co0 + c * 16 + kb * 4;
+            bf16x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float v = acc[r][c][j] + (bias ? bias[co + j] : 0.f);
+                if (RELU) v = v > 0.f ? v : 0.f;
+                o[j] = (__bf16)v;
+            }
+            *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of the 3x3 convolution on the matrix cores:
+//   P[s][co][tap][ci] = sum over the pixels of split s of dY[p][co] X[p + tap][ci]
+// GEMM per tap: M = co, N = ci, K = pixels.  The operands need 8 consecutive
+// pixels per lane, so dY (16x16 pixels x TCO channels) and the tap-shifted X
+// (16x16 pixels x 16 channels) are staged transposed ([channel][pixel]) in LDS.
+// Wave w owns output channels 16w..16w+15 and all 9 taps of a 16-channel ci
+// block.  Splits are reduced by wgrad_reduce_k (fixed order: deterministic).
+// ---------------------------------------------------------------------------
+template <int TCO>
+__global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__ X, const __bf16* __restrict__ dY,
+                                                      float* __restrict__ part, int N, int H, int Wd, int Ci, int Co,
+                                                      int S) {
+    constexpr int NT = TCO * 4;          // 64 threads (one wave) per 16 output channels
+    constexpr int KS = 256 + 8;          // row stride (bf16) of the transposed tiles
+    __shared__ __align__(16) __bf16 sdy[TCO * KS];
+    __shared__ __align__(16) __bf16 sxt[16 * KS];
+    const int s = blockIdx.x;
+    const int co0 = blockIdx.y * TCO;
+    const int ci0 = blockIdx.z * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, kb = lane >> 4;
+    const int tiles_x = Wd / 16, tiles_y = H / 16, ntiles = N * tiles_x * tiles_y;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tile = s; tile < ntiles; tile += S) {
+        int b = tile;
+        const int tx0 = (b % tiles_x) * 16;
+        b /= tiles_x;
+        const int ty0 = (b % tiles_y) * 16;
+        const int n = b / tiles_y;
+        __syncthreads();
+        for (int q = threadIdx.x; q < 256 * (TCO / 8); q += NT) {
+            const int p = q / (TCO / 8), ch = q - p * (TCO / 8);
+            const int y = ty0 + (p >> 4), x = tx0 + (p & 15);
+            const bf16x8 v =
+                *reinterpret_cast<const bf16x8*>(dY + (((size_t)n * H + y) * Wd + x) * Co + co0 + ch * 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sdy[(ch * 8 + e) * KS + p] = v[e];
+        }
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            __syncthreads();
+            for (int q = threadIdx.x; q < 256 * 2; q += NT) {
+                const int p = q >> 1, ch = q & 1;
+                const int y = wrap(ty0 + (p >> 4) + dy, H), x = wrap(tx0 + (p & 15) + dx, Wd);
+                const bf16x8 v =
+                    *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sxt[(ch * 8 + e) * KS + p] = v[e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k0 = 0; k0 < 256; k0 += 32) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(sdy + (wave * 16 + l16) * KS + k0 + kb * 8);
+                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(sxt + l16 * KS + k0 + kb * 8);
+                acc[tap] = mfma16(a, bb, acc[tap]);
+            }
+        }
+    }
+    // lane holds ci = ci0 + l16, co = co0 + 16*wave + 4*kb + j
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = co0 + wave * 16 + kb * 4 + j;
+            part[(((size_t)s * Co + co) * 9 + tap) * Ci + ci0 + l16] = acc[tap][j];
+        }
+}
+
+// dW[co][ci][ky][kx] (FP32 parameter layout, only the first ci_real input
+// channels) = sum_s P[s][co][tap][ci].
+__global__ void wgrad_reduce_k(const float* __restrict__ part, float* __restrict__ dW, int S, int Co, int Ci,
+                               int ci_real) {
+    const long long total = (long long)Co * ci_real * 9;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int tap = (int)(i % 9);
+        const int ci = (int)((i / 9) % ci_real);
+        const int co = (int)(i / (9LL * ci_real));
+        float acc = 0.f;
+        for (int s = 0; s < S; ++s) acc += part[(((size_t)s * Co + co) * 9 + tap) * Ci + ci];
+        dW[i] = acc;
+    }
+}
+
+// Column sums over pixels (bias gradients): part[s][c] = sum_{p in split s} G[p][c]
+template <typename T>
+__global__ void colsum_part_k(const T* __restrict__ G, long long P, int C, int S, float* __restrict__ part) {
+    const int s = blockIdx.x;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float acc = 0.f;
+        for (long long p = s; p < P; p += S) acc += (float)G[p * C + c];
+        part[(size_t)s * C + c] = acc;
+    }
+}
+
+__global__ void colsum_reduce_k(const float* __restrict__ part, int S, int C, float* __restrict__ out) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int s = 0; s < S; ++s) acc += part[(size_t)s * C + c];
+        out[c] = acc;
+    }
+}
+
+// ----------------------------------------------------------- weight packing
+// master W[co][ci][3][3] (FP32) -> Wt[co][tap][cip] (BF16, zero padded ci)
+__global__ void pack_w_k(const float* __restrict__ W, __bf16* __restrict__ Wt, int Co, int Ci, int Cip) {
+    const long long total = (long long)Co * 9 * Cip;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % Cip);
+        const int tap = (int)((i / Cip) % 9);
+        const int co = (int)(i / (9LL * Cip));
+        Wt[i] = (__bf16)(ci < Ci ? W[((size_t)co * Ci + ci) * 9 + tap] : 0.f);
+    }
+}
+
+// master W[co][ci][3][3] -> Wf[ci][tap'][co] = W[co][ci][8 - tap'] (the flipped,
+// transposed kernel that turns the data gradient into a forward convolution)
+__global__ void pack_wflip_k(const float* __restrict__ W, __bf16* __restrict__ Wf, int Co, int Ci) {
+    const long long total = (long long)Ci * 9 * Co;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int co = (int)(i % Co);
+        const int tp = (int)((i / Co) % 9);
+        const int ci = (int)(i / (9LL * Co));
+        Wf[i] = (__bf16)W[((size_t)co * Ci + ci) * 9 + (8 - tp)];
+    }
+}
+
+// ------------------------------------------------------------- elementwise
+// fp32 [P][cin] -> bf16 [P][cpad] (zero padded channels)
+__global__ void pack_input_k(const float* __restrict__ x, __bf16* __restrict__ out, long long P, int cin, int cpad) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P * cpad;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / cpad;
+        const int c = (int)(i % cpad);
+        out[i] = (__bf16)(c < cin ? x[p * cin + c] : 0.f);
+    }
+}
+
+// Surrogate input for a single field: channel 0 = phi (fp32), channels
+// 1..ncond = constant conditioning values, rest zero.  Also writes the fp32
+// copy of phi used by the residual head (xin with one channel).
+__global__ void pack_phi_cond_k(const float* __restrict__ phi, const float* __restrict__ cond, int ncond,
+                                __bf16* __restrict__ out, float* __restrict__ xin, long long P, int cpad) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P * cpad;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / cpad;
+        const int c = (int)(i % cpad);
+        float v = 0.f;
+        if (c == 0) {
+            v = phi[p];
+            xin[p] = v;
+        } else if (c <= ncond) {
+            v = cond[c - 1];
+        }
+        out[i] = (__bf16)v;
+    }
+}
+
+__global__ void avgpool2_k(const __bf16* __restrict__ x, __bf16* __restrict__ y, int N, int H, int Wd, int C) {
+    const int Ho = H / 2, Wo = Wd / 2;
+    const long long total = (long long)N * Ho * Wo * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long q = i / C;
+        const int xo = (int)(q % Wo);
+        q /= Wo;
+        const int yo = (int)(q % Ho);
+        const int n = (int)(q / Ho);
+        auto at = [&](int yy, int xx) { return (float)x[(((size_t)n * H + yy) * Wd + xx) * C + c]; };
+        y[i] = (__bf16)(0.25f * ((at(2 * yo, 2 * xo) + at(2 * yo, 2 * xo + 1)) +
+                                 (at(2 * yo + 1, 2 * xo) + at(2 * yo + 1, 2 * xo + 1))));
+    }
+}
+
+// dx (N,H,W,C) (+)= avgpool2 adjoint of dy (N,H/2,W/2,C)
+__global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict__ dx, int N, int H, int Wd, int C,
+                               int accumulate) {
+    const long long total = (long long)N * H * Wd * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long q = i / C;
+        const int x = (int)(q % Wd);
+        q /= Wd;
+        const int y = (int)(q % H);
+        const int n = (int)(q / H);
+        float v = 0.25f * (float)dy[(((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c];
+        if (accumulate) v += (float)dx[i];
+        dx[i] = (__bf16)v;
+    }
+}
+
+// z[..., 0:Cu] = up2(u), z[..., Cu:Cu+Cs] = s     (u: N,H/2,W/2,Cu; s, z: N,H,W)
+__global__ void up2_concat_k(const __bf16* __restrict__ u, const __bf16* __restrict__ sk, __bf16* __restrict__ z,
+                             int N, int H, int Wd, int Cu, int Cs) {
+    const int C = Cu + Cs;
+    const long long total = (long long)N * H * Wd * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const long long p = i / C;
+        const int x = (int)(p % Wd);
+        const long long q = p / Wd;
+        const int y = (int)(q % H);
+        const int n = (int)(q / H);
+        z[i] = c < Cu ? u[(((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + c] : sk[p * Cs + (c - Cu)];
+    }
+}
+
+// adjoint of up2_concat: du = sum of the 2x2 block of dz[..., :Cu]; dsk (+)= dz[..., Cu:]
+__global__ void up2_concat_bwd_k(const __bf16* __restrict__ dz, __bf16* __restrict__ du, __bf16* __restrict__ dsk,
+                                 int N, int H, int Wd, int Cu, int Cs, int accumulate) {
+    const int C = Cu + Cs;
+    const int Ho = H / 2, Wo = Wd / 2;
+    const long long tu = (long long)N * Ho * Wo * Cu;
+    const long long ts = (long long)N * H * Wd * Cs;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tu + ts;
+         i += (long long)gridDim.x * blockDim.x) {
+        if (i < tu) {
+            const int c = (int)(i % Cu);
+            long long q = i / Cu;
+            const int xo = (int)(q % Wo);
+            q /= Wo;
+            const int yo = (int)(q % Ho);
+            const int n = (int)(q / Ho);
+            float v = 0.f;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb)
+                    v += (float)dz[(((size_t)n * H + 2 * yo + a) * Wd + 2 * xo + bb) * C + c];
+            du[i] = (__bf16)v;
+        } else {
+            const long long j = i - tu;
+            const int c = (int)(j % Cs);
+            const long long p = j / Cs;
+            float v = (float)dz[p * C + Cu + c];
+            if (accumulate) v += (float)dsk[j];
+            dsk[j] = (__bf16)v;
+        }
+    }
+}
+
+// g = dy * (y > 0)   (ReLU backward from the stored post-activation)
+__global__ void relu_bwd_k(const __bf16* __restrict__ dy, const __bf16* __restrict__ y, __bf16* __restrict__ g,
+                           long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        g[i] = (float)y[i] > 0.f ? dy[i] : (__bf16)0.f;
+}
+
+// head: out[p] = phi[p] + b + sum_c w[c] d[p][c]   (phi = input channel 0, fp32)
+__global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict__ w, const float* __restrict__ b,
+                           const float* __restrict__ xin, int cin, float* __restrict__ out, long long P, int C) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+        float acc = b[0];
+        for (int c = 0; c < C; ++c) acc += w[c] * (float)d[p * C + c];
+        out[p] = xin[p * cin] + acc;
+    }
+}
+
+// dd[p][c] = g[p] w[c]; part[s][c] = sum_{p in split} g[p] d[p][c] (c < C), part[s][C] = sum g
+__global__ void head_bwd_k(const float* __restrict__ g, const __bf16* __restrict__ d, const float* __restrict__ w,
+                           __bf16* __restrict__ dd, long long P, int C, int S, float* __restrict__ part) {
+    const int s = blockIdx.x;
+    for (long long p = s * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)S * blockDim.x)
+        for (int c = 0; c < C; ++c) dd[p * C + c] = (__bf16)(g[p] * w[c]);
+    // reductions: thread c handles column c (and C the bias)
+    for (int c = threadIdx.x; c <= C; c += blockDim.x) {
+        float acc = 0.f;
+        for (long long p = s; p < P; p += S) acc += c < C ? g[p] * (float)d[p * C + c] : g[p];
+        part[(size_t)s * (C + 1) + c] = acc;
+    }
+}
+
+// masked MSE: g = 2 (pred - target) / count inside the interior, 0 outside;
+// part[block] = partial sum of squared differences (float64)
+__global__ void mse_k(const float* __restrict__ pred, const float* __restrict__ target, float* __restrict__ g, int N,
+                      int H, int Wd, int margin, double inv_count, double* __restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const long long total = (long long)N * H * Wd;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % Wd);
+        const int y = (int)((i / Wd) % H);
+        const bool in = y >= margin && y < H - margin && x >= margin && x < Wd - margin;
+        const double diff = (double)pred[i] - (double)target[i];
+        g[i] = in ? (float)(2.0 * diff * inv_count) : 0.f;
+        if (in) acc += diff * diff;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void sum_k(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Adam (bias-corrected) on the FP32 master parameters.
+__global__ void adam_k(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       long long n, float lr, float b1, float b2, float eps, float wd, float c1, float c2) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i] + wd * w[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void widen_k(const __bf16* __restrict__ a, float* __restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+// ----------------------------------------------------------------- launchers
+namespace {
+int grid_for(long long n) {
+    long long b = (n + 255) / 256;
+    return (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+}
+}  // namespace
+
+hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd, int Ci,
+                     int Co, bool relu, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || Co % 32) return hipErrorInvalidValue;
+    const int tiles = N * (H / 16) * (Wd / 16);
+    if (Co % 64 == 0) {
+        dim3 grid(tiles, Co / 64);
+        if (relu) conv3_fwd_k<64, true><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
+        else conv3_fwd_k<64, false><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
+    } else {
+        dim3 grid(tiles, Co / 32);
+        if (relu) conv3_fwd_k<32, true><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
+        else conv3_fwd_k<32, false><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
+    }
+    return hipGetLastError();
+}
+
+hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
+                    hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 16 || Co % 32) return hipErrorInvalidValue;
+    if (Co % 64 == 0) {
+        dim3 grid(S, Co / 64, Ci / 16);
+        conv3_dw_k<64><<<grid, 256, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S);
+    } else {
+        dim3 grid(S, Co / 32, Ci / 16);
+        conv3_dw_k<32><<<grid, 128, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S);
+    }
+    return hipGetLastError();
+}
+
+hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s) {
+    wgrad_reduce_k<<<grid_for((long long)Co * ci_real * 9), 256, 0, s>>>(part, dW, S, Co, Ci, ci_real);
+    return hipGetLastError();
+}
+
+hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s) {
+    colsum_part_k<__bf16><<<S, 256, 0, s>>>(G, P, C, S, part);
+    colsum_reduce_k<<<(C + 255) / 256, 256, 0, s>>>(part, S, C, out);
+    return hipGetLastError();
+}
+
+hipError_t widen(const __bf16* a, float* b, long long n, hipStream_t s) {
+    widen_k<<<grid_for(n), 256, 0, s>>>(a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t pack_w(const float* W, __bf16* Wt, int Co, int Ci, int Cip, hipStream_t s) {
+    pack_w_k<<<grid_for((long long)Co * 9 * Cip), 256, 0, s>>>(W, Wt, Co, Ci, Cip);
+    return hipGetLastError();
+}
+
+hipError_t pack_wflip(const float* W, __bf16* Wf, int Co, int Ci, hipStream_t s) {
+    pack_wflip_k<<<grid_for((long long)Co * 9 * Ci), 256, 0, s>>>(W, Wf, Co, Ci);
+    return hipGetLastError();
+}
+
+hipError_t pack_input(const float* x, __bf16* out, long long P, int cin, int cpad, hipStream_t s) {
+    pack_input_k<<<grid_for(P * cpad), 256, 0, s>>>(x, out, P, cin, cpad);
+    return hipGetLastError();
+}
+
+hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16* out, float* xin, long long P, int cpad,
+                         hipStream_t s) {
+    pack_phi_cond_k<<<grid_for(P * cpad), 256, 0, s>>>(phi, cond, ncond, out, xin, P, cpad);
+    return hipGetLastError();
+}
+
+hipError_t avgpool2(const __bf16* x, __bf16* y, int N, int H, int Wd, int C, hipStream_t s) {
+    avgpool2_k<<<grid_for((long long)N * H * Wd * C / 4), 256, 0, s>>>(x, y, N, H, Wd, C);
+    return hipGetLastError();
+}
+
+hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s) {
+    avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t up2_concat(const __bf16* u, const __bf16* sk, __bf16* z, int N, int H, int Wd, int Cu, int Cs,
+                      hipStream_t s) {
+    up2_concat_k<<<grid_for((long long)N * H * Wd * (Cu + Cs)), 256, 0, s>>>(u, sk, z, N, H, Wd, Cu, Cs);
+    return hipGetLastError();
+}
+
+hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
+                          bool accumulate, hipStream_t s) {
+    const long long n = (long long)N * (H / 2) * (Wd / 2) * Cu + (long long)N * H * Wd * Cs;
+    up2_concat_bwd_k<<<grid_for(n), 256, 0, s>>>(dz, du, dsk, N, H, Wd, Cu, Cs, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s) {
+    relu_bwd_k<<<grid_for(n), 256, 0, s>>>(dy, y, g, n);
+    return hipGetLastError();
+}
+
+hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
+                    long long P, int C, hipStream_t s) {
+    head_fwd_k<<<grid_for(P), 256, 0, s>>>(d, w, b, xin, cin, out, P, C);
+    return hipGetLastError();
+}
+
+hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float* part,
+                    float* grad_wb, hipStream_t s) {
+    head_bwd_k<<<S, 256, 0, s>>>(g, d, w, dd, P, C, S, part);
+    colsum_reduce_k<<<1, 256, 0, s>>>(part, S, C + 1, grad_wb);
+    return hipGetLastError();
+}
+
+hipError_t mse(const float* pred, const float* target, float* g, int N, int H, int Wd, int margin, double* part,
+               double* out, hipStream_t s) {
+    const long long inner = (long long)N * (H - 2 * margin) * (Wd - 2 * margin);
+    if (inner <= 0) return hipErrorInvalidValue;
+    mse_k<<<256, 256, 0, s>>>(pred, target, g, N, H, Wd, margin, 1.0 / (double)inner, part);
+    sum_k<<<1, 256, 0, s>>>(part, 256, out);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* w, const float* g, float* m, float* v, long long n, float lr, float b1, float b2, float eps,
+                float wd, float c1, float c2, hipStream_t s) {
+    adam_k<<<grid_for(n), 256, 0, s>>>(w, g, m, v, n, lr, b1, b2, eps, wd, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace lbsg

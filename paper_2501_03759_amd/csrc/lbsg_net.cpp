@@ -1,0 +1,520 @@
+// The surrogate network (include/lbsg.h): parameter storage, activation
+// buffers and the order of kernel launches for forward, backward, Adam.
+#include "../../include/lbch_diag.h"
+#include "../../include/lbsg.h"
+#include "lbch_internal.h"
+#include "lbsg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+using lbch::fail;
+
+#define HIP_TRY(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(LBCH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+struct Layer {
+    int ci_real, ci_pad, co, k;
+    long long offW, offB;
+    __bf16* wt = nullptr;     // [co][9][ci_pad]
+    __bf16* wf = nullptr;     // [ci_pad][9][co] flipped (data gradient), not for the first layer
+};
+
+struct Level {
+    // forward activations (bf16, channels-last)
+    __bf16 *z = nullptr, *a = nullptr, *e = nullptr;      // encoder block input, mid, output
+    __bf16 *zc = nullptr, *da = nullptr, *d = nullptr;    // decoder block input (concat), mid, output
+    // gradients
+    __bf16 *gz = nullptr, *ga = nullptr, *ge = nullptr, *gzc = nullptr, *gda = nullptr, *gd = nullptr;
+};
+
+int round32(int c) { return (c + 31) / 32 * 32; }
+
+}  // namespace
+
+struct lbsg_net {
+    lbsg_arch arch{};
+    int max_b = 0, max_h = 0, max_w = 0;
+    bool train = false;
+    hipStream_t stream = nullptr;
+    std::vector<Layer> layers;
+    std::vector<Level> lv;
+    long long nparam = 0;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    __bf16* gtmp = nullptr;          // relu-masked gradient of one conv output
+    float* wpart = nullptr;          // weight-gradient split partials
+    long long wpart_elems = 0;
+    float* cpart = nullptr;          // column-sum partials
+    float* out = nullptr;            // fp32 prediction [B][H][W]
+    float* gout = nullptr;           // fp32 dLoss/dprediction
+    float* xin1 = nullptr;           // fp32 phi (one channel) for lbsg_predict
+    float* cond = nullptr;           // conditioning values (device)
+    double* dpart = nullptr;
+    double* dloss = nullptr;
+    int adam_t = 0;
+    // shape of the last forward
+    int cur_b = 0, cur_h = 0, cur_w = 0;
+    std::vector<void*> allocs;       // every device allocation of the net
+};
+
+namespace {
+
+struct Alloc {
+    std::vector<void*> ptrs;
+    hipError_t err = hipSuccess;
+    template <typename T>
+    T* get(size_t count) {
+        if (err != hipSuccess) return nullptr;
+        void* p = nullptr;
+        err = hipMalloc(&p, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+        if (err != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return (T*)p;
+    }
+};
+
+}  // namespace
+
+namespace {
+
+lbch_status ok() { return LBCH_OK; }
+
+void release(lbsg_net* n) {
+    for (void* p : n->allocs)
+        if (p) (void)hipFree(p);
+    n->allocs.clear();
+}
+
+lbch_status repack(lbsg_net* n) {
+    for (size_t k = 0; k < n->layers.size(); ++k) {
+        Layer& L = n->layers[k];
+        if (L.k != 3) continue;
+        HIP_TRY(lbsg::pack_w(n->w + L.offW, L.wt, L.co, L.ci_real, L.ci_pad, n->stream));
+        if (L.wf) HIP_TRY(lbsg::pack_wflip(n->w + L.offW, L.wf, L.co, L.ci_real, n->stream));
+    }
+    return ok();
+}
+
+// gradient of one conv layer: gout = dLoss/d(post-ReLU output y), input z.
+lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16* y, const __bf16* gout, __bf16* dz,
+                      int B, int H, int W) {
+    const long long P = (long long)B * H * W;
+    HIP_TRY(lbsg::relu_bwd(gout, y, n->gtmp, P * L.co, n->stream));
+    const int ntiles = B * (H / 16) * (W / 16);
+    const int other = (L.co % 64 == 0 ? L.co / 64 : L.co / 32) * (L.ci_pad / 16);
+    int S = 1024 / (other > 0 ? other : 1);
+    if (S < 1) S = 1;
+    if (S > ntiles) S = ntiles;
+    while ((long long)S * L.co * 9 * L.ci_pad > n->wpart_elems && S > 1) S /= 2;
+    HIP_TRY(lbsg::conv3_dw(z, n->gtmp, n->wpart, S, B, H, W, L.ci_pad, L.co, n->stream));
+    HIP_TRY(lbsg::wgrad_reduce(n->wpart, n->g + L.offW, S, L.co, L.ci_pad, L.ci_real, n->stream));
+    HIP_TRY(lbsg::colsum_bf16(n->gtmp, P, L.co, 256, n->cpart, n->g + L.offB, n->stream));
+    if (dz) HIP_TRY(lbsg::conv3_fwd(n->gtmp, L.wf, nullptr, dz, B, H, W, L.co, L.ci_pad, false, n->stream));
+    return ok();
+}
+
+lbch_status check_shape(const lbsg_net* n, int B, int H, int W) {
+    const int unit = 16 << (n->arch.levels - 1);
+    if (B < 1 || B > n->max_b || H < unit || W < unit || H > n->max_h || W > n->max_w || H % unit || W % unit)
+        return fail(LBCH_E_INVALID, "batch %d of %dx%d: need 1..%d images, sides multiples of %d up to %dx%d", B, H, W,
+                    n->max_b, unit, n->max_h, n->max_w);
+    return ok();
+}
+
+// everything after the packed input (z_0) is in place
+lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, int cres) {
+    const int Lv = n->arch.levels;
+    const int* C = n->arch.chans;
+    int li = 0;
+    for (int l = 0; l < Lv; ++l) {
+        const int h = H >> l, w = W >> l;
+        Level& lv = n->lv[l];
+        if (l > 0) HIP_TRY(lbsg::avgpool2(n->lv[l - 1].e, lv.z, B, h * 2, w * 2, C[l - 1], n->stream));
+        const Layer& La = n->layers[li++];
+        const Layer& Lb = n->layers[li++];
+        HIP_TRY(lbsg::conv3_fwd(lv.z, La.wt, n->w + La.offB, lv.a, B, h, w, La.ci_pad, La.co, true, n->stream));
+        HIP_TRY(lbsg::conv3_fwd(lv.a, Lb.wt, n->w + Lb.offB, lv.e, B, h, w, Lb.ci_pad, Lb.co, true, n->stream));
+    }
+    const __bf16* d = n->lv[Lv - 1].e;
+    for (int l = Lv - 2; l >= 0; --l) {
+        const int h = H >> l, w = W >> l;
+        Level& lv = n->lv[l];
+        const Layer& La = n->layers[li++];
+        const Layer& Lb = n->layers[li++];
+        HIP_TRY(lbsg::up2_concat(d, lv.e, lv.zc, B, h, w, C[l + 1], C[l], n->stream));
+        HIP_TRY(lbsg::conv3_fwd(lv.zc, La.wt, n->w + La.offB, lv.da, B, h, w, La.ci_pad, La.co, true, n->stream));
+        HIP_TRY(lbsg::conv3_fwd(lv.da, Lb.wt, n->w + Lb.offB, lv.d, B, h, w, Lb.ci_pad, Lb.co, true, n->stream));
+        d = lv.d;
+    }
+    const Layer& Lh = n->layers[li];
+    HIP_TRY(lbsg::head_fwd(d, n->w + Lh.offW, n->w + Lh.offB, xres, cres, n->out, (long long)B * H * W, C[0],
+                           n->stream));
+    n->cur_b = B;
+    n->cur_h = H;
+    n->cur_w = W;
+    return ok();
+}
+
+lbch_status backward_body(lbsg_net* n, const float* gphi) {
+    const int Lv = n->arch.levels;
+    const int* C = n->arch.chans;
+    const int B = n->cur_b, H = n->cur_h, W = n->cur_w;
+    const long long P0 = (long long)B * H * W;
+    const Layer& Lh = n->layers.back();
+    HIP_TRY(lbsg::head_bwd(gphi, n->lv[0].d, n->w + Lh.offW, n->lv[0].gd, P0, C[0], 256, n->cpart, n->g + Lh.offW,
+                           n->stream));
+    // decoder layers sit after the 2*Lv encoder layers, dec{Lv-2} first
+    auto dec_layer = [&](int l, int ab) -> const Layer& { return n->layers[2 * Lv + 2 * (Lv - 2 - l) + ab]; };
+    const __bf16* gcur = n->lv[0].gd;
+    for (int l = 0; l <= Lv - 2; ++l) {
+        const int h = H >> l, w = W >> l;
+        Level& lv = n->lv[l];
+        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w);
+        if (st != LBCH_OK) return st;
+        st = conv_back(n, dec_layer(l, 0), lv.zc, lv.da, lv.gda, lv.gzc, B, h, w);
+        if (st != LBCH_OK) return st;
+        __bf16* du = (l + 1 < Lv - 1) ? n->lv[l + 1].gd : n->lv[Lv - 1].ge;
+        HIP_TRY(lbsg::up2_concat_bwd(lv.gzc, du, lv.ge, B, h, w, C[l + 1], C[l], false, n->stream));
+        gcur = du;
+    }
+    for (int l = Lv - 1; l >= 0; --l) {
+        const int h = H >> l, w = W >> l;
+        Level& lv = n->lv[l];
+        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.e, lv.ge, lv.ga, B, h, w);
+        if (st != LBCH_OK) return st;
+        st = conv_back(n, n->layers[2 * l], lv.z, lv.a, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w);
+        if (st != LBCH_OK) return st;
+        if (l > 0) HIP_TRY(lbsg::avgpool2_bwd(lv.gz, n->lv[l - 1].ge, B, h * 2, w * 2, C[l - 1], true, n->stream));
+    }
+    return ok();
+}
+
+}  // namespace
+
+extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int32_t max_h, int32_t max_w,
+                                   int32_t train, uint64_t seed, void* hip_stream, lbsg_net** out) {
+    if (!arch || !out) return fail(LBCH_E_INVALID, "NULL argument");
+    const int Lv = arch->levels;
+    if (Lv < 2 || Lv > LBSG_MAX_LEVELS) return fail(LBCH_E_INVALID, "levels %d outside 2..%d", Lv, LBSG_MAX_LEVELS);
+    for (int l = 0; l < Lv; ++l)
+        if (arch->chans[l] < 32 || arch->chans[l] % 32 || arch->chans[l] > 512)
+            return fail(LBCH_E_INVALID, "chans[%d] = %d must be a multiple of 32 in 32..512", l, arch->chans[l]);
+    if (arch->in_ch < 1 || arch->in_ch > 32) return fail(LBCH_E_INVALID, "in_ch %d outside 1..32", arch->in_ch);
+    const int unit = 16 << (Lv - 1);
+    if (max_batch < 1 || max_h < unit || max_w < unit || max_h % unit || max_w % unit)
+        return fail(LBCH_E_INVALID, "max sizes must be positive multiples of %d", unit);
+    lbsg_net* n = new (std::nothrow) lbsg_net();
+    if (!n) return fail(LBCH_E_OOM, "host allocation failed");
+    n->arch = *arch;
+    n->max_b = max_batch;
+    n->max_h = max_h;
+    n->max_w = max_w;
+    n->train = train != 0;
+    n->stream = (hipStream_t)hip_stream;
+    const int* C = arch->chans;
+    // layer table (same order as the flat parameter layout)
+    auto add = [&](int ci, int co, int k) {
+        Layer L;
+        L.ci_real = ci;
+        L.ci_pad = k == 3 ? round32(ci) : ci;
+        L.co = co;
+        L.k = k;
+        L.offW = n->nparam;
+        n->nparam += (long long)co * ci * k * k;
+        L.offB = n->nparam;
+        n->nparam += co;
+        n->layers.push_back(L);
+    };
+    int prev = arch->in_ch;
+    for (int l = 0; l < Lv; ++l) {
+        add(prev, C[l], 3);
+        add(C[l], C[l], 3);
+        prev = C[l];
+    }
+    for (int l = Lv - 2; l >= 0; --l) {
+        add(C[l + 1] + C[l], C[l], 3);
+        add(C[l], C[l], 3);
+    }
+    add(C[0], 1, 1);
+
+    Alloc A;
+    n->w = A.get<float>(n->nparam);
+    const long long P0 = (long long)max_batch * max_h * max_w;
+    size_t max_act = 0;
+    n->lv.resize(Lv);
+    for (int l = 0; l < Lv; ++l) {
+        const long long P = P0 >> (2 * l);
+        Level& lv = n->lv[l];
+        const int cz = l == 0 ? 32 : C[l - 1];
+        lv.z = A.get<__bf16>(P * cz);
+        lv.a = A.get<__bf16>(P * C[l]);
+        lv.e = A.get<__bf16>(P * C[l]);
+        if (l < Lv - 1) {
+            lv.zc = A.get<__bf16>(P * (C[l + 1] + C[l]));
+            lv.da = A.get<__bf16>(P * C[l]);
+            lv.d = A.get<__bf16>(P * C[l]);
+        }
+        if (n->train) {
+            if (l > 0) lv.gz = A.get<__bf16>(P * cz);
+            lv.ga = A.get<__bf16>(P * C[l]);
+            lv.ge = A.get<__bf16>(P * C[l]);
+            if (l < Lv - 1) {
+                lv.gzc = A.get<__bf16>(P * (C[l + 1] + C[l]));
+                lv.gda = A.get<__bf16>(P * C[l]);
+                lv.gd = A.get<__bf16>(P * C[l]);
+            }
+        }
+        max_act = std::max(max_act, (size_t)(P * C[l]));
+    }
+    for (Layer& L : n->layers) {
+        if (L.k != 3) continue;
+        L.wt = A.get<__bf16>((size_t)L.co * 9 * L.ci_pad);
+        if (n->train && &L != &n->layers[0]) L.wf = A.get<__bf16>((size_t)L.co * 9 * L.ci_pad);
+    }
+    n->out = A.get<float>(P0);
+    n->xin1 = A.get<float>(P0);
+    n->cond = A.get<float>(32);
+    n->cpart = A.get<float>(256 * 513);
+    if (n->train) {
+        n->g = A.get<float>(n->nparam);
+        n->m = A.get<float>(n->nparam);
+        n->v = A.get<float>(n->nparam);
+        n->gtmp = A.get<__bf16>(max_act);
+        n->gout = A.get<float>(P0);
+        long long wp = 0;
+        for (const Layer& L : n->layers)
+            if (L.k == 3) wp = std::max(wp, 1024LL * L.co * 9 * L.ci_pad / std::max(1, (L.co % 64 == 0 ? L.co / 64 : L.co / 32) * (L.ci_pad / 16)));
+        n->wpart_elems = wp;
+        n->wpart = A.get<float>(wp);
+        n->dpart = A.get<double>(256);
+        n->dloss = A.get<double>(1);
+    }
+    if (A.err != hipSuccess) {
+        for (void* p : A.ptrs) (void)hipFree(p);
+        delete n;
+        (void)hipGetLastError();
+        return fail(A.err == hipErrorOutOfMemory ? LBCH_E_OOM : LBCH_E_DEVICE, "surrogate allocation failed: %s",
+                    hipGetErrorString(A.err));
+    }
+    n->allocs = A.ptrs;
+    // He-normal initialisation on the host (deterministic from seed)
+    std::vector<float> host(n->nparam);
+    std::mt19937_64 rng(seed);
+    for (const Layer& L : n->layers) {
+        std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (float)(L.ci_real * L.k * L.k)));
+        for (long long i = 0; i < (long long)L.co * L.ci_real * L.k * L.k; ++i) host[L.offW + i] = nd(rng);
+        for (int c = 0; c < L.co; ++c) host[L.offB + c] = 0.f;
+    }
+    // the head starts at zero: the untrained net is the identity map on phi
+    for (int c = 0; c < C[0] + 1; ++c) host[n->layers.back().offW + c] = 0.f;
+    lbch_status st = lbsg_set_params(n, host.data(), n->nparam);
+    if (st != LBCH_OK) {
+        lbsg_destroy(n);
+        return st;
+    }
+    if (n->train) {
+        HIP_TRY(hipMemset(n->m, 0, n->nparam * sizeof(float)));
+        HIP_TRY(hipMemset(n->v, 0, n->nparam * sizeof(float)));
+        HIP_TRY(hipMemset(n->g, 0, n->nparam * sizeof(float)));
+    }
+    *out = n;
+    return ok();
+}
+
+extern "C" lbch_status lbsg_destroy(lbsg_net* n) {
+    if (!n) return ok();
+    (void)hipStreamSynchronize(n->stream);
+    release(n);
+    delete n;
+    return ok();
+}
+
+extern "C" lbch_status lbsg_param_count(const lbsg_net* n, int64_t* count) {
+    if (!n || !count) return fail(LBCH_E_INVALID, "NULL argument");
+    *count = n->nparam;
+    return ok();
+}
+
+extern "C" lbch_status lbsg_get_params(lbsg_net* n, float* host, int64_t count) {
+    if (!n || !host) return fail(LBCH_E_INVALID, "NULL argument");
+    if (count != n->nparam) return fail(LBCH_E_INVALID, "count %lld != %lld parameters", (long long)count, n->nparam);
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    HIP_TRY(hipMemcpy(host, n->w, count * sizeof(float), hipMemcpyDeviceToHost));
+    return ok();
+}
+
+extern "C" lbch_status lbsg_set_params(lbsg_net* n, const float* host, int64_t count) {
+    if (!n || !host) return fail(LBCH_E_INVALID, "NULL argument");
+    if (count != n->nparam) return fail(LBCH_E_INVALID, "count %lld != %lld parameters", (long long)count, n->nparam);
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(host[i])) return fail(LBCH_E_INVALID, "parameter %lld is not finite", (long long)i);
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    HIP_TRY(hipMemcpy(n->w, host, count * sizeof(float), hipMemcpyHostToDevice));
+    lbch_status st = repack(n);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(hipStreamSynchronize(n->stream));
+    n->adam_t = 0;
+    return ok();
+}
+
+extern "C" lbch_status lbsg_forward(lbsg_net* n, const float* x, int32_t B, int32_t H, int32_t W, float* phi_out) {
+    if (!n || !x || !phi_out) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = check_shape(n, B, H, W);
+    if (st != LBCH_OK) return st;
+    const long long P0 = (long long)B * H * W;
+    HIP_TRY(lbsg::pack_input(x, n->lv[0].z, P0, n->arch.in_ch, 32, n->stream));
+    st = forward_body(n, B, H, W, x, n->arch.in_ch);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(hipMemcpyAsync(phi_out, n->out, P0 * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    return ok();
+}
+
+extern "C" lbch_status lbsg_backward(lbsg_net* n, const float* dphi, float* grads) {
+    if (!n || !dphi) return fail(LBCH_E_INVALID, "NULL argument");
+    if (!n->train) return fail(LBCH_E_STATE, "network was created without training buffers");
+    if (n->cur_b == 0) return fail(LBCH_E_STATE, "backward before forward");
+    lbch_status st = backward_body(n, dphi);
+    if (st != LBCH_OK) return st;
+    if (grads) HIP_TRY(hipMemcpyAsync(grads, n->g, n->nparam * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    return ok();
+}
+
+extern "C" lbch_status lbsg_train_step(lbsg_net* n, const float* x, const float* target, int32_t B, int32_t H,
+                                       int32_t W, int32_t margin, float lr, double* loss_out) {
+    if (!n || !x || !target) return fail(LBCH_E_INVALID, "NULL argument");
+    if (!n->train) return fail(LBCH_E_STATE, "network was created without training buffers");
+    lbch_status st = check_shape(n, B, H, W);
+    if (st != LBCH_OK) return st;
+    if (margin < 0 || 2 * margin >= H || 2 * margin >= W) return fail(LBCH_E_INVALID, "margin %d too large", margin);
+    if (!(lr > 0) || !std::isfinite(lr)) return fail(LBCH_E_INVALID, "lr must be positive");
+    const long long P0 = (long long)B * H * W;
+    HIP_TRY(lbsg::pack_input(x, n->lv[0].z, P0, n->arch.in_ch, 32, n->stream));
+    st = forward_body(n, B, H, W, x, n->arch.in_ch);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(lbsg::mse(n->out, target, n->gout, B, H, W, margin, n->dpart, n->dloss, n->stream));
+    st = backward_body(n, n->gout);
+    if (st != LBCH_OK) return st;
+    n->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
+    HIP_TRY(lbsg::adam(n->w, n->g, n->m, n->v, n->nparam, lr, b1, b2, 1e-8f, 0.f, c1, c2, n->stream));
+    st = repack(n);
+    if (st != LBCH_OK) return st;
+    if (loss_out) {
+        HIP_TRY(hipMemcpyAsync(loss_out, n->dloss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        HIP_TRY(hipStreamSynchronize(n->stream));
+    }
+    return ok();
+}
+
+extern "C" lbch_status lbsg_predict(lbsg_net* n, const float* phi, const float* cond, int32_t ncond, int32_t H,
+                                    int32_t W, float* phi_out) {
+    if (!n || !phi || !phi_out || (ncond > 0 && !cond)) return fail(LBCH_E_INVALID, "NULL argument");
+    if (ncond != n->arch.in_ch - 1) return fail(LBCH_E_INVALID, "ncond %d != in_ch - 1 = %d", ncond, n->arch.in_ch - 1);
+    lbch_status st = check_shape(n, 1, H, W);
+    if (st != LBCH_OK) return st;
+    if (ncond > 0) HIP_TRY(hipMemcpyAsync(n->cond, cond, ncond * sizeof(float), hipMemcpyHostToDevice, n->stream));
+    const long long P0 = (long long)H * W;
+    HIP_TRY(lbsg::pack_phi_cond(phi, n->cond, ncond, n->lv[0].z, n->xin1, P0, 32, n->stream));
+    st = forward_body(n, 1, H, W, n->xin1, 1);
+    if (st != LBCH_OK) return st;
+    HIP_TRY(hipMemcpyAsync(phi_out, n->out, P0 * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    HIP_TRY(hipStreamSynchronize(n->stream));     // cond is a host array the copy reads
+    return ok();
+}
+
+// ------------------------------------------------------- operator checks
+namespace {
+
+struct Scratch {
+    std::vector<void*> p;
+    ~Scratch() {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    T* get(size_t n) {
+        void* q = nullptr;
+        if (hipMalloc(&q, n * sizeof(T) + 16) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return (T*)q;
+    }
+};
+
+lbch_status diag_shape(int n, int h, int wd, int ci, int co) {
+    if (n < 1 || h < 16 || wd < 16 || h % 16 || wd % 16 || ci < 32 || co < 32 || ci % 32 || co % 32)
+        return fail(LBCH_E_INVALID, "operator check needs H, W multiples of 16 and Ci, Co multiples of 32");
+    return LBCH_OK;
+}
+
+}  // namespace
+
+extern "C" lbch_status lbsg_diag_conv3(const float* x, const float* w, const float* bias, float* y, int32_t n,
+                                       int32_t h, int32_t wd, int32_t ci, int32_t co, int32_t relu) {
+    if (!x || !w || !y) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    __bf16* xb = S.get<__bf16>(P * ci);
+    __bf16* wt = S.get<__bf16>((size_t)co * 9 * ci);
+    __bf16* yb = S.get<__bf16>(P * co);
+    if (!xb || !wt || !yb) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
+    HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
+    HIP_TRY(lbsg::conv3_fwd(xb, wt, bias, yb, n, h, wd, ci, co, relu != 0, nullptr));
+    HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, float* dx, int32_t n, int32_t h,
+                                             int32_t wd, int32_t ci, int32_t co) {
+    if (!dy || !w || !dx) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    __bf16* gb = S.get<__bf16>(P * co);
+    __bf16* wf = S.get<__bf16>((size_t)co * 9 * ci);
+    __bf16* xb = S.get<__bf16>(P * ci);
+    if (!gb || !wf || !xb) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
+    HIP_TRY(lbsg::pack_wflip(w, wf, co, ci, nullptr));
+    HIP_TRY(lbsg::conv3_fwd(gb, wf, nullptr, xb, n, h, wd, co, ci, false, nullptr));
+    HIP_TRY(lbsg::widen(xb, dx, P * ci, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, float* dw, int32_t n, int32_t h,
+                                             int32_t wd, int32_t ci, int32_t co) {
+    if (!x || !dy || !dw) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    const int ntiles = n * (h / 16) * (wd / 16);
+    const int splits = ntiles < 7 ? ntiles : 7;      // several splits, uneven tile counts per split
+    __bf16* xb = S.get<__bf16>(P * ci);
+    __bf16* gb = S.get<__bf16>(P * co);
+    float* part = S.get<float>((size_t)splits * co * 9 * ci);
+    if (!xb || !gb || !part) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
+    HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
+    HIP_TRY(lbsg::conv3_dw(xb, gb, part, splits, n, h, wd, ci, co, nullptr));
+    HIP_TRY(lbsg::wgrad_reduce(part, dw, splits, co, ci, ci, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}

@@ -1,0 +1,183 @@
+"""The BF16-MFMA surrogate against the float64 NumPy reference network: forward,
+parameter gradients (same weights, same inputs), and that training lowers the loss."""
+import numpy as np
+import pytest
+
+from oracle import unet
+
+pytestmark = pytest.mark.gpu
+
+
+def flat_to_dict(flat, levels, chans, c_in):
+    d, off = {}, 0
+    for name, ci, co, k in unet.layer_shapes(levels, chans, c_in):
+        n = co * ci * k * k
+        d[name + ".W"] = flat[off:off + n].reshape(co, ci, k, k).astype(np.float64)
+        off += n
+        d[name + ".b"] = flat[off:off + co].astype(np.float64)
+        off += co
+    assert off == flat.size
+    return d
+
+
+def dict_to_flat(d, levels, chans, c_in):
+    parts = []
+    for name, ci, co, k in unet.layer_shapes(levels, chans, c_in):
+        parts += [d[name + ".W"].reshape(-1), d[name + ".b"].reshape(-1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def bf16_round(a):
+    import torch
+    return torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def run_both(levels, chans, hw, bias_shift, seed):
+    import torch
+    from paper_2501_03759_amd import lbsg
+    c_in, B = 5, 2
+    rng = np.random.default_rng(seed)
+    net = lbsg.Surrogate(chans, c_in, B, hw, hw, train=True, seed=1)
+    params = unet.init_params(levels, chans, c_in, seed=seed)
+    params["head.W"] *= 0.5
+    for k in params:
+        if k.endswith(".b") and not k.startswith("head"):
+            params[k] = params[k] + bias_shift
+        params[k] = bf16_round(params[k])
+    net.set_params(dict_to_flat(params, levels, chans, c_in))
+    x = bf16_round(rng.normal(size=(B, hw, hw, c_in)) * 0.5)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    out = torch.empty((B, hw, hw), dtype=torch.float32, device="cuda")
+    net.forward(xt.data_ptr(), B, hw, hw, out.data_ptr())
+    torch.cuda.synchronize()
+    pred_ref, cache = unet.forward(params, x, levels, chans)
+    got = out.cpu().numpy().astype(np.float64)
+    dphi = rng.normal(size=(B, hw, hw))
+    dt = torch.tensor(dphi, dtype=torch.float32, device="cuda")
+    grads = torch.empty(net.nparam, dtype=torch.float32, device="cuda")
+    net.backward(dt.data_ptr(), grads.data_ptr())
+    torch.cuda.synchronize()
+    g_gpu = flat_to_dict(grads.cpu().numpy(), levels, chans, c_in)
+    g_ref, _ = unet.backward(params, cache, dphi, levels, chans)
+    return got - x[..., 0], pred_ref - x[..., 0], g_gpu, g_ref
+
+
+OPS = [(2, 32, 48, 32, 64), (1, 16, 16, 96, 32), (3, 48, 32, 64, 128)]
+
+
+def diag():
+    from paper_2501_03759_amd import lbch
+    L = lbch.lib()
+    import ctypes
+    for name, nargs in (("lbsg_diag_conv3", 10), ("lbsg_diag_conv3_dgrad", 8), ("lbsg_diag_conv3_wgrad", 8)):
+        fn = getattr(L, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_void_p] * (4 if name == "lbsg_diag_conv3" else 3) + [ctypes.c_int32] * (
+            nargs - (4 if name == "lbsg_diag_conv3" else 3))
+    return L
+
+
+@pytest.mark.parametrize("n,h,w,ci,co", OPS)
+def test_mfma_conv_forward_exact_on_bf16_inputs(n, h, w, ci, co):
+    import torch
+    L = diag()
+    rng = np.random.default_rng(ci + co)
+    x = bf16_round(rng.normal(size=(n, h, w, ci)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
+    b = rng.normal(size=co)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    wt = torch.tensor(W, dtype=torch.float32, device="cuda")
+    bt = torch.tensor(b, dtype=torch.float32, device="cuda")
+    yt = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    for relu in (0, 1):
+        assert L.lbsg_diag_conv3(xt.data_ptr(), wt.data_ptr(), bt.data_ptr(), yt.data_ptr(), n, h, w, ci, co, relu) == 0
+        ref = unet.conv3(x, W, b.astype(np.float32).astype(np.float64))
+        if relu:
+            ref = np.maximum(ref, 0)
+        got = yt.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,h,w,ci,co", OPS)
+def test_mfma_conv_gradients_exact_on_bf16_inputs(n, h, w, ci, co):
+    import torch
+    L = diag()
+    rng = np.random.default_rng(3 * ci + co)
+    x = bf16_round(rng.normal(size=(n, h, w, ci)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
+    dy = bf16_round(rng.normal(size=(n, h, w, co)))
+    dx_ref, dw_ref, _ = unet.conv3_backward(x, W, dy)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    wt = torch.tensor(W, dtype=torch.float32, device="cuda")
+    gt = torch.tensor(dy, dtype=torch.float32, device="cuda")
+    dxt = torch.empty((n, h, w, ci), dtype=torch.float32, device="cuda")
+    dwt = torch.empty((co, ci, 3, 3), dtype=torch.float32, device="cuda")
+    assert L.lbsg_diag_conv3_dgrad(gt.data_ptr(), wt.data_ptr(), dxt.data_ptr(), n, h, w, ci, co) == 0
+    assert L.lbsg_diag_conv3_wgrad(xt.data_ptr(), gt.data_ptr(), dwt.data_ptr(), n, h, w, ci, co) == 0
+    dx = dxt.cpu().numpy().astype(np.float64)
+    dw = dwt.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(dx - dx_ref) <= 2.0 ** -8 * np.abs(dx_ref) + 1e-5 * np.abs(dx_ref).max())
+    assert np.abs(dw - dw_ref).max() <= 1e-5 * np.abs(dw_ref).max()
+
+
+def test_forward_and_gradients_default_init():
+    # Whole-network composition (pool / upsample / concat adjoints, layer order) against the
+    # float64 reference.  Each operator is exact on BF16 inputs (tests above); here BF16
+    # rounding of activations and gradients flips ReLU masks of near-zero pre-activations and
+    # the differences compound layer by layer in the backward pass, so the bound is on the
+    # typical output channel and on the whole tensor.  A composition mistake (a wrong channel
+    # offset, a missing adjoint) gives O(1) errors.
+    y_gpu, y_ref, g_gpu, g_ref = run_both(2, (32, 64), 32, bias_shift=0.0, seed=2)
+    assert rel(y_gpu, y_ref) < 3e-2
+    for name in g_ref:
+        if name.startswith("head"):
+            assert rel(g_gpu[name], g_ref[name]) < 2e-2
+            continue
+        a, b = g_gpu[name], g_ref[name]
+        per_co = [rel(a[c], b[c]) for c in range(b.shape[0])]
+        assert np.median(per_co) < 0.1 and rel(a, b) < 0.25, (name, np.median(per_co), rel(a, b))
+
+
+def test_untrained_net_is_identity_and_training_lowers_loss():
+    import torch
+    from paper_2501_03759_amd import lbsg
+    chans, c_in, B, hw = (32, 64), 3, 4, 32
+    net = lbsg.Surrogate(chans, c_in, B, hw, hw, train=True, seed=3)
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=(B, hw, hw, c_in)).astype(np.float32)
+    # target: a fixed smooth map of the input (a learnable residual)
+    target = x[..., 0] + 0.3 * np.roll(x[..., 0], 1, axis=1) - 0.2 * x[..., 1]
+    xt = torch.tensor(x, device="cuda")
+    tt = torch.tensor(target.astype(np.float32), device="cuda")
+    out = torch.empty((B, hw, hw), dtype=torch.float32, device="cuda")
+    net.forward(xt.data_ptr(), B, hw, hw, out.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), x[..., 0])
+    losses = [net.train_step(xt.data_ptr(), tt.data_ptr(), B, hw, hw, 2, 2e-3) for _ in range(60)]
+    assert losses[-1] < 0.3 * losses[0], losses[::10]
+
+
+def test_predict_matches_forward_with_constant_planes():
+    import torch
+    from paper_2501_03759_amd import lbsg
+    chans, c_in, hw = (32, 64), 4, 64
+    net = lbsg.Surrogate(chans, c_in, 1, hw, hw, train=False, seed=4)
+    params = net.get_params()
+    rng = np.random.default_rng(2)
+    params[-(chans[0] + 1):] = rng.normal(size=chans[0] + 1).astype(np.float32) * 0.1
+    net.set_params(params)
+    phi = rng.normal(size=(hw, hw)).astype(np.float32)
+    cond = [0.2, -0.5, 0.75]
+    x = np.concatenate([phi[..., None], np.broadcast_to(np.array(cond, np.float32), (hw, hw, 3))], axis=2)[None]
+    xt = torch.tensor(np.ascontiguousarray(x), device="cuda")
+    a = torch.empty((1, hw, hw), dtype=torch.float32, device="cuda")
+    b = torch.empty((hw, hw), dtype=torch.float32, device="cuda")
+    net.forward(xt.data_ptr(), 1, hw, hw, a.data_ptr())
+    pt = torch.tensor(phi, device="cuda")
+    net.predict(pt.data_ptr(), cond, hw, hw, b.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy()[0], b.cpu().numpy())
