@@ -7,7 +7,7 @@
  *   encoder  e_0 = B(x),  e_l = B(avgpool2(e_{l-1}))
  *   decoder  d_{L-1} = e_{L-1},  d_l = B(concat(up2(d_{l+1}), e_l))
  *   B(z)     = relu(conv3(relu(conv3(z)+b))+b); conv3 pads periodically
- *   output   phi_pred = x[..., 0] + conv1(d_0) + b      (residual on phi)
+ *   output   phi_pred = x[..., 0] + s (conv1(d_0) + b)  (residual on phi, fixed scale s)
  * Parameters, flat FP32 in this layer order: enc0a, enc0b, ..., enc{L-1}b,
  * dec{L-2}a, dec{L-2}b, ..., dec0a, dec0b, head; each layer W[co][ci][k][k]
  * followed by b[co].
@@ -33,6 +33,7 @@ typedef struct lbsg_arch {
     int32_t levels;                  /* 2 .. LBSG_MAX_LEVELS */
     int32_t chans[LBSG_MAX_LEVELS];  /* each a multiple of 32, <= 512 */
     int32_t in_ch;                   /* 1 .. 32 input planes (phi first) */
+    float out_scale;                 /* s > 0 (0 is read as 1): the size of the residual the head is scaled to */
 } lbsg_arch;
 
 typedef struct lbsg_net lbsg_net;
@@ -68,6 +69,16 @@ lbch_status lbsg_train_step(lbsg_net* net, const float* x_dev, const float* targ
  * phi_out_dev [h][w].  Stream-ordered. */
 lbch_status lbsg_predict(lbsg_net* net, const float* phi_dev, const float* cond, int32_t ncond, int32_t h, int32_t w,
                          float* phi_out_dev);
+
+/* Training samples cut from a periodic field_dev [h][w] (FP32, device):
+ * crop q (q < k) of side `crop` starts at row yx[2q], column yx[2q+1]
+ * (host array, wrapped periodically).  x_dev (nullable) receives
+ * [k][crop][crop][1 + ncond]: phi then the sample's conditioning values
+ * cond[q*ncond .. q*ncond + ncond - 1] (host array); y_dev (nullable)
+ * receives [k][crop][crop] phi.  Stream-ordered (host arrays are copied
+ * before return). */
+lbch_status lbsg_gather(const float* field_dev, int32_t h, int32_t w, const int32_t* yx, int32_t k, int32_t crop,
+                        const float* cond, int32_t ncond, float* x_dev, float* y_dev, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ Definition (levels L, channels C_0..C_{L-1}, input channels c_in):
   decoder   d_{L-1} = e_{L-1};  d_l = block(concat(up2(d_{l+1}), e_l))  l = L-2..0
   block(z)  = relu(conv3(relu(conv3(z) + b) ) + b)  (two 3x3 convolutions)
   head      y = conv1(d_0) + b                      (one output channel)
-  output    phi_pred = x[..., 0] + y                 (residual on the phi channel)
+  output    phi_pred = x[..., 0] + s * y             (residual on the phi channel, fixed scale s)
 conv3 pads periodically (circular), stride 1; avgpool2 is the 2x2 mean; up2
 repeats each pixel 2x2; concat puts the upsampled tensor first.
 Weights of a 3x3 conv: W[co, ci, ky, kx] with tap (ky, kx) reading pixel
@@ -87,7 +87,7 @@ def init_params(levels, chans, c_in, seed=0):
     return params
 
 
-def forward(params, x, levels, chans):
+def forward(params, x, levels, chans, scale=1.0):
     """Returns (phi_pred [B,H,W], cache)."""
     cache = {}
 
@@ -113,7 +113,8 @@ def forward(params, x, levels, chans):
     y = d @ W.T + params["head.b"]
     cache["head"] = d
     cache["enc"] = enc
-    return x[..., 0] + y[..., 0], cache
+    cache["scale"] = scale
+    return x[..., 0] + scale * y[..., 0], cache
 
 
 def backward(params, cache, dphi, levels, chans):
@@ -121,7 +122,7 @@ def backward(params, cache, dphi, levels, chans):
     grads = {}
     d = cache["head"]
     W = params["head.W"][:, :, 0, 0]
-    dy = dphi[..., None]
+    dy = cache["scale"] * dphi[..., None]
     grads["head.W"] = np.einsum("nyxo,nyxi->oi", dy, d)[:, :, None, None]
     grads["head.b"] = dy.sum(axis=(0, 1, 2))
     dd = dy @ W

@@ -53,26 +53,6 @@ double s_j_of(const lbch_params* p) {
 
 }  // namespace
 
-struct lbch_sim {
-    lbch_params p{};
-    int precision = 0;
-    size_t esize = 8;
-    Grid g{};
-    Tiling t{};
-    void* f[2] = {nullptr, nullptr};
-    int cur = 0;
-    hipStream_t stream = nullptr;
-    int64_t step = 0;
-    bool initialized = false;
-    double* phi64 = nullptr;         // nx*ny float64 scratch for reductions
-    double* partials = nullptr;      // kRedBlocks * 4
-    double* result = nullptr;        // 8 doubles (device)
-    unsigned* bad = nullptr;         // non-finite counter of init_device
-    StepCoef<double> cd{};
-    StepCoef<float> cf{};
-    RedCoef rc{};
-    int user_nt = 0, user_hc = 0, user_loader = 0;
-};
 
 // ------------------------------------------------------------ host helpers
 extern "C" int32_t lbch_abi_version(void) { return LBCH_ABI_VERSION; }

@@ -487,3 +487,14 @@ extern "C" lbch_status lbch_batch_autotune(lbch_batch* b, int32_t steps_per_tria
     if (ms_per_step) *ms_per_step = best / steps_per_trial;
     return ok();
 }
+
+lbch_status lbch_batch_load_window(lbch_batch* b, int member, const lbch_sim* s, int y0, int x0) {
+    lbch_status st = check_member(b, member);
+    if (st != LBCH_OK) return st;
+    if (!s || !s->initialized) return fail(LBCH_E_STATE, "source simulation not initialised");
+    if (s->precision != b->precision) return fail(LBCH_E_INVALID, "precision mismatch");
+    HIP_TRY(launch_copy_window(b->precision, s->f[s->cur], s->g, y0, x0, member_ptr(b, b->cur, member),
+                               b->m[member].g, b->stream));
+    b->m[member].initialized = true;
+    return ok();
+}

@@ -1,0 +1,207 @@
+// Surrogate jump + lattice Boltzmann correction / rejection (include/lbch_hybrid.h).
+#include "../../include/lbch_batch.h"
+#include "../../include/lbch_hybrid.h"
+#include "lbch_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+using namespace lbch;
+
+#define HIP_TRY(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(LBCH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define ST_TRY(expr)                      \
+    do {                                  \
+        lbch_status s_ = (expr);          \
+        if (s_ != LBCH_OK) return s_;     \
+    } while (0)
+
+extern "C" lbch_status lbch_hybrid_default_opts(lbch_hybrid_opts* o) {
+    if (!o) return fail(LBCH_E_INVALID, "NULL argument");
+    std::memset(o, 0, sizeof *o);
+    o->jump = 200;
+    o->correct_steps = 10;
+    o->tol_energy = 1e-6;
+    o->windows = 4;
+    o->window_interior = 192;
+    o->window_margin = 64;
+    o->tol_window = 1e-2;
+    o->check_every = 1;
+    o->seed = 1;
+    o->ncond = 0;
+    return LBCH_OK;
+}
+
+namespace {
+
+struct Buffers {
+    std::vector<void*> p;
+    ~Buffers() {
+        for (void* q : p) (void)hipFree(q);
+    }
+    hipError_t get(void** out, size_t bytes) {
+        hipError_t e = hipMalloc(out, bytes);
+        if (e == hipSuccess) p.push_back(*out);
+        return e;
+    }
+};
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    void start() { (void)hipEventRecord(a, s); }
+    double stop() {
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+};
+
+}  // namespace
+
+extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const lbch_hybrid_opts* o, int64_t nsteps,
+                                           lbch_hybrid_stats* stats) {
+    if (!sim || !o || (!net && !o->dry_run)) return fail(LBCH_E_INVALID, "NULL argument");
+    if (!sim->initialized) return fail(LBCH_E_STATE, "simulation not initialised");
+    if (o->jump < 1 || o->correct_steps < 0 || !(o->tol_energy >= 0) || o->windows < 0 || o->window_interior < 1 ||
+        o->window_margin < 0 || !(o->tol_window > 0) || o->check_every < 1 || o->ncond < 0 || o->ncond > 8 ||
+        nsteps < 0)
+        return fail(LBCH_E_INVALID, "invalid hybrid options");
+    const int nx = sim->g.nx, ny = sim->g.ny;
+    const long long N = (long long)nx * ny;
+    const int side = o->window_interior + 2 * o->window_margin;
+    if (o->windows > 0 && (side > nx || side > ny)) return fail(LBCH_E_INVALID, "window larger than the grid");
+    hipStream_t s = sim->stream;
+    lbch_hybrid_stats st{};
+    Buffers B;
+    void *snap = nullptr, *phi = nullptr, *phin = nullptr, *dsum = nullptr, *part = nullptr, *wphi = nullptr;
+    const size_t fbytes = (size_t)sim->g.plane * 9 * sim->esize;
+    HIP_TRY(B.get(&snap, fbytes));
+    HIP_TRY(B.get(&phi, N * sizeof(float)));
+    HIP_TRY(B.get(&phin, N * sizeof(float)));
+    HIP_TRY(B.get(&dsum, 8 * sizeof(double)));
+    HIP_TRY(B.get(&part, (size_t)kRedBlocks * 4 * sizeof(double)));
+    lbch_batch* win = nullptr;
+    if (o->windows > 0) {
+        HIP_TRY(B.get(&wphi, (size_t)side * side * sizeof(float)));
+        std::vector<lbch_params> mp(o->windows, sim->p);
+        for (auto& q : mp) q.nx = q.ny = side;
+        ST_TRY(lbch_batch_create(mp.data(), o->windows, s, &win));
+    }
+    struct BatchGuard {
+        lbch_batch* b;
+        ~BatchGuard() {
+            if (b) lbch_batch_destroy(b);
+        }
+    } guard{win};
+    std::mt19937_64 rng(o->seed);
+    Timer tm(s);
+    const int64_t cyc = (int64_t)o->jump + o->correct_steps;
+    int64_t left = nsteps;
+    double E0 = 0.0, E1 = 0.0;
+    while (left >= cyc) {
+        st.cycles += 1;
+        lbch_status est = lbch_free_energy(sim, &E0, nullptr);
+        if (est != LBCH_OK) return est;
+        const int64_t step0 = sim->step;
+        // snapshot, prediction, mass projection, re-initialisation
+        tm.start();
+        HIP_TRY(hipMemcpyAsync(snap, sim->f[sim->cur], fbytes, hipMemcpyDeviceToDevice, s));
+        if (!o->dry_run) {
+            ST_TRY(lbch_phi_device(sim, phi, LBCH_FP32));
+            ST_TRY(lbsg_predict(net, (const float*)phi, o->cond, o->ncond, ny, nx, (float*)phin));
+            HIP_TRY(launch_sum_f32((const float*)phi, N, (double*)part, (double*)dsum, s));
+            HIP_TRY(launch_sum_f32((const float*)phin, N, (double*)part, (double*)dsum + 1, s));
+            HIP_TRY(launch_add_f32((float*)phin, N, (const double*)dsum, (const double*)dsum + 1, 1.0 / (double)N, s));
+            ST_TRY(lbch_init_device(sim, phin, LBCH_FP32, N));
+        }
+        st.ms_surrogate += tm.stop();
+        tm.start();
+        ST_TRY(lbch_step(sim, o->dry_run ? cyc : o->correct_steps));
+        st.ms_correct += tm.stop();
+        sim->step = step0 + cyc;
+        // checks
+        tm.start();
+        bool accept = true;
+        est = lbch_free_energy(sim, &E1, nullptr);
+        if (est != LBCH_OK && est != LBCH_E_NONFINITE) return est;
+        if (est == LBCH_E_NONFINITE || !(E1 <= E0 * (1.0 + o->tol_energy))) {
+            accept = false;
+            st.rejected_energy += 1;
+        }
+        if (accept && o->windows > 0 && (st.cycles - 1) % o->check_every == 0) {
+            // shadow windows from the snapshot (swap it in temporarily as the state to read)
+            std::vector<std::pair<int, int>> pos(o->windows);
+            void* live = sim->f[sim->cur];
+            sim->f[sim->cur] = snap;
+            for (int w = 0; w < o->windows; ++w) {
+                pos[w] = {(int)(rng() % (uint64_t)ny), (int)(rng() % (uint64_t)nx)};
+                lbch_status ls = lbch_batch_load_window(win, w, sim, pos[w].first, pos[w].second);
+                if (ls != LBCH_OK) {
+                    sim->f[sim->cur] = live;
+                    return ls;
+                }
+            }
+            sim->f[sim->cur] = live;
+            ST_TRY(lbch_batch_step(win, cyc));
+            ST_TRY(lbch_phi_device(sim, phi, LBCH_FP32));
+            double worst = 0.0;
+            for (int w = 0; w < o->windows; ++w) {
+                ST_TRY(lbch_batch_phi_device(win, w, wphi, LBCH_FP32));
+                HIP_TRY(launch_window_err((const float*)wphi, side, (const float*)phi, ny, nx, pos[w].first,
+                                          pos[w].second, o->window_margin, o->window_interior, (double*)part,
+                                          (double*)dsum + 2, s));
+                double e2[2];
+                HIP_TRY(hipMemcpyAsync(e2, (double*)dsum + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                const double rel = std::sqrt(e2[0] / (e2[1] > 0 ? e2[1] : 1e-300));
+                if (rel > worst) worst = rel;
+            }
+            if (worst > st.max_window_err) st.max_window_err = worst;
+            if (worst > o->tol_window) {
+                accept = false;
+                st.rejected_window += 1;
+            }
+        }
+        st.ms_checks += tm.stop();
+        if (accept) {
+            st.accepted += 1;
+            st.last_energy = E1;
+        } else {
+            tm.start();
+            HIP_TRY(hipMemcpyAsync(sim->f[sim->cur], snap, fbytes, hipMemcpyDeviceToDevice, s));
+            sim->step = step0;
+            ST_TRY(lbch_step(sim, cyc));
+            st.plain_steps += cyc;
+            st.ms_plain += tm.stop();
+        }
+        left -= cyc;
+    }
+    if (left > 0) {
+        tm.start();
+        ST_TRY(lbch_step(sim, left));
+        st.plain_steps += left;
+        st.ms_plain += tm.stop();
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (stats) *stats = st;
+    return LBCH_OK;
+}

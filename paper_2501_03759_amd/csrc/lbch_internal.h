@@ -94,4 +94,42 @@ Tiling make_tiling(int nx, int ny, int nt, int hc);
 constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
 constexpr int kRedThreads = 256;
 
+// Hybrid-schedule helpers (lbch_kernels.hip)
+hipError_t launch_sum_f32(const float* x, long long n, double* partials, double* out, hipStream_t s);
+hipError_t launch_add_f32(float* x, long long n, const double* num, const double* den_minus, double inv_n,
+                          hipStream_t s);
+hipError_t launch_copy_window(int precision, const void* src, const Grid& sg, int y0, int x0, void* dst,
+                              const Grid& dg, hipStream_t s);
+hipError_t launch_window_err(const float* win, int side, const float* big, int ny, int nx, int y0, int x0, int margin,
+                             int interior, double* partials, double* out2, hipStream_t s);
+
 }  // namespace lbch
+
+// The simulation handle (opaque in the C ABI).
+struct lbch_sim {
+    lbch_params p{};
+    int precision = 0;
+    size_t esize = 8;
+    lbch::Grid g{};
+    lbch::Tiling t{};
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    hipStream_t stream = nullptr;
+    int64_t step = 0;
+    bool initialized = false;
+    double* phi64 = nullptr;         // nx*ny float64 scratch for reductions
+    double* partials = nullptr;      // kRedBlocks * 4
+    double* result = nullptr;        // 8 doubles (device)
+    unsigned* bad = nullptr;         // non-finite counter of init_device
+    lbch::StepCoef<double> cd{};
+    lbch::StepCoef<float> cf{};
+    lbch::RedCoef rc{};
+    int user_nt = 0, user_hc = 0, user_loader = 0;
+};
+
+// Ensemble helper used by the hybrid schedule: member `member` of batch b
+// takes the populations of the window of sim s whose corner is (y0, x0)
+// (wrapped periodically), in the internal pull layout of both.
+struct lbch_batch;
+lbch_status lbch_batch_load_window(lbch_batch* b, int member, const lbch_sim* s, int y0, int x0);
+

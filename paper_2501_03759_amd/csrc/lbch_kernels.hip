@@ -882,3 +882,90 @@ hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t 
 }
 
 }  // namespace lbch
+
+// ---------------------------------------------------------------------------
+// Helpers of the hybrid (surrogate jump + lattice Boltzmann correction) schedule.
+// ---------------------------------------------------------------------------
+namespace lbch {
+
+__global__ __launch_bounds__(kRedThreads) void sum_f32_k(const float* __restrict__ x, long long n,
+                                                         double* partials) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int kind[4] = {0, 0, 0, 0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        v[0] += (double)x[i];
+    block_reduce_store<4>(v, kind, partials + 4 * blockIdx.x);
+}
+
+// x += (num[0] - den_minus[0]) * inv_n   (exact mass projection: shift by the mean defect)
+__global__ void add_f32_k(float* __restrict__ x, long long n, const double* __restrict__ num,
+                          const double* __restrict__ den_minus, double inv_n) {
+    const float shift = (float)((num[0] - den_minus[0]) * inv_n);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] += shift;
+}
+
+// dst (a window grid) <- the 9 population planes of src at rows y0.., columns x0.. (wrapped)
+template <typename T>
+__global__ void copy_window_k(const T* __restrict__ src, const Grid sg, int y0, int x0, T* __restrict__ dst,
+                              const Grid dg) {
+    const long long n = (long long)dg.nx * dg.ny;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(idx / dg.nx), x = (int)(idx % dg.nx);
+        int ys = (y0 + y) % sg.ny, xs = (x0 + x) % sg.nx;
+        if (ys < 0) ys += sg.ny;
+        if (xs < 0) xs += sg.nx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            dst[i * dg.plane + (long long)y * dg.pitch + x] = src[i * sg.plane + (long long)ys * sg.pitch + xs];
+    }
+}
+
+// sums of (win - big)^2 and big^2 over the window interior
+__global__ __launch_bounds__(kRedThreads) void window_err_k(const float* __restrict__ win, int side,
+                                                            const float* __restrict__ big, int ny, int nx, int y0,
+                                                            int x0, int margin, int interior, double* partials) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int kind[4] = {0, 0, 0, 0};
+    const long long n = (long long)interior * interior;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i / interior) + margin, c = (int)(i % interior) + margin;
+        int yb = (y0 + r) % ny, xb = (x0 + c) % nx;
+        if (yb < 0) yb += ny;
+        if (xb < 0) xb += nx;
+        const double a = win[(long long)r * side + c], b = big[(long long)yb * nx + xb];
+        v[0] += (a - b) * (a - b);
+        v[1] += b * b;
+    }
+    block_reduce_store<4>(v, kind, partials + 4 * blockIdx.x);
+}
+
+hipError_t launch_sum_f32(const float* x, long long n, double* partials, double* out, hipStream_t s) {
+    sum_f32_k<<<kRedBlocks, kRedThreads, 0, s>>>(x, n, partials);
+    const int kinds[4] = {0, 0, 0, 0};
+    return launch_finalize(partials, kRedBlocks, 4, kinds, out, s);
+}
+
+hipError_t launch_add_f32(float* x, long long n, const double* num, const double* den_minus, double inv_n,
+                          hipStream_t s) {
+    add_f32_k<<<elementwise_blocks(n), 256, 0, s>>>(x, n, num, den_minus, inv_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_window(int precision, const void* src, const Grid& sg, int y0, int x0, void* dst,
+                              const Grid& dg, hipStream_t s) {
+    const int nb = elementwise_blocks((long long)dg.nx * dg.ny);
+    if (precision == 0) copy_window_k<double><<<nb, 256, 0, s>>>((const double*)src, sg, y0, x0, (double*)dst, dg);
+    else copy_window_k<float><<<nb, 256, 0, s>>>((const float*)src, sg, y0, x0, (float*)dst, dg);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_err(const float* win, int side, const float* big, int ny, int nx, int y0, int x0, int margin,
+                             int interior, double* partials, double* out2, hipStream_t s) {
+    window_err_k<<<kRedBlocks, kRedThreads, 0, s>>>(win, side, big, ny, nx, y0, x0, margin, interior, partials);
+    const int kinds[4] = {0, 0, 0, 0};
+    return launch_finalize(partials, kRedBlocks, 4, kinds, out2, s);
+}
+
+}  // namespace lbch

@@ -12,6 +12,8 @@ hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N
                     hipStream_t s);
 hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s);
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s);
+hipError_t gather(const float* field, int H, int W, const int* yx, int k, int crop, const float* cond, int ncond,
+                  float* x, float* y, hipStream_t s);
 hipError_t widen(const __bf16* a, float* b, long long n, hipStream_t s);
 hipError_t pack_w(const float* W, __bf16* Wt, int Co, int Ci, int Cip, hipStream_t s);
 hipError_t pack_wflip(const float* W, __bf16* Wf, int Co, int Ci, hipStream_t s);
@@ -26,9 +28,9 @@ hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int 
                           bool accumulate, hipStream_t s);
 hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s);
 hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
-                    long long P, int C, hipStream_t s);
-hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float* part,
-                    float* grad_wb, hipStream_t s);
+                    long long P, int C, float scale, hipStream_t s);
+hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float scale,
+                    float* part, float* grad_wb, hipStream_t s);
 hipError_t mse(const float* pred, const float* target, float* g, int N, int H, int Wd, int margin, double* part,
                double* out, hipStream_t s);
 hipError_t adam(float* w, const float* g, float* m, float* v, long long n, float lr, float b1, float b2, float eps,

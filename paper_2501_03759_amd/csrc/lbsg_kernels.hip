@@ -361,27 +361,29 @@ __global__ void relu_bwd_k(const __bf16* __restrict__ dy, const __bf16* __restri
         g[i] = (float)y[i] > 0.f ? dy[i] : (__bf16)0.f;
 }
 
-// head: out[p] = phi[p] + b + sum_c w[c] d[p][c]   (phi = input channel 0, fp32)
+// head: out[p] = phi[p] + scale (b + sum_c w[c] d[p][c])   (phi = input channel 0, fp32)
 __global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict__ w, const float* __restrict__ b,
-                           const float* __restrict__ xin, int cin, float* __restrict__ out, long long P, int C) {
+                           const float* __restrict__ xin, int cin, float* __restrict__ out, long long P, int C,
+                           float scale) {
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
         float acc = b[0];
         for (int c = 0; c < C; ++c) acc += w[c] * (float)d[p * C + c];
-        out[p] = xin[p * cin] + acc;
+        out[p] = xin[p * cin] + scale * acc;
     }
 }
 
-// dd[p][c] = g[p] w[c]; part[s][c] = sum_{p in split} g[p] d[p][c] (c < C), part[s][C] = sum g
+// with gs = scale g: dd[p][c] = gs[p] w[c]; part[s][c] = sum_{p in split} gs[p] d[p][c] (c < C),
+// part[s][C] = sum gs
 __global__ void head_bwd_k(const float* __restrict__ g, const __bf16* __restrict__ d, const float* __restrict__ w,
-                           __bf16* __restrict__ dd, long long P, int C, int S, float* __restrict__ part) {
+                           __bf16* __restrict__ dd, long long P, int C, int S, float scale, float* __restrict__ part) {
     const int s = blockIdx.x;
     for (long long p = s * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)S * blockDim.x)
-        for (int c = 0; c < C; ++c) dd[p * C + c] = (__bf16)(g[p] * w[c]);
+        for (int c = 0; c < C; ++c) dd[p * C + c] = (__bf16)(scale * g[p] * w[c]);
     // reductions: thread c handles column c (and C the bias)
     for (int c = threadIdx.x; c <= C; c += blockDim.x) {
         float acc = 0.f;
         for (long long p = s; p < P; p += S) acc += c < C ? g[p] * (float)d[p * C + c] : g[p];
-        part[(size_t)s * (C + 1) + c] = acc;
+        part[(size_t)s * (C + 1) + c] = scale * acc;
     }
 }
 
@@ -436,6 +438,30 @@ __global__ void adam_k(float* __restrict__ w, const float* __restrict__ g, float
     }
 }
 
+// Training samples from a periodic field: crop q of side `crop` starts at
+// (yx[2q], yx[2q+1]) and wraps.  x (nullable): [k][crop][crop][1 + ncond]
+// with phi first and the constant conditioning values of the sample
+// (cond[q * ncond + j]) after it; y (nullable): [k][crop][crop] phi only.
+__global__ void gather_k(const float* __restrict__ field, int H, int W, const int* __restrict__ yx, int k, int crop,
+                         const float* __restrict__ cond, int ncond, float* __restrict__ x, float* __restrict__ y) {
+    const long long total = (long long)k * crop * crop;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int q = (int)(i / ((long long)crop * crop));
+        const int r = (int)((i / crop) % crop), c = (int)(i % crop);
+        int yy = (yx[2 * q] + r) % H, xx = (yx[2 * q + 1] + c) % W;
+        if (yy < 0) yy += H;
+        if (xx < 0) xx += W;
+        const float v = field[(long long)yy * W + xx];
+        if (y) y[i] = v;
+        if (x) {
+            float* o = x + i * (1 + ncond);
+            o[0] = v;
+            for (int j = 0; j < ncond; ++j) o[1 + j] = cond[q * ncond + j];
+        }
+    }
+}
+
 __global__ void widen_k(const __bf16* __restrict__ a, float* __restrict__ b, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         b[i] = (float)a[i];
@@ -486,6 +512,12 @@ hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s) {
     colsum_part_k<__bf16><<<S, 256, 0, s>>>(G, P, C, S, part);
     colsum_reduce_k<<<(C + 255) / 256, 256, 0, s>>>(part, S, C, out);
+    return hipGetLastError();
+}
+
+hipError_t gather(const float* field, int H, int W, const int* yx, int k, int crop, const float* cond, int ncond,
+                  float* x, float* y, hipStream_t s) {
+    gather_k<<<grid_for((long long)k * crop * crop), 256, 0, s>>>(field, H, W, yx, k, crop, cond, ncond, x, y);
     return hipGetLastError();
 }
 
@@ -544,14 +576,14 @@ hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, h
 }
 
 hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
-                    long long P, int C, hipStream_t s) {
-    head_fwd_k<<<grid_for(P), 256, 0, s>>>(d, w, b, xin, cin, out, P, C);
+                    long long P, int C, float scale, hipStream_t s) {
+    head_fwd_k<<<grid_for(P), 256, 0, s>>>(d, w, b, xin, cin, out, P, C, scale);
     return hipGetLastError();
 }
 
-hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float* part,
-                    float* grad_wb, hipStream_t s) {
-    head_bwd_k<<<S, 256, 0, s>>>(g, d, w, dd, P, C, S, part);
+hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float scale,
+                    float* part, float* grad_wb, hipStream_t s) {
+    head_bwd_k<<<S, 256, 0, s>>>(g, d, w, dd, P, C, S, scale, part);
     colsum_reduce_k<<<1, 256, 0, s>>>(part, S, C + 1, grad_wb);
     return hipGetLastError();
 }

@@ -64,6 +64,7 @@ struct lbsg_net {
     double* dpart = nullptr;
     double* dloss = nullptr;
     int adam_t = 0;
+    float scale = 1.f;               // residual scale of the head
     // shape of the last forward
     int cur_b = 0, cur_h = 0, cur_w = 0;
     std::vector<void*> allocs;       // every device allocation of the net
@@ -160,7 +161,7 @@ lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, in
     }
     const Layer& Lh = n->layers[li];
     HIP_TRY(lbsg::head_fwd(d, n->w + Lh.offW, n->w + Lh.offB, xres, cres, n->out, (long long)B * H * W, C[0],
-                           n->stream));
+                           n->scale, n->stream));
     n->cur_b = B;
     n->cur_h = H;
     n->cur_w = W;
@@ -173,8 +174,8 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
     const int B = n->cur_b, H = n->cur_h, W = n->cur_w;
     const long long P0 = (long long)B * H * W;
     const Layer& Lh = n->layers.back();
-    HIP_TRY(lbsg::head_bwd(gphi, n->lv[0].d, n->w + Lh.offW, n->lv[0].gd, P0, C[0], 256, n->cpart, n->g + Lh.offW,
-                           n->stream));
+    HIP_TRY(lbsg::head_bwd(gphi, n->lv[0].d, n->w + Lh.offW, n->lv[0].gd, P0, C[0], 256, n->scale, n->cpart,
+                           n->g + Lh.offW, n->stream));
     // decoder layers sit after the 2*Lv encoder layers, dec{Lv-2} first
     auto dec_layer = [&](int l, int ab) -> const Layer& { return n->layers[2 * Lv + 2 * (Lv - 2 - l) + ab]; };
     const __bf16* gcur = n->lv[0].gd;
@@ -212,12 +213,15 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
         if (arch->chans[l] < 32 || arch->chans[l] % 32 || arch->chans[l] > 512)
             return fail(LBCH_E_INVALID, "chans[%d] = %d must be a multiple of 32 in 32..512", l, arch->chans[l]);
     if (arch->in_ch < 1 || arch->in_ch > 32) return fail(LBCH_E_INVALID, "in_ch %d outside 1..32", arch->in_ch);
+    if (!(arch->out_scale >= 0) || !std::isfinite(arch->out_scale))
+        return fail(LBCH_E_INVALID, "out_scale must be >= 0 (0 = 1)");
     const int unit = 16 << (Lv - 1);
     if (max_batch < 1 || max_h < unit || max_w < unit || max_h % unit || max_w % unit)
         return fail(LBCH_E_INVALID, "max sizes must be positive multiples of %d", unit);
     lbsg_net* n = new (std::nothrow) lbsg_net();
     if (!n) return fail(LBCH_E_OOM, "host allocation failed");
     n->arch = *arch;
+    n->scale = arch->out_scale > 0 ? arch->out_scale : 1.f;
     n->max_b = max_batch;
     n->max_h = max_h;
     n->max_w = max_w;
@@ -516,5 +520,21 @@ extern "C" lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, fl
     HIP_TRY(lbsg::conv3_dw(xb, gb, part, splits, n, h, wd, ci, co, nullptr));
     HIP_TRY(lbsg::wgrad_reduce(part, dw, splits, co, ci, ci, nullptr));
     HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_gather(const float* field, int32_t h, int32_t w, const int32_t* yx, int32_t k, int32_t crop,
+                                   const float* cond, int32_t ncond, float* x, float* y, void* hip_stream) {
+    if (!field || !yx || (!x && !y) || (ncond > 0 && !cond)) return fail(LBCH_E_INVALID, "NULL argument");
+    if (h < 1 || w < 1 || k < 1 || crop < 1 || ncond < 0 || ncond > 31) return fail(LBCH_E_INVALID, "bad sizes");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Scratch S;
+    int* dyx = S.get<int>(2 * (size_t)k);
+    float* dc = S.get<float>((size_t)k * (ncond > 0 ? ncond : 1));
+    if (!dyx || !dc) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(hipMemcpyAsync(dyx, yx, 2 * (size_t)k * sizeof(int), hipMemcpyHostToDevice, s));
+    if (ncond > 0) HIP_TRY(hipMemcpyAsync(dc, cond, (size_t)k * ncond * sizeof(float), hipMemcpyHostToDevice, s));
+    HIP_TRY(lbsg::gather(field, h, w, dyx, k, crop, dc, ncond, x, y, s));
+    HIP_TRY(hipStreamSynchronize(s));     // scratch is freed on return
     return LBCH_OK;
 }

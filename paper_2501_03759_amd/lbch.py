@@ -372,3 +372,49 @@ class Batch:
         v = ctypes.c_int64()
         _check(lib().lbch_batch_nodes(self._h, ctypes.byref(v)), "lbch_batch_nodes")
         return v.value
+
+
+class HybridOpts(ctypes.Structure):
+    _fields_ = [("jump", ctypes.c_int32), ("correct_steps", ctypes.c_int32), ("tol_energy", ctypes.c_double),
+                ("windows", ctypes.c_int32), ("window_interior", ctypes.c_int32), ("window_margin", ctypes.c_int32),
+                ("tol_window", ctypes.c_double), ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("ncond", ctypes.c_int32), ("cond", ctypes.c_float * 8), ("dry_run", ctypes.c_int32)]
+
+
+class HybridStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int64), ("accepted", ctypes.c_int64), ("rejected_energy", ctypes.c_int64),
+                ("rejected_window", ctypes.c_int64), ("plain_steps", ctypes.c_int64),
+                ("max_window_err", ctypes.c_double), ("last_energy", ctypes.c_double),
+                ("ms_surrogate", ctypes.c_double), ("ms_correct", ctypes.c_double), ("ms_checks", ctypes.c_double),
+                ("ms_plain", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def hybrid_opts(**kw) -> HybridOpts:
+    L = lib()
+    L.lbch_hybrid_default_opts.restype = ctypes.c_int
+    L.lbch_hybrid_default_opts.argtypes = [ctypes.POINTER(HybridOpts)]
+    o = HybridOpts()
+    _check(L.lbch_hybrid_default_opts(ctypes.byref(o)), "lbch_hybrid_default_opts")
+    cond = kw.pop("cond", None)
+    if cond is not None:
+        o.ncond = len(cond)
+        for i, v in enumerate(cond):
+            o.cond[i] = v
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def hybrid_advance(sim: Sim, net, opts: HybridOpts, nsteps: int) -> HybridStats:
+    """Surrogate-jump / lattice Boltzmann correction schedule (include/lbch_hybrid.h)."""
+    L = lib()
+    L.lbch_hybrid_advance.restype = ctypes.c_int
+    L.lbch_hybrid_advance.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(HybridOpts), ctypes.c_int64,
+                                      ctypes.POINTER(HybridStats)]
+    st = HybridStats()
+    _check(L.lbch_hybrid_advance(sim.handle, net._h if net is not None else None, ctypes.byref(opts), nsteps,
+                                 ctypes.byref(st)), "lbch_hybrid_advance")
+    return st

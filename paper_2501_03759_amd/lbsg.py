@@ -12,15 +12,17 @@ MAX_LEVELS = 6
 
 
 class Arch(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("chans", ctypes.c_int32 * MAX_LEVELS), ("in_ch", ctypes.c_int32)]
+    _fields_ = [("levels", ctypes.c_int32), ("chans", ctypes.c_int32 * MAX_LEVELS), ("in_ch", ctypes.c_int32),
+                ("out_scale", ctypes.c_float)]
 
 
-def make_arch(chans, in_ch) -> Arch:
+def make_arch(chans, in_ch, out_scale=1.0) -> Arch:
     a = Arch()
     a.levels = len(chans)
     for i, c in enumerate(chans):
         a.chans[i] = c
     a.in_ch = in_ch
+    a.out_scale = out_scale
     return a
 
 
@@ -37,6 +39,9 @@ _SIGS = {
     "lbsg_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                        ctypes.POINTER(ctypes.c_double)]),
+    "lbsg_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbsg_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
 }
@@ -58,9 +63,9 @@ def _bind():
 class Surrogate:
     """The periodic U-Net (lbsg_net). Device tensors are passed as raw pointers (e.g. torch .data_ptr())."""
 
-    def __init__(self, chans, in_ch, max_batch, max_h, max_w, train=True, seed=0, stream=None):
+    def __init__(self, chans, in_ch, max_batch, max_h, max_w, train=True, seed=0, stream=None, out_scale=1.0):
         L = _bind()
-        self.arch = make_arch(chans, in_ch)
+        self.arch = make_arch(chans, in_ch, out_scale)
         self.chans, self.in_ch = tuple(chans), in_ch
         self._h = ctypes.c_void_p()
         _check(L.lbsg_create(ctypes.byref(self.arch), max_batch, max_h, max_w, 1 if train else 0, seed,
@@ -117,3 +122,18 @@ def layer_names(levels):
     for l in range(levels - 2, -1, -1):
         names += [f"dec{l}a", f"dec{l}b"]
     return names + ["head"]
+
+
+def gather(field_ptr: int, h: int, w: int, yx: np.ndarray, crop: int, cond: np.ndarray | None,
+           x_ptr: int | None, y_ptr: int | None, stream=None):
+    """Crops of a periodic device field into training inputs / targets (lbsg_gather)."""
+    yx = np.ascontiguousarray(yx, dtype=np.int32).reshape(-1, 2)
+    k = yx.shape[0]
+    if cond is None or cond.size == 0:
+        c, nc = None, 0
+    else:
+        cond = np.ascontiguousarray(cond, dtype=np.float32).reshape(k, -1)
+        c, nc = cond.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), cond.shape[1]
+    _check(_bind().lbsg_gather(ctypes.c_void_p(field_ptr), h, w, yx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               k, crop, c, nc, ctypes.c_void_p(x_ptr) if x_ptr else None,
+                               ctypes.c_void_p(y_ptr) if y_ptr else None, _stream_handle(stream)), "lbsg_gather")

@@ -27,18 +27,18 @@ def test_pool_and_upsample_are_adjoint_up_to_scale():
     assert abs((unet.up2(y) * x).sum() - (y * unet.up2_backward(x)).sum()) < 1e-12
 
 
-@pytest.mark.parametrize("levels,chans", [(2, (4, 6)), (3, (3, 4, 5))])
-def test_gradients_match_finite_differences(levels, chans):
+@pytest.mark.parametrize("levels,chans,scale", [(2, (4, 6), 1.0), (3, (3, 4, 5), 0.3)])
+def test_gradients_match_finite_differences(levels, chans, scale):
     c_in = 3
     params = unet.init_params(levels, chans, c_in, seed=3)
     x = RNG.normal(size=(2, 8, 8, c_in))
     target = RNG.normal(size=(2, 8, 8))
 
     def loss_of(p, xx):
-        pred, _ = unet.forward(p, xx, levels, chans)
+        pred, _ = unet.forward(p, xx, levels, chans, scale)
         return unet.masked_mse(pred, target, 1)[0]
 
-    pred, cache = unet.forward(params, x, levels, chans)
+    pred, cache = unet.forward(params, x, levels, chans, scale)
     _, g = unet.masked_mse(pred, target, 1)
     grads, dx = unet.backward(params, cache, g, levels, chans)
     h = 1e-6
