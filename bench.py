@@ -4,12 +4,15 @@
 Workload: periodic 8192 x 8192 D2Q9 spinodal decomposition in FP32 (phi0 =
 U(-0.05, 0.05) from seed 5, alpha = 0.2, m = 4, Willmore eps = 0.03,
 M = 0.1, interface eps_w = 1.5 -> D = 2 sqrt(2) eps_w, sigma = 0.01).
-One "step" is one lbch_step: pull-stream + phi + all stencils + anisotropic
-chemical potential + equilibrium + source + MRT collision (one kernel).
+One "step" is one time step of lbch_step: pull-stream + phi + all stencils +
+anisotropic chemical potential + equilibrium + source + MRT collision.  By
+default one kernel launch advances two time steps (temporal blocking).
 
 Prints ONE JSON line: MLUPS (whole job), the roofline of the step kernel
 (algorithmic 72 B per lattice update in FP32 = 9 populations read + 9
-written) and the oracle's CPU throughput on a bounded sample.
+written, times the updates of one launch; the launch's own minimum traffic,
+one read and one write of the state, is reported beside it) and the
+oracle's CPU throughput on a bounded sample.
 """
 from __future__ import annotations
 
@@ -27,17 +30,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(n_nodes: int, precision: str):
+def measured_traffic(n_nodes: int, precision: str, depth: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source at this size; else None."""
-    from paper_2501_03759_amd.profiling import kernel_hash
+    the current kernel source at this size and depth; else None."""
+    from paper_2501_03759_amd.profiling import STEP_KERNELS, kernel_hash
     side = int(round(n_nodes ** 0.5))
-    path = os.path.join(ROOT, "profiles", f"step_fused_spinodal{side}_{precision}.json")
+    path = os.path.join(ROOT, "profiles", f"{STEP_KERNELS[depth]}_spinodal{side}_{precision}.json")
     try:
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("kernel_sha256_16") != kernel_hash() or rec.get("nodes") != n_nodes or rec.get("precision") != precision:
+    if (rec.get("kernel_sha256_16") != kernel_hash() or rec.get("nodes") != n_nodes
+            or rec.get("precision") != precision or rec.get("depth", 1) != depth):
         return None
     return rec.get("bytes_per_launch")
 
@@ -95,6 +99,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=8192, help="grid side (default: the 8192^2 workload)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per kernel launch")
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -118,6 +123,7 @@ def main():
     stream = torch.cuda.Stream()
     copy = copy_ceiling(torch, lbch, stream)
     sim = lbch.Sim(p, stream)
+    sim.set_time_blocking(args.depth)
     if args.tiling:
         bt, rows = (int(v) for v in args.tiling.split(","))
         sim.set_tiling(bt, rows)
@@ -142,13 +148,26 @@ def main():
 
     nodes = n * n
     mlups = nodes * args.steps / (ms_total * 1e-3) / 1e6
-    alg_bytes = 18 * esize * nodes                     # 9 populations read + 9 written per node
-    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    depth = args.depth
+    # every launch advances `depth` steps (an odd tail step, if any, is one
+    # single-step launch of about half the time: the average below counts it
+    # as half a launch)
+    launch_ms = ms_step * depth
+    bytes_per_update = 18 * esize                      # 9 populations read + 9 written
+    alg_bytes = bytes_per_update * nodes * depth       # per launch
+    min_bytes = bytes_per_update * nodes               # one read + one write of the state per launch
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(nodes, args.precision)}
+                "traffic": measured_traffic(nodes, args.precision, depth),
+                "kernel": "step2_fused" if depth == 2 else "step_fused",
+                "launch_ms": round(launch_ms, 4), "updates_per_launch": depth * nodes,
+                "bytes_per_update": bytes_per_update, "algorithmic_bytes_per_launch": alg_bytes,
+                "min_bytes_per_launch": min_bytes,
+                "min_bytes_GBs": round(min_bytes / (launch_ms * 1e-3) / 1e9, 1),
+                "min_bytes_frac": round(min_bytes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out = {
-        "metric": "MLUPS (lattice updates per second / 1e6), fused MRT-LBM step, 1 GPU",
+        "metric": "MLUPS & % HBM peak (1 GPU)",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -162,7 +181,7 @@ def main():
         "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
         "config": {"workload": f"spinodal-{n}x{n}-{args.precision}", "grid": [n, n], "lattice": "D2Q9",
                    "alpha": d["alpha"], "m": d["m"], "regularization": "willmore", "eps_reg": d["eps_reg"],
-                   "mobility": d["mobility"], "tiling": list(tiling)},
+                   "mobility": d["mobility"], "time_steps_per_launch": depth, "tiling": list(tiling)},
         "roofline": roofline,
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
         "hbm_copy": copy,

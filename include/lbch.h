@@ -207,18 +207,30 @@ lbch_status lbch_load_state(lbch_sim* sim, const void* src, int32_t src_is_devic
 
 /* Launch shape of the fused step kernel. -------------------------------------- */
 
-/* block_threads in {64, 128, 256, 512}: each workgroup owns a strip of
- * block_threads - 8 columns; rows_per_block >= 1 rows of that strip are
- * swept per workgroup.  The result is bitwise independent of the choice.
- * 0 for either argument restores the built-in default for the grid. */
+/* Time steps per kernel launch (temporal blocking): 1, or 2 (each launch
+ * reads the populations once, keeps the first step's post-collision rows on
+ * chip and writes the state two steps later; lbch_step with an odd count
+ * finishes with one single-step launch).  Results are bitwise identical for
+ * both depths.  Default 2.  Changing the depth restores the default tiling
+ * of that depth.  depth not in {1, 2} -> LBCH_E_INVALID. */
+lbch_status lbch_set_time_blocking(lbch_sim* sim, int32_t depth);
+lbch_status lbch_get_time_blocking(const lbch_sim* sim, int32_t* depth);
+
+/* Tiling of the current depth.  block_threads in {64, 128, 256, 512} at
+ * depth 1 and {128, 256, 512} at depth 2 (at most 256 in FP64): each
+ * workgroup owns a strip of block_threads - 8 * depth columns;
+ * rows_per_block >= 1 rows of that strip are swept per workgroup.  The
+ * result is bitwise independent of the choice.  0 for either argument
+ * restores the built-in default for the grid. */
 lbch_status lbch_set_tiling(lbch_sim* sim, int32_t block_threads, int32_t rows_per_block);
 lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t* rows_per_block);
 
-/* Times the step kernel over the launch shapes block_threads in {64, 128,
- * 256, 512} x rows_per_block in {8, ..., 256} (steps_per_trial launches each,
- * reading the current state and writing the idle buffer, so the state and
- * the step counter are unchanged), keeps the fastest and returns it.
- * Synchronises.  Before init -> LBCH_E_STATE. */
+/* Times the step kernel over depth in {1, 2} x block_threads x
+ * rows_per_block in {8, ..., 512} (steps_per_trial launches each, reading
+ * the current state and writing the idle buffer, so the state and the step
+ * counter are unchanged), keeps the fastest per step (depth and tiling) and
+ * returns its tiling and time per step.  Synchronises.  Before init ->
+ * LBCH_E_STATE. */
 lbch_status lbch_autotune(lbch_sim* sim, int32_t steps_per_trial, int32_t* block_threads,
                           int32_t* rows_per_block, double* ms_per_step);
 

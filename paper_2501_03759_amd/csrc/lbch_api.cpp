@@ -202,29 +202,59 @@ void fill_red(const lbch_params* p, RedCoef& r) {
     r.reg = p->regularization;
 }
 
-Tiling make_tiling(int nx, int ny, int nt, int hc) {
-    if (nt == 0) {
-        // smallest lane count over the row, ties to the larger block
-        const int cand[4] = {64, 128, 256, 512};
-        long long best = -1;
-        for (int k = 0; k < 4; ++k) {
-            const int W = cand[k] - 8;
-            const long long cost = (long long)((nx + W - 1) / W) * cand[k];
-            if (best < 0 || cost <= best) {
-                best = cost;
-                nt = cand[k];
-            }
+// Default lane count: at depth 1 the fewest lanes over the row (ties to the
+// larger block); at depth 2 the shape with the most resident waves per CU on
+// large grids (256 lanes in FP32, whose LDS rings allow 3 workgroups per CU;
+// 128 in FP64).
+static int default_nt(int nx, int depth, int esize) {
+    if (depth == 2) return (esize == 4 && nx >= 192) ? 256 : 128;
+    const int cand[4] = {64, 128, 256, 512};
+    long long best = -1;
+    int nt = 64;
+    for (int k = 0; k < 4; ++k) {
+        const int W = cand[k] - 8;
+        const long long cost = (long long)((nx + W - 1) / W) * cand[k];
+        if (best < 0 || cost <= best) {
+            best = cost;
+            nt = cand[k];
         }
     }
+    return nt;
+}
+
+// slots: workgroups resident on the whole device at once (0 = unknown).
+Tiling make_tiling(int nx, int ny, int nt, int hc, int depth, int esize, int slots) {
+    if (nt == 0) nt = default_nt(nx, depth, esize);
     Tiling t{};
     t.nt = nt;
-    t.W = nt - 8;          // multiple of 8: strips start on 32-byte boundaries
+    t.depth = depth;
+    t.W = nt - 8 * depth;  // multiple of 8: strips start on 32-byte boundaries
     t.strips = (nx + t.W - 1) / t.W;
     if (hc == 0) {
-        // short sweeps measured fastest on 8192^2 (more resident workgroups;
-        // the extra halo rows mostly hit L2): about 8 tiles per CU, >= 16 rows
-        long long want = (long long)t.strips * ny / 8192;
-        hc = (int)(want < 16 ? 16 : (want > 256 ? 256 : want));
+        if (depth == 1) {
+            // short sweeps measured fastest on 8192^2 (more resident
+            // workgroups; the extra halo rows mostly hit L2): about 8 tiles
+            // per CU, >= 16 rows
+            long long want = (long long)t.strips * ny / 8192;
+            hc = (int)(want < 16 ? 16 : (want > 256 ? 256 : want));
+        } else if (ny <= 32 || slots <= 0) {
+            long long want = (long long)t.strips * ny / 2048;
+            hc = (int)(want < 32 ? 32 : (want > 512 ? 512 : want));
+        } else {
+            // a chunk of h rows costs about (h + 14) first-step rows and
+            // (h + 7) second-step rows; the launch takes ceil(tiles / slots)
+            // rounds of the longest chunk: minimise rounds * (2h + 21)
+            long long best = -1;
+            const int hmax = ny < 512 ? ny : 512;
+            for (int h = 32; h <= hmax; ++h) {
+                const long long tiles = (long long)t.strips * ((ny + h - 1) / h);
+                const long long cost = ((tiles + slots - 1) / slots) * (2LL * h + 21);
+                if (best < 0 || cost < best) {
+                    best = cost;
+                    hc = h;
+                }
+            }
+        }
     }
     t.hc = hc < ny ? hc : ny;
     t.chunks = (ny + t.hc - 1) / t.hc;
@@ -232,6 +262,18 @@ Tiling make_tiling(int nx, int ny, int nt, int hc) {
     t.per_xcd = (t.ntiles + 7) / 8;
     t.nblocks = 8 * t.per_xcd;
     t.staged = 1;
+    return t;
+}
+
+// Tiling of the given depth for sim s (nt, hc = 0: defaults), with the
+// sim's row-loader choice and the device's resident-workgroup count.
+static Tiling sim_tiling(const lbch_sim* s, int depth, int nt, int hc) {
+    if (nt == 0) nt = default_nt(s->g.nx, depth, (int)s->esize);
+    const bool staged = s->user_loader == 0 && s->precision == LBCH_FP32 && s->g.nx % 4 == 0;
+    const bool unit = s->precision == LBCH_FP32 ? s->cf.unit != 0 : s->cd.unit != 0;
+    const int slots = s->cus * step_blocks_per_cu(s->precision, depth, nt, unit, staged);
+    Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize, slots);
+    t.staged = s->user_loader == 0;
     return t;
 }
 
@@ -295,10 +337,20 @@ extern "C" lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_
     // planes padded by 256 elements so that the nine planes do not alias in
     // the same DRAM channel at power-of-two sizes
     s->g.plane = (long long)s->g.pitch * p->ny + 256;
-    s->t = make_tiling(p->nx, p->ny, 0, 0);
     fill_coef<double>(p, s->cd);
     fill_coef<float>(p, s->cf);
     fill_red(p, s->rc);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            s->cus = cus;
+        (void)hipGetLastError();
+    }
+    // two steps per launch by default (each population crosses HBM once per
+    // two updates); single-step launches finish odd step counts
+    s->t1 = sim_tiling(s, 1, 0, 0);
+    s->t = sim_tiling(s, 2, 0, 0);
     const size_t fbytes = (size_t)s->g.plane * 9 * s->esize;
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&s->f[0], fbytes)) != hipSuccess || (e = hipMalloc(&s->f[1], fbytes)) != hipSuccess ||
@@ -360,8 +412,16 @@ extern "C" lbch_status lbch_step(lbch_sim* s, int64_t nsteps) {
     lbch_status st = check_init(s);
     if (st != LBCH_OK) return st;
     if (nsteps < 0) return fail(LBCH_E_INVALID, "nsteps = %lld < 0", (long long)nsteps);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        HIP_TRY(launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t, coef_ptr(s), s->stream));
+    int64_t k = 0;
+    if (s->t.depth == 2) {
+        for (; k + 2 <= nsteps; k += 2) {
+            HIP_TRY(launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t, coef_ptr(s), s->stream));
+            s->cur ^= 1;
+            s->step += 2;
+        }
+    }
+    for (; k < nsteps; ++k) {
+        HIP_TRY(launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t1, coef_ptr(s), s->stream));
         s->cur ^= 1;
         s->step += 1;
     }
@@ -511,17 +571,38 @@ extern "C" lbch_status lbch_load_state(lbch_sim* s, const void* src, int32_t src
 }
 
 // ---------------------------------------------------------------- tiling
+extern "C" lbch_status lbch_set_time_blocking(lbch_sim* s, int32_t depth) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (depth != 1 && depth != 2) return fail(LBCH_E_INVALID, "time-blocking depth %d not in {1, 2}", depth);
+    s->t = sim_tiling(s, depth, 0, 0);
+    if (depth == 1) s->t1 = s->t;
+    return ok();
+}
+
+extern "C" lbch_status lbch_get_time_blocking(const lbch_sim* s, int32_t* depth) {
+    lbch_status st = check_sim(s);
+    if (st != LBCH_OK) return st;
+    if (!depth) return fail(LBCH_E_INVALID, "depth pointer is NULL");
+    *depth = s->t.depth;
+    return ok();
+}
+
 extern "C" lbch_status lbch_set_tiling(lbch_sim* s, int32_t block_threads, int32_t rows_per_block) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
+    const int depth = s->t.depth;
     if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256 &&
         block_threads != 512)
         return fail(LBCH_E_INVALID, "block_threads %d not in {64, 128, 256, 512}", block_threads);
+    if (depth == 2 && (block_threads == 64 || (s->esize == 8 && block_threads == 512)))
+        return fail(LBCH_E_INVALID, "block_threads %d not available at time-blocking depth 2 in %s", block_threads,
+                    s->esize == 8 ? "FP64" : "FP32");
     if (rows_per_block < 0) return fail(LBCH_E_INVALID, "rows_per_block %d < 0", rows_per_block);
     s->user_nt = block_threads;
     s->user_hc = rows_per_block;
-    s->t = make_tiling(s->g.nx, s->g.ny, block_threads, rows_per_block);
-    s->t.staged = s->user_loader == 0;
+    s->t = sim_tiling(s, depth, block_threads, rows_per_block);
+    if (depth == 1) s->t1 = s->t;
     return ok();
 }
 
@@ -531,6 +612,7 @@ extern "C" lbch_status lbch_set_row_loader(lbch_sim* s, int32_t mode) {
     if (mode != 0 && mode != 1) return fail(LBCH_E_INVALID, "row loader mode %d not in {0, 1}", mode);
     s->user_loader = mode;
     s->t.staged = mode == 0;
+    s->t1.staged = mode == 0;
     return ok();
 }
 
@@ -560,45 +642,53 @@ extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32
     if (steps_per_trial < 1) return fail(LBCH_E_INVALID, "steps_per_trial %d < 1", steps_per_trial);
     // Trials read the current state and write the idle buffer, so the state is untouched.
     const int nts[4] = {64, 128, 256, 512};
-    const int hcs[6] = {8, 16, 32, 64, 128, 256};
+    const int hcs[7] = {8, 16, 32, 64, 128, 256, 512};
     hipEvent_t a = nullptr, b = nullptr;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
-    float best = -1.0f;
-    Tiling best_t = s->t;
-    const Tiling saved = s->t;
-    for (int nt : nts) {
-        if (nt > 128 && s->g.nx < nt / 2) continue;          // mostly idle lanes
-        for (int hc : hcs) {
-            if (hc > s->g.ny && hc != hcs[0]) continue;
-            Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc);
-            t.staged = saved.staged;
-            hipError_t e = launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
-            if (e == hipSuccess) e = hipEventRecord(a, s->stream);
-            for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k)
-                e = launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
-            if (e == hipSuccess) e = hipEventRecord(b, s->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e != hipSuccess) {
-                (void)hipEventDestroy(a);
-                (void)hipEventDestroy(b);
-                return fail(LBCH_E_DEVICE, "autotune trial failed: %s", hipGetErrorString(e));
-            }
-            if (best < 0.0f || ms < best) {
-                best = ms;
-                best_t = t;
+    float best[2] = {-1.0f, -1.0f};          // per step, per depth
+    Tiling best_t[2] = {s->t1, s->t};
+    const int staged = s->t.staged;
+    for (int depth = 1; depth <= 2; ++depth) {
+        for (int nt : nts) {
+            if (nt > 128 && s->g.nx < nt / 2) continue;          // mostly idle lanes
+            if (depth == 2 && (nt == 64 || (s->esize == 8 && nt == 512))) continue;
+            for (int hc : hcs) {
+                if (hc > s->g.ny && hc != hcs[0]) continue;
+                if (depth == 2 && hc < 32) continue;             // 14 start-up rows per chunk
+                Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize);
+                t.staged = staged;
+                hipError_t e =
+                    launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
+                if (e == hipSuccess) e = hipEventRecord(a, s->stream);
+                for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k)
+                    e = launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
+                if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                if (e != hipSuccess) {
+                    (void)hipEventDestroy(a);
+                    (void)hipEventDestroy(b);
+                    return fail(LBCH_E_DEVICE, "autotune trial failed: %s", hipGetErrorString(e));
+                }
+                ms /= (float)depth;
+                if (best[depth - 1] < 0.0f || ms < best[depth - 1]) {
+                    best[depth - 1] = ms;
+                    best_t[depth - 1] = t;
+                }
             }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    s->t = best_t;
-    s->user_nt = best_t.nt;
-    s->user_hc = best_t.hc;
-    if (block_threads) *block_threads = best_t.nt;
-    if (rows_per_block) *rows_per_block = best_t.hc;
-    if (ms_per_step) *ms_per_step = best / steps_per_trial;
+    s->t1 = best_t[0];
+    const int d = (best[1] >= 0.0f && best[1] < best[0]) ? 2 : 1;
+    s->t = best_t[d - 1];
+    s->user_nt = s->t.nt;
+    s->user_hc = s->t.hc;
+    if (block_threads) *block_threads = s->t.nt;
+    if (rows_per_block) *rows_per_block = s->t.hc;
+    if (ms_per_step) *ms_per_step = best[d - 1] / steps_per_trial;
     return ok();
 }

@@ -16,12 +16,14 @@ struct Grid {
     long long plane;      // elements between consecutive population planes
 };
 
-// Decomposition of the fused step: strips of W = NT - 8 columns, chunks of
-// `hc` rows; tiles are strip-fastest; blocks are dealt to the 8 XCDs in
-// contiguous tile ranges of `per_xcd`.
+// Decomposition of the fused step: strips of W = NT - 8 * depth columns,
+// chunks of `hc` rows; tiles are strip-fastest; blocks are dealt to the 8
+// XCDs in contiguous tile ranges of `per_xcd`.  depth = time steps per
+// launch (1 or 2).
 struct Tiling {
     int nt, W, strips, hc, chunks, ntiles, per_xcd, nblocks;
     int staged;           // FP32 row loader through LDS (used when nx % 4 == 0)
+    int depth;
 };
 
 // Per-step constants in the working precision T (lattice units folded in).
@@ -83,13 +85,15 @@ hipError_t launch_batch_step(int precision, int nt, bool unit_all, const void* f
                              hipStream_t s);
 // resident workgroups per CU of the batch kernel (for sizing its persistent grid)
 int batch_blocks_per_cu(int precision, int nt, bool unit_all);
+// resident workgroups per CU of the step kernel of the given depth and shape
+int step_blocks_per_cu(int precision, int depth, int nt, bool unit, bool staged);
 
 // Host helpers shared by the C-ABI files (lbch_api.cpp).
 lbch_status fail(lbch_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 template <typename T>
 void fill_coef(const lbch_params* p, StepCoef<T>& c);
 void fill_red(const lbch_params* p, RedCoef& r);
-Tiling make_tiling(int nx, int ny, int nt, int hc);
+Tiling make_tiling(int nx, int ny, int nt, int hc, int depth = 1, int esize = 4, int slots = 0);
 
 constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
 constexpr int kRedThreads = 256;
@@ -111,7 +115,8 @@ struct lbch_sim {
     int precision = 0;
     size_t esize = 8;
     lbch::Grid g{};
-    lbch::Tiling t{};
+    lbch::Tiling t{};                // tiling of the active depth
+    lbch::Tiling t1{};               // depth-1 tiling (odd remainders of lbch_step)
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     hipStream_t stream = nullptr;
@@ -125,6 +130,7 @@ struct lbch_sim {
     lbch::StepCoef<float> cf{};
     lbch::RedCoef rc{};
     int user_nt = 0, user_hc = 0, user_loader = 0;
+    int cus = 256;                   // compute units of the device
 };
 
 // Ensemble helper used by the hybrid schedule: member `member` of batch b

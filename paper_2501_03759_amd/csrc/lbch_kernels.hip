@@ -134,7 +134,7 @@ __device__ __forceinline__ void collide_unit(T phi, T jx, T jy, T mua, T gx, T g
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Fused step.  Workgroup = strip of W = NT - 6 output columns x hc output rows.
+// Fused step.  Workgroup = strip of W = NT - 8 output columns x hc output rows.
 // Lane t owns column x0 - 3 + t (wrapped) for the whole sweep.  Each loop
 // iteration j brings in one new row r = y0 - 3 + j and runs four stages
 // that lag behind it:
@@ -175,13 +175,14 @@ struct RowLoader<T, NT, false> {
     using Buf = T[9];
     const T* P[9];
     int xc, cm, cp, nx, ny, pitch;
-    __device__ __forceinline__ void setup(const T* fin, const Grid& g, int x0, T* /*s_f*/) {
+    // lane0: column of lane 0 (the strip's first column minus its halo)
+    __device__ __forceinline__ void setup(const T* fin, const Grid& g, int lane0, T* /*s_f*/) {
         nx = g.nx;
         ny = g.ny;
         pitch = g.pitch;
 #pragma unroll
         for (int i = 0; i < 9; ++i) P[i] = fin + i * g.plane;
-        xc = (x0 - 3 + (int)threadIdx.x) % nx;
+        xc = (lane0 + (int)threadIdx.x) % nx;
         if (xc < 0) xc += nx;
         cm = (xc == 0) ? nx - 1 : xc - 1;
         cp = (xc == nx - 1) ? 0 : xc + 1;
@@ -213,7 +214,7 @@ template <typename T, int NT>
 struct RowLoader<T, NT, true> {
     using V = typename Vec16<T>::type;
     static constexpr int VEC = 16 / sizeof(T);
-    static constexpr int SPAN = NT + 4;             // staged columns x0-4 .. x0+NT-1
+    static constexpr int SPAN = NT + 4;             // staged columns lane0-1 .. lane0+NT+2
     static constexpr int CPR = SPAN / VEC;          // chunks per plane-row
     static constexpr int NCH = 9 * CPR;
     static constexpr int M = (NCH + NT - 1) / NT;   // chunks per lane
@@ -223,7 +224,9 @@ struct RowLoader<T, NT, true> {
     int dy[M];             // row offset of the plane's pull: -1, 0, +1
     unsigned live;         // bit m: chunk m exists
     int nx, ny, pitch;
-    __device__ __forceinline__ void setup(const T* f, const Grid& g, int x0, T* /*s_f*/) {
+    // lane0: column of lane 0; staged column 0 is lane0 - 1, which must be a
+    // multiple of VEC
+    __device__ __forceinline__ void setup(const T* f, const Grid& g, int lane0, T* /*s_f*/) {
         fin = f;
         nx = g.nx;
         ny = g.ny;
@@ -240,7 +243,7 @@ struct RowLoader<T, NT, true> {
             const int ii = i < 9 ? i : 0;
             // c_iy of eq 20a: the pull of plane i reads row r - c_iy
             dy[m] = (ii == 2 || ii == 5 || ii == 6) ? -1 : ((ii == 4 || ii == 7 || ii == 8) ? 1 : 0);
-            int cw = (x0 - 4 + q * VEC) % nx;
+            int cw = (lane0 - 1 + q * VEC) % nx;
             if (cw < 0) cw += nx;
             off[m] = ii * (int)g.plane + cw;
             if (ch < NCH) live |= 1u << m;
@@ -289,6 +292,102 @@ struct StageLds {
     static constexpr int kF = STAGED ? 9 * (NT + 4) : 1;
 };
 
+// ---- stage bodies shared by the one-step and the two-step sweeps ----------
+// Rings hold three consecutive rows: slot sN = newest (row r+1 of the stage's
+// centre row r), sC = row r, sS = row r - 1.
+
+// Stage B at one lane: grad phi and lap phi (eq 26), gamma and gamma' (eq 6
+// generalised), Q (eq 15, derived or printed form), w (eq 9 / eq 8); writes
+// Q and w to their rings and returns the pointwise part of mu_beta (eq 16
+// without div Q and lap w) and mu_alpha (eq 16).
+template <typename T, int NT>
+__device__ __forceinline__ void stage_b(const StepCoef<T>& c, T (*s_phi)[NT], T (*s_qx)[NT], T (*s_qy)[NT],
+                                        T (*s_w)[NT], int sN, int sC, int sS, int t, T& tl, T& mua) {
+    const T pC = s_phi[sC][t], pE = s_phi[sC][t + 1], pW = s_phi[sC][t - 1];
+    const T pN = s_phi[sN][t], pNE = s_phi[sN][t + 1], pNW = s_phi[sN][t - 1];
+    const T pS = s_phi[sS][t], pSE = s_phi[sS][t + 1], pSW = s_phi[sS][t - 1];
+    const T px = c.g3 * (pE - pW) + c.g12 * ((pNE - pSW) + (pSE - pNW));
+    const T py = c.g3 * (pN - pS) + c.g12 * ((pNE - pSW) + (pNW - pSE));
+    const T lap = c.l23 * ((pE + pW) + (pN + pS)) + c.l16 * ((pNE + pSW) + (pNW + pSE)) - c.l103 * pC;
+    const T fb = c.beta4 * pC * (pC * pC - T(1));
+    const T g2 = px * px + py * py;
+    T gamma, gp;
+    anisotropy<T>(px, py, g2, c.m, c.alpha, c.alpha_m, c.rot_c, c.rot_s, c.floor2, gamma, gp);
+    T qx, qy;
+    if (c.qform == 0) {
+        qx = c.kappa * (gamma * px - gp * py);
+        qy = c.kappa * (gamma * py + gp * px);
+    } else {
+        qx = gamma * c.kappa * px - gp * py;
+        qy = gamma * c.kappa * py + gp * px;
+    }
+    T w, tl0 = (gamma - T(1)) * fb + c.kappa * lap;
+    if (c.reg == REG_WILLMORE) {
+        w = lap - fb;
+        const T fpr = c.beta4 * (T(3) * pC * pC - T(1));
+        tl0 -= c.eps * fpr * w;
+    } else if (c.reg == REG_LINEAR) {
+        w = lap;
+    } else {
+        w = T(0);
+    }
+    s_qx[sN][t] = qx;
+    s_qy[sN][t] = qy;
+    s_w[sN][t] = w;
+    tl = tl0;
+    mua = fb - c.kappa * lap;
+}
+
+// Stage C at one lane: div Q (eq 26a per component) and lap w (eq 26b)
+// complete mu_beta (eqs 13, 16).
+template <typename T, int NT>
+__device__ __forceinline__ T stage_c(const StepCoef<T>& c, T (*s_qx)[NT], T (*s_qy)[NT], T (*s_w)[NT], int sN,
+                                     int sC, int sS, int t, T tl) {
+    const T divq = c.g3 * (s_qx[sC][t + 1] - s_qx[sC][t - 1]) +
+                   c.g12 * ((s_qx[sN][t + 1] - s_qx[sS][t - 1]) + (s_qx[sS][t + 1] - s_qx[sN][t - 1])) +
+                   c.g3 * (s_qy[sN][t] - s_qy[sS][t]) +
+                   c.g12 * ((s_qy[sN][t + 1] - s_qy[sS][t - 1]) + (s_qy[sN][t - 1] - s_qy[sS][t + 1]));
+    T mb = tl - divq;
+    if (c.reg != REG_NONE) {
+        const T lw = c.l23 * ((s_w[sC][t + 1] + s_w[sC][t - 1]) + (s_w[sN][t] + s_w[sS][t])) +
+                     c.l16 * ((s_w[sN][t + 1] + s_w[sS][t - 1]) + (s_w[sN][t - 1] + s_w[sS][t + 1])) -
+                     c.l103 * s_w[sC][t];
+        mb += c.eps * lw;
+    }
+    return mb;
+}
+
+// Stage D at one lane: grad mu_beta (eq 26a), then the collision (eqs 17-19,
+// 23, 25) of the node's pulled populations (all nine, or phi, j_x, j_y).
+template <typename T, int NT, bool UNIT>
+__device__ __forceinline__ void stage_d(const StepCoef<T>& c, T (*s_mb)[NT], int sN, int sC, int sS, int t,
+                                        const T (&pop)[9], const T (&red)[3], T mu_a, T (&o)[9]) {
+    const T gx = c.g3 * (s_mb[sC][t + 1] - s_mb[sC][t - 1]) +
+                 c.g12 * ((s_mb[sN][t + 1] - s_mb[sS][t - 1]) + (s_mb[sS][t + 1] - s_mb[sN][t - 1]));
+    const T gy = c.g3 * (s_mb[sN][t] - s_mb[sS][t]) +
+                 c.g12 * ((s_mb[sN][t + 1] - s_mb[sS][t - 1]) + (s_mb[sN][t - 1] - s_mb[sS][t + 1]));
+    if (UNIT) collide_unit<T>(red[0], red[1], red[2], mu_a, gx, gy, c, o);
+    else collide<T>(pop, mu_a, gx, gy, c, o);
+}
+
+// Stage A after the pull: phi = sum f_i (eq 22) in the summation order the
+// collision uses, and what stage D keeps of the node.
+template <typename T, bool UNIT>
+__device__ __forceinline__ T stage_a(const T (&f)[9], T (&pop)[9], T (&red)[3]) {
+    const T a = (f[1] + f[2]) + (f[3] + f[4]);
+    const T b = (f[5] + f[6]) + (f[7] + f[8]);
+    const T phi = f[0] + a + b;
+    if (UNIT) {
+        red[0] = phi;
+        red[1] = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));   // j_x = m_3
+        red[2] = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));   // j_y = m_5
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) pop[i] = f[i];
+    }
+    return phi;
+}
+
 template <typename T, int NT, bool UNIT, bool STAGED>
 __device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __restrict__ fout, const Grid& g,
                                             const int x0, const int wlen, const int y0, const int hlen,
@@ -303,7 +402,7 @@ __device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __rest
     const int t = threadIdx.x;
 
     Loader ld;
-    ld.setup(fin, g, x0, s_f);
+    ld.setup(fin, g, x0 - 3, s_f);
     int xc = (x0 - 3 + t) % nx;      // the lane's column (wrapped)
     if (xc < 0) xc += nx;
 
@@ -330,7 +429,7 @@ __device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __rest
             const int j = jb + k;
             if (j < niter) {
                 const int sN = j % 3, sC = (j + 2) % 3, sS = (j + 1) % 3;
-                // ---- A: populations of row r, phi (same summation order as the collision) ----
+                // ---- A: populations of row r, phi ----
                 if (Loader::kNeedsBarrier) {
                     ld.park(buf[k], s_f);
                     lds_barrier();
@@ -338,18 +437,7 @@ __device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __rest
                 {
                     T f[9];
                     ld.fetch(buf[k], s_f, f);
-                    const T a = (f[1] + f[2]) + (f[3] + f[4]);
-                    const T b = (f[5] + f[6]) + (f[7] + f[8]);
-                    const T phi = f[0] + a + b;
-                    s_phi[sN][t] = phi;
-                    if (UNIT) {
-                        red[k][0] = phi;
-                        red[k][1] = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));   // j_x = m_3
-                        red[k][2] = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));   // j_y = m_5
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 9; ++i) pop[k][i] = f[i];
-                    }
+                    s_phi[sN][t] = stage_a<T, UNIT>(f, pop[k], red[k]);
                 }
                 // unconditional: past the last row of the sweep this fetches a
                 // (wrapped, valid) row that is never used; a branch here would
@@ -358,75 +446,150 @@ __device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __rest
                 rA = (rA == ny - 1) ? 0 : rA + 1;
                 lds_barrier();
                 // ---- B: row r-1 ----
-                if (j >= 2 && t >= 1 && t < NT - 1) {
-                    const T pC = s_phi[sC][t], pE = s_phi[sC][t + 1], pW = s_phi[sC][t - 1];
-                    const T pN = s_phi[sN][t], pNE = s_phi[sN][t + 1], pNW = s_phi[sN][t - 1];
-                    const T pS = s_phi[sS][t], pSE = s_phi[sS][t + 1], pSW = s_phi[sS][t - 1];
-                    const T px = c.g3 * (pE - pW) + c.g12 * ((pNE - pSW) + (pSE - pNW));
-                    const T py = c.g3 * (pN - pS) + c.g12 * ((pNE - pSW) + (pNW - pSE));
-                    const T lap = c.l23 * ((pE + pW) + (pN + pS)) + c.l16 * ((pNE + pSW) + (pNW + pSE)) -
-                                  c.l103 * pC;
-                    const T fb = c.beta4 * pC * (pC * pC - T(1));
-                    const T g2 = px * px + py * py;
-                    T gamma, gp;
-                    anisotropy<T>(px, py, g2, c.m, c.alpha, c.alpha_m, c.rot_c, c.rot_s, c.floor2, gamma, gp);
-                    T qx, qy;
-                    if (c.qform == 0) {
-                        qx = c.kappa * (gamma * px - gp * py);
-                        qy = c.kappa * (gamma * py + gp * px);
-                    } else {
-                        qx = gamma * c.kappa * px - gp * py;
-                        qy = gamma * c.kappa * py + gp * px;
-                    }
-                    T w, tl0 = (gamma - T(1)) * fb + c.kappa * lap;
-                    if (c.reg == REG_WILLMORE) {
-                        w = lap - fb;
-                        const T fpr = c.beta4 * (T(3) * pC * pC - T(1));
-                        tl0 -= c.eps * fpr * w;
-                    } else if (c.reg == REG_LINEAR) {
-                        w = lap;
-                    } else {
-                        w = T(0);
-                    }
-                    s_qx[sN][t] = qx;
-                    s_qy[sN][t] = qy;
-                    s_w[sN][t] = w;
-                    tloc[k] = tl0;
-                    mua[k] = fb - c.kappa * lap;
-                }
+                if (j >= 2 && t >= 1 && t < NT - 1)
+                    stage_b<T, NT>(c, s_phi, s_qx, s_qy, s_w, sN, sC, sS, t, tloc[k], mua[k]);
                 lds_barrier();
                 // ---- C: row r-2 ----
-                if (j >= 4 && t >= 2 && t < NT - 2) {
-                    const T divq =
-                        c.g3 * (s_qx[sC][t + 1] - s_qx[sC][t - 1]) +
-                        c.g12 * ((s_qx[sN][t + 1] - s_qx[sS][t - 1]) + (s_qx[sS][t + 1] - s_qx[sN][t - 1])) +
-                        c.g3 * (s_qy[sN][t] - s_qy[sS][t]) +
-                        c.g12 * ((s_qy[sN][t + 1] - s_qy[sS][t - 1]) + (s_qy[sN][t - 1] - s_qy[sS][t + 1]));
-                    T mb = tloc[(k + U - 1) % U] - divq;
-                    if (c.reg != REG_NONE) {
-                        const T lw = c.l23 * ((s_w[sC][t + 1] + s_w[sC][t - 1]) + (s_w[sN][t] + s_w[sS][t])) +
-                                     c.l16 * ((s_w[sN][t + 1] + s_w[sS][t - 1]) + (s_w[sN][t - 1] + s_w[sS][t + 1])) -
-                                     c.l103 * s_w[sC][t];
-                        mb += c.eps * lw;
-                    }
-                    s_mb[sN][t] = mb;
-                }
+                if (j >= 4 && t >= 2 && t < NT - 2)
+                    s_mb[sN][t] = stage_c<T, NT>(c, s_qx, s_qy, s_w, sN, sC, sS, t, tloc[(k + U - 1) % U]);
                 lds_barrier();
                 // ---- D: row r-3 ----
                 if (j >= 6 && t >= 3 && t < 3 + wlen) {
-                    const T gx = c.g3 * (s_mb[sC][t + 1] - s_mb[sC][t - 1]) +
-                                 c.g12 * ((s_mb[sN][t + 1] - s_mb[sS][t - 1]) + (s_mb[sS][t + 1] - s_mb[sN][t - 1]));
-                    const T gy = c.g3 * (s_mb[sN][t] - s_mb[sS][t]) +
-                                 c.g12 * ((s_mb[sN][t + 1] - s_mb[sS][t - 1]) + (s_mb[sN][t - 1] - s_mb[sS][t + 1]));
-                    const T mu_a = mua[(k + U - 2) % U];
                     T o[9];
-                    if (UNIT) {
-                        const T(&rr)[3] = red[(k + U - 3) % U];
-                        collide_unit<T>(rr[0], rr[1], rr[2], mu_a, gx, gy, c, o);
-                    } else {
-                        collide<T>(pop[(k + U - 3) % U], mu_a, gx, gy, c, o);
-                    }
+                    stage_d<T, NT, UNIT>(c, s_mb, sN, sC, sS, t, pop[(k + U - 3) % U], red[(k + U - 3) % U],
+                                         mua[(k + U - 2) % U], o);
                     const int rd = y0 - 6 + j;
+                    T* __restrict__ q = fout + ((long long)rd * pitch + xc);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per sweep (temporal blocking).  Lane t owns column
+// x0 - 7 + t; a strip yields W = NT - 16 columns of the second step.  Each
+// iteration j loads row a = y0 - 7 + j and runs eight lagging stages:
+//   A1..D1 (rows a .. a-3): the first step exactly as in sweep_strip, except
+//          that D1 keeps its post-collision row d = a-3 on chip;
+//   A2 (row a-4)          : pull of the second step from that on-chip row
+//                           buffer (planes 0, 2, 4 pull along the lane's own
+//                           column and stay in registers; 1/3, 5/6 and 7/8
+//                           go through LDS rings of 2, 3 and 1 rows, the lag
+//                           of their pull: 1, 2 and 0 rows);
+//   B2..D2 (rows a-5 .. a-7): the second step; D2 stores to HBM.
+// Every population is read from and written to HBM once per two updates.
+// Valid lanes shrink by one per stage: A1 all, B1 [1, NT-1), C1 [2, NT-2),
+// D1 [3, NT-3), A2 [4, NT-4), B2 [5, NT-5), C2 [6, NT-6), D2 [7, NT-7).
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+struct Pass2Lds {
+    T phi[3][NT], qx[3][NT], qy[3][NT], w[3][NT], mb[3][NT];
+};
+
+template <typename T, int NT, bool UNIT, bool STAGED>
+__device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __restrict__ fout, const Grid& g,
+                                             const int x0, const int wlen, const int y0, const int hlen,
+                                             const StepCoef<T>& c, Pass2Lds<T, NT>& L1, Pass2Lds<T, NT>& L2,
+                                             T (*s_13)[2][NT], T (*s_56)[2][NT], T (*s_78)[NT], T* s_f) {
+    constexpr int U = 4;
+    using Loader = RowLoader<T, NT, STAGED>;
+    const int nx = g.nx, ny = g.ny, pitch = g.pitch;
+    const int niter = hlen + 14;
+    const int t = threadIdx.x;
+
+    Loader ld;
+    ld.setup(fin, g, x0 - 7, s_f);
+    int xc = (x0 - 7 + t) % nx;
+    if (xc < 0) xc += nx;
+    int rA = (y0 - 7) % ny;
+    if (rA < 0) rA += ny;
+
+    typename Loader::Buf buf[U];
+    T pop1[U][9], red1[U][3], mua1[U], tl1[U];
+    T pop2[U][9], red2[U][3], mua2[U], tl2[U];
+    T o0r[U], o2r[U], o4r[U];         // D1 planes 0, 2, 4 of the lane (A2 uses them 1, 2, 0 iterations later)
+#pragma unroll
+    for (int k = 0; k < U; ++k) o0r[k] = o2r[k] = o4r[k] = T(0);
+
+    ld.issue(rA, buf[0]);
+    rA = (rA == ny - 1) ? 0 : rA + 1;
+
+    for (int jb = 0; jb < niter; jb += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j = jb + k;
+            if (j < niter) {
+                const int sN = j % 3, sC = (j + 2) % 3, sS = (j + 1) % 3;
+                // ---- A1: row a ----
+                if (Loader::kNeedsBarrier) {
+                    ld.park(buf[k], s_f);
+                    lds_barrier();
+                }
+                {
+                    T f[9];
+                    ld.fetch(buf[k], s_f, f);
+                    L1.phi[sN][t] = stage_a<T, UNIT>(f, pop1[k], red1[k]);
+                }
+                ld.issue(rA, buf[(k + 1) % U]);
+                rA = (rA == ny - 1) ? 0 : rA + 1;
+                lds_barrier();
+                // ---- B1: row a-1 ----
+                if (j >= 2 && t >= 1 && t < NT - 1)
+                    stage_b<T, NT>(c, L1.phi, L1.qx, L1.qy, L1.w, sN, sC, sS, t, tl1[k], mua1[k]);
+                lds_barrier();
+                // ---- C1: row a-2 ----
+                if (j >= 4 && t >= 2 && t < NT - 2)
+                    L1.mb[sN][t] = stage_c<T, NT>(c, L1.qx, L1.qy, L1.w, sN, sC, sS, t, tl1[(k + U - 1) % U]);
+                lds_barrier();
+                // ---- D1: row d = a-3, kept on chip ----
+                if (j >= 6 && t >= 3 && t < NT - 3) {
+                    T o[9];
+                    stage_d<T, NT, UNIT>(c, L1.mb, sN, sC, sS, t, pop1[(k + U - 3) % U], red1[(k + U - 3) % U],
+                                         mua1[(k + U - 2) % U], o);
+                    o0r[k] = o[0];
+                    o2r[k] = o[2];
+                    o4r[k] = o[4];
+                    s_13[j & 1][0][t] = o[1];
+                    s_13[j & 1][1][t] = o[3];
+                    s_56[j % 3][0][t] = o[5];
+                    s_56[j % 3][1][t] = o[6];
+                    s_78[0][t] = o[7];
+                    s_78[1][t] = o[8];
+                }
+                lds_barrier();
+                // ---- A2: row a-4 = d-1, pulled from the first step's rows d-2 .. d ----
+                if (j >= 8 && t >= 4 && t < NT - 4) {
+                    T f[9];
+                    const int p1 = (j + 1) & 1, p2 = (j + 1) % 3;   // slots of rows d-1 and d-2
+                    f[0] = o0r[(k + U - 1) % U];
+                    f[1] = s_13[p1][0][t - 1];
+                    f[2] = o2r[(k + U - 2) % U];
+                    f[3] = s_13[p1][1][t + 1];
+                    f[4] = o4r[k];
+                    f[5] = s_56[p2][0][t - 1];
+                    f[6] = s_56[p2][1][t + 1];
+                    f[7] = s_78[0][t + 1];
+                    f[8] = s_78[1][t - 1];
+                    L2.phi[sN][t] = stage_a<T, UNIT>(f, pop2[k], red2[k]);
+                }
+                lds_barrier();
+                // ---- B2: row a-5 ----
+                if (j >= 10 && t >= 5 && t < NT - 5)
+                    stage_b<T, NT>(c, L2.phi, L2.qx, L2.qy, L2.w, sN, sC, sS, t, tl2[k], mua2[k]);
+                lds_barrier();
+                // ---- C2: row a-6 ----
+                if (j >= 12 && t >= 6 && t < NT - 6)
+                    L2.mb[sN][t] = stage_c<T, NT>(c, L2.qx, L2.qy, L2.w, sN, sC, sS, t, tl2[(k + U - 1) % U]);
+                lds_barrier();
+                // ---- D2: row a-7, stored ----
+                if (j >= 14 && t >= 7 && t < 7 + wlen) {
+                    T o[9];
+                    stage_d<T, NT, UNIT>(c, L2.mb, sN, sC, sS, t, pop2[(k + U - 3) % U], red2[(k + U - 3) % U],
+                                         mua2[(k + U - 2) % U], o);
+                    const int rd = y0 - 14 + j;
                     T* __restrict__ q = fout + ((long long)rd * pitch + xc);
 #pragma unroll
                     for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i];
@@ -454,6 +617,27 @@ __global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* _
     const int y0 = chunk * tl.hc;
     sweep_strip<T, NT, UNIT, STAGED>(fin, fout, g, x0, min(tl.W, g.nx - x0), y0, min(tl.hc, g.ny - y0), c, s_phi,
                                      s_qx, s_qy, s_w, s_mb, s_f);
+}
+
+// Two steps per launch: fin holds the state at step n, fout receives step n + 2.
+template <typename T, int NT, bool UNIT, bool STAGED>
+__global__ __launch_bounds__(NT) void step2_fused(const T* __restrict__ fin, T* __restrict__ fout,
+                                                  const Grid g, const Tiling tl, const StepCoef<T> c) {
+    __shared__ Pass2Lds<T, NT> L1;
+    __shared__ Pass2Lds<T, NT> L2;
+    __shared__ T s_13[2][2][NT];
+    __shared__ T s_56[3][2][NT];
+    __shared__ T s_78[2][NT];
+    __shared__ __align__(16) T s_f[StageLds<T, NT, STAGED>::kF];
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * tl.per_xcd + (bid >> 3);
+    if (tile >= tl.ntiles) return;
+    const int strip = tile % tl.strips;
+    const int chunk = tile / tl.strips;
+    const int x0 = strip * tl.W;
+    const int y0 = chunk * tl.hc;
+    sweep_strip2<T, NT, UNIT, STAGED>(fin, fout, g, x0, min(tl.W, g.nx - x0), y0, min(tl.hc, g.ny - y0), c, L1, L2,
+                                      s_13, s_56, s_78, s_f);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,6 +903,23 @@ template <typename T, bool UNIT, bool STAGED>
 static hipError_t launch_step_v(const T* fin, T* fout, const Grid& g, const Tiling& t, const StepCoef<T>& c,
                                 hipStream_t s) {
     dim3 grid(t.nblocks);
+    if (t.depth == 2) {
+        switch (t.nt) {
+            case 128: step2_fused<T, 128, UNIT, STAGED><<<grid, 128, 0, s>>>(fin, fout, g, t, c); break;
+            case 256: step2_fused<T, 256, UNIT, STAGED><<<grid, 256, 0, s>>>(fin, fout, g, t, c); break;
+            case 512:
+                // the float64 rings of 512 lanes exceed the LDS of one workgroup
+                if constexpr (sizeof(T) == 4) {
+                    step2_fused<T, 512, UNIT, STAGED><<<grid, 512, 0, s>>>(fin, fout, g, t, c);
+                    break;
+                } else {
+                    return hipErrorInvalidValue;
+                }
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (t.depth != 1) return hipErrorInvalidValue;
     switch (t.nt) {
         case 64: step_fused<T, 64, UNIT, STAGED><<<grid, 64, 0, s>>>(fin, fout, g, t, c); break;
         case 128: step_fused<T, 128, UNIT, STAGED><<<grid, 128, 0, s>>>(fin, fout, g, t, c); break;
@@ -790,6 +991,38 @@ static int occ_t(int nt) {
         default: return 1;
     }
     return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+template <typename T, bool UNIT, bool STAGED>
+static int occ_step_t(int depth, int nt) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (depth == 2) {
+        switch (nt) {
+            case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2_fused<T, 128, UNIT, STAGED>, 128, 0); break;
+            case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2_fused<T, 256, UNIT, STAGED>, 256, 0); break;
+            case 512:
+                if constexpr (sizeof(T) == 4)
+                    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2_fused<T, 512, UNIT, STAGED>, 512, 0);
+                break;
+            default: break;
+        }
+    } else {
+        switch (nt) {
+            case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_fused<T, 64, UNIT, STAGED>, 64, 0); break;
+            case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_fused<T, 128, UNIT, STAGED>, 128, 0); break;
+            case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_fused<T, 256, UNIT, STAGED>, 256, 0); break;
+            case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_fused<T, 512, UNIT, STAGED>, 512, 0); break;
+            default: break;
+        }
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int step_blocks_per_cu(int precision, int depth, int nt, bool unit, bool staged) {
+    if (precision == 0) return unit ? occ_step_t<double, true, false>(depth, nt) : occ_step_t<double, false, false>(depth, nt);
+    if (staged) return unit ? occ_step_t<float, true, true>(depth, nt) : occ_step_t<float, false, true>(depth, nt);
+    return unit ? occ_step_t<float, true, false>(depth, nt) : occ_step_t<float, false, false>(depth, nt);
 }
 
 int batch_blocks_per_cu(int precision, int nt, bool unit_all) {

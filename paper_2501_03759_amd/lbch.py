@@ -86,6 +86,8 @@ _SIGNATURES = {
     "lbch_get_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
     "lbch_set_row_loader": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_set_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_get_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "lbch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "lbch_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
@@ -270,6 +272,15 @@ class Sim:
 
     def set_row_loader(self, mode: int):
         _check(lib().lbch_set_row_loader(self._h, mode), "lbch_set_row_loader")
+
+    def set_time_blocking(self, depth: int):
+        """Time steps per kernel launch (1 or 2); resets the tiling to that depth's default."""
+        _check(lib().lbch_set_time_blocking(self._h, depth), "lbch_set_time_blocking")
+
+    def time_blocking(self) -> int:
+        d = ctypes.c_int32()
+        _check(lib().lbch_get_time_blocking(self._h, ctypes.byref(d)), "lbch_get_time_blocking")
+        return d.value
 
     def tiling(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -26,10 +26,12 @@ def c1_params(precision=0, **kw):
     return common.make_params(64, 64, precision, **args)
 
 
-def run_gpu(p, phi0, nsteps, tiling=None, loader=0):
+def run_gpu(p, phi0, nsteps, tiling=None, loader=0, depth=None):
     L = lb()
     with L.Sim(p) as s:
         s.set_row_loader(loader)
+        if depth:
+            s.set_time_blocking(depth)
         if tiling:
             s.set_tiling(*tiling)
         s.init(phi0)
@@ -42,10 +44,50 @@ def test_c1_droplet_fp64_2000_steps(rates):
     kw = {} if rates == "unit" else {"s": inputs.C1_RATES_DISTINCT}
     p = c1_params(0, **kw)
     phi0 = inputs.droplet(64, 64, 16.0, 2.0)
-    print(f"case c1 rates={rates}", flush=True)
-    got = run_gpu(p, phi0, 2000)
     want = common.oracle_phi(phi0, p, 2000)
-    assert np.abs(got - want).max() <= FP64_TOL
+    for depth in (1, 2):
+        print(f"case c1 rates={rates} depth={depth}", flush=True)
+        got = run_gpu(p, phi0, 2000, depth=depth)
+        assert np.abs(got - want).max() <= FP64_TOL, depth
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("rates", ["unit", "distinct"])
+@pytest.mark.parametrize("shape", [(300, 130), (203, 77), (40, 24)])
+def test_time_blocking_is_bitwise(precision, rates, shape):
+    # two steps per launch (and the single-step tail of an odd count) against
+    # one step per launch; staged and per-lane row loaders, several tilings
+    nx, ny = shape
+    kw = {} if rates == "unit" else {"s": inputs.C1_RATES_DISTINCT}
+    p = common.make_params(nx, ny, precision, width=4.0, alpha=0.3, **kw)
+    phi0 = inputs.spinodal(nx, ny, seed=5, amp=0.3)
+    print(f"case time-blocking {shape} precision={precision} rates={rates}", flush=True)
+    ref = {k: run_gpu(p, phi0, k, depth=1) for k in (60, 61)}
+    tilings = [None, (128, 1), (128, 37), (256, 130), (256, 1000)] + ([(512, 64)] if precision == 1 else [])
+    for loader in (0, 1):
+        for tiling in tilings:
+            for nsteps in (61, 60):
+                got = run_gpu(p, phi0, nsteps, tiling, loader, depth=2)
+                assert np.array_equal(got, ref[nsteps]), (tiling, loader, nsteps)
+
+
+def test_time_blocking_errors():
+    L = lb()
+    with L.Sim(common.make_params(96, 64, 0, width=4.0)) as s:
+        assert s.time_blocking() == 2
+        with pytest.raises(L.LbchError):
+            s.set_time_blocking(3)
+        s.set_time_blocking(1)
+        assert s.time_blocking() == 1
+        s.set_time_blocking(2)
+        with pytest.raises(L.LbchError):
+            s.set_tiling(512, 16)          # float64 rings of 512 lanes do not fit in LDS
+        with pytest.raises(L.LbchError):
+            s.set_tiling(64, 16)
+        s.set_tiling(256, 16)
+        assert s.tiling() == (256, 16)
+        s.set_time_blocking(1)
+        s.set_tiling(64, 16)
 
 
 def test_c2_parameters_at_128_fp64():
@@ -102,12 +144,15 @@ def test_tiling_is_bitwise_invariant(precision):
     p = common.make_params(300, 130, precision, width=4.0, alpha=0.3, s=inputs.C1_RATES_DISTINCT)
     phi0 = inputs.spinodal(300, 130, seed=5, amp=0.3)
     ref = None
+    shapes = {1: [(64, 1), (64, 7), (128, 16), (256, 5), (256, 130), (512, 33), (128, 1000)],
+              2: [(128, 3), (256, 29), (128, 130)] + ([(512, 40)] if precision == 1 else [])}
     for loader in (0, 1):
-        for tiling in [(64, 1), (64, 7), (128, 16), (256, 5), (256, 130), (512, 33), (128, 1000)]:
-            got = run_gpu(p, phi0, 60, tiling, loader)
-            if ref is None:
-                ref = got
-            assert np.array_equal(got, ref), (tiling, loader)
+        for depth, tilings in shapes.items():
+            for tiling in tilings:
+                got = run_gpu(p, phi0, 60, tiling, loader, depth=depth)
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got, ref), (depth, tiling, loader)
 
 
 def test_reductions_against_oracle():
@@ -254,16 +299,19 @@ def test_fp32_vs_fp64_c2_full_size_1000_steps():
     assert np.abs(out[1] - out[0]).max() <= FP32_TOL
 
 
-@pytest.mark.parametrize("n,precision,seed", [(1024, 0, 0), (1024, 1, 0), (8192, 1, 5)])
-def test_full_size_sampled_against_oracle(n, precision, seed):
-    # Full-size grids in the default launch shape: sampled nodes against oracle windows.
+@pytest.mark.parametrize("n,precision,seed,depth", [(1024, 0, 0, 1), (1024, 1, 0, 1), (8192, 1, 5, 1),
+                                                     (1024, 0, 0, 2), (8192, 1, 5, 2)])
+def test_full_size_sampled_against_oracle(n, precision, seed, depth):
+    # Full-size grids in the default launch shape of each depth (3 steps: at
+    # depth 2 one two-step and one single-step launch): sampled nodes against
+    # oracle windows.
     d = inputs.C5 if n == 8192 else inputs.C2
     p = common.make_params(n, n, precision, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"],
                            eps_reg=d["eps_reg"])
     phi0 = inputs.spinodal(n, n, seed=seed, amp=d["amp"])
     k = 3
-    print(f"case full-size n={n} precision={precision}", flush=True)
-    got = run_gpu(p, phi0, k)
+    print(f"case full-size n={n} precision={precision} depth={depth}", flush=True)
+    got = run_gpu(p, phi0, k, depth=depth)
     rng = np.random.default_rng(77)
     pts = [(int(y), int(x)) for y, x in rng.integers(0, n, size=(24, 2))]
     pts += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (n // 2, 249), (n // 2, 250), (131, 500)]
@@ -300,7 +348,7 @@ def test_autotune_keeps_state_and_results():
         s.step(10)
         before = s.phi()
         nt, hc, ms = s.autotune(2)
-        assert nt in (64, 128, 256, 512) and hc >= 1 and ms > 0
+        assert nt in (64, 128, 256, 512) and hc >= 1 and ms > 0 and s.time_blocking() in (1, 2)
         assert s.nstep == 10 and np.array_equal(s.phi(), before)
         s.step(30)
         assert np.array_equal(s.phi(), want)
