@@ -92,6 +92,118 @@ def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=5):
             "verified": ok}
 
 
+def hybrid_workload(args):
+    """Time-to-t of the jump + correction schedule against the plain scheme on the same GPU.
+
+    The 8192^2 FP32 spinodal run (alpha 0.2) is advanced plainly to the onset of coarsening
+    (--hybrid-warm steps), then --hybrid-steps steps are timed twice from that state: plain, and
+    with the hybrid schedule (rate-extrapolated jumps, optionally plus the trained network's
+    residual).  Reports the wall-time ratio, the relative L2 difference of the final fields and
+    whether the free energy, sampled every --hybrid-chunk steps, never rose."""
+    import torch
+
+    from paper_2501_03759_amd import inputs, lbch
+
+    d = inputs.C5
+    n = args.n
+    p = lbch.default_params(nx=n, ny=n, precision=lbch.FP32,
+                            sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"])),
+                            mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    K, NC = args.hybrid_jump, args.hybrid_correct
+    cyc = K + NC
+    chunk = max(cyc, args.hybrid_chunk // cyc * cyc)
+    net, cond = None, []
+    train_s = 0.0
+    with torch.cuda.stream(stream):
+        if args.surrogate:
+            from paper_2501_03759_amd import lbsg, surrogate_train as st
+            t0 = time.time()
+            runs = st.draw_runs(64, seed=1)
+            X, Y = st.generate(runs, 256, 60000, 300000, 4000, K, 256, 1, seed=7, stream=stream,
+                               log=lambda m: print(m, file=sys.stderr, flush=True), extrapolate=True)
+            tr = lbsg.Surrogate((32, 32), 1 + st.N_COND, 16, 256, 256, train=True, seed=0, stream=stream,
+                                out_scale=0.02)
+            st.train(tr, X, Y, epochs=8, batch=16, lr=1e-3, margin=0, log=lambda m: None)
+            w = tr.get_params()
+            tr.close()
+            del X, Y
+            torch.cuda.empty_cache()
+            net = lbsg.Surrogate((32, 32), 1 + st.N_COND, 1, n, n, train=False, seed=0, stream=stream,
+                                 out_scale=0.02)
+            net.set_params(w)
+            cond = list(st.conditioning(d["alpha"], d["m"], 0.0))
+            train_s = time.time() - t0
+        def note(msg):
+            print(msg, file=sys.stderr, flush=True)
+
+        plain = lbch.Sim(p, stream)
+        plain.init(inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"]))
+        for k in range(0, args.hybrid_warm, 20000):
+            plain.step(min(20000, args.hybrid_warm - k))
+            plain.synchronize()
+            note(f"warm-up: step {plain.nstep}")
+        blob = plain.save_state()
+        hyb = lbch.Sim(p, stream)
+        hyb.load_state(blob)
+        del blob
+
+        def run(advance):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done = 0
+            while done < args.hybrid_steps:
+                k = min(chunk, args.hybrid_steps - done)
+                advance(k)
+                done += k
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        e_plain, e_hyb = [plain.free_energy()[0]], [hyb.free_energy()[0]]
+        inner = [int(v) for v in args.hybrid_inner.split(",")]
+        o = lbch.hybrid_opts(jump=K, correct_steps=NC, windows=4, window_interior=192, window_margin=64,
+                             tol_window=1e-2, tol_energy=0.0, check_every=4, extrapolate=1, cond=cond,
+                             inner_steps=inner[0], inner_jump=inner[1])
+        totals = {}
+
+        def adv_plain(k):
+            plain.step(k)
+            e_plain.append(plain.free_energy()[0])
+            note(f"plain: step {plain.nstep}, E = {e_plain[-1]:.6f}")
+
+        def adv_hyb(k):
+            st_ = lbch.hybrid_advance(hyb, net, o, k)
+            for f, _ in st_._fields_:
+                v = getattr(st_, f)
+                if f == "max_window_err":
+                    totals[f] = max(totals.get(f, 0.0), v)
+                elif f != "last_energy":
+                    totals[f] = totals.get(f, 0) + v
+            e_hyb.append(hyb.free_energy()[0])
+            note(f"hybrid: step {hyb.nstep}, E = {e_hyb[-1]:.6f}, accepted {st_.accepted}/{st_.cycles}")
+
+        t_plain = run(adv_plain)
+        t_hyb = run(adv_hyb)
+        pa, ph = plain.phi(), hyb.phi()
+        rel = float(np.linalg.norm(ph - pa) / np.linalg.norm(pa))
+    out = {
+        "metric": "time-to-t speedup of the jump + correction schedule over the plain scheme (1 GPU)",
+        "value": round(t_plain / t_hyb, 3), "unit": "x", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
+        "config": {"workload": f"spinodal-{n}x{n}-fp32-coarsening", "warm_steps": args.hybrid_warm,
+                   "timed_steps": args.hybrid_steps, "jump": K, "correct_steps": NC, "windows": 4,
+                   "check_every": 4, "jump_form": "rate extrapolation" + (" + network residual" if net else ""),
+                   "inner_steps": inner[0], "inner_jump": inner[1]},
+        "plain_s": round(t_plain, 3), "hybrid_s": round(t_hyb, 3), "rel_l2": rel,
+        "energy_nonincreasing": {"plain": bool(np.all(np.diff(e_plain) <= 0)),
+                                 "hybrid": bool(np.all(np.diff(e_hyb) <= 0)), "samples": len(e_hyb)},
+        "energy_final": {"plain": e_plain[-1], "hybrid": e_hyb[-1]},
+        "stats": totals, "surrogate_train_s": round(train_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,12 +214,26 @@ def main():
     ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per kernel launch")
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["step", "hybrid"], default="step",
+                    help="step: throughput of lbch_step (the default line); hybrid: time-to-t of the jump schedule")
+    ap.add_argument("--hybrid-warm", type=int, default=80000)
+    ap.add_argument("--hybrid-steps", type=int, default=200000)
+    ap.add_argument("--hybrid-jump", type=int, default=200)
+    ap.add_argument("--hybrid-correct", type=int, default=64)
+    ap.add_argument("--hybrid-chunk", type=int, default=10000)
+    ap.add_argument("--hybrid-inner", type=str, default="4,16",
+                    help="inner_steps,inner_jump: projective steps of the populations inside the correction phase")
+    ap.add_argument("--surrogate", action="store_true", help="hybrid: add the trained network's residual")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "hybrid":
+        hybrid_workload(args)
+        return
 
     import torch
 

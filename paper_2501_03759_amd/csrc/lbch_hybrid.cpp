@@ -79,11 +79,11 @@ struct Timer {
 
 extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const lbch_hybrid_opts* o, int64_t nsteps,
                                            lbch_hybrid_stats* stats) {
-    if (!sim || !o || (!net && !o->dry_run)) return fail(LBCH_E_INVALID, "NULL argument");
+    if (!sim || !o || (!net && !o->dry_run && !o->extrapolate)) return fail(LBCH_E_INVALID, "NULL argument");
     if (!sim->initialized) return fail(LBCH_E_STATE, "simulation not initialised");
     if (o->jump < 1 || o->correct_steps < 0 || !(o->tol_energy >= 0) || o->windows < 0 || o->window_interior < 1 ||
         o->window_margin < 0 || !(o->tol_window > 0) || o->check_every < 1 || o->ncond < 0 || o->ncond > 8 ||
-        nsteps < 0)
+        o->inner_steps < 0 || o->inner_jump < 0 || nsteps < 0)
         return fail(LBCH_E_INVALID, "invalid hybrid options");
     const int nx = sim->g.nx, ny = sim->g.ny;
     const long long N = (long long)nx * ny;
@@ -92,11 +92,13 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
     hipStream_t s = sim->stream;
     lbch_hybrid_stats st{};
     Buffers B;
-    void *snap = nullptr, *phi = nullptr, *phin = nullptr, *dsum = nullptr, *part = nullptr, *wphi = nullptr;
+    void *snap = nullptr, *phi = nullptr, *phin = nullptr, *phi1 = nullptr, *dsum = nullptr, *part = nullptr,
+         *wphi = nullptr;
     const size_t fbytes = (size_t)sim->g.plane * 9 * sim->esize;
     HIP_TRY(B.get(&snap, fbytes));
     HIP_TRY(B.get(&phi, N * sizeof(float)));
     HIP_TRY(B.get(&phin, N * sizeof(float)));
+    if (o->extrapolate) HIP_TRY(B.get(&phi1, N * sizeof(float)));
     HIP_TRY(B.get(&dsum, 8 * sizeof(double)));
     HIP_TRY(B.get(&part, (size_t)kRedBlocks * 4 * sizeof(double)));
     lbch_batch* win = nullptr;
@@ -116,18 +118,52 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
     Timer tm(s);
     const int64_t cyc = (int64_t)o->jump + o->correct_steps;
     int64_t left = nsteps;
+    // correction phase: plain steps, optionally with projective steps of the populations
+    const size_t pop_elems = (size_t)sim->g.plane * 9;
+    auto correct = [&](int64_t n) -> lbch_status {
+        int64_t done = 0;
+        if (o->inner_steps > 0 && o->inner_jump > 0) {
+            // the difference spans the last launch: two steps when the plain steps run two per launch
+            const int span = (sim->t.depth == 2 && o->inner_steps % 2 == 0) ? 2 : 1;
+            while (done + 2LL * o->inner_steps + o->inner_jump <= n) {
+                lbch_status ls = lbch_step(sim, o->inner_steps);
+                if (ls != LBCH_OK) return ls;
+                HIP_TRY(launch_extrap_pop(sim->precision, sim->f[sim->cur], sim->f[sim->cur ^ 1],
+                                          (double)o->inner_jump / span, (long long)pop_elems, s));
+                sim->step += o->inner_jump;
+                done += o->inner_steps + o->inner_jump;
+            }
+        }
+        return lbch_step(sim, n - done);
+    };
     double E0 = 0.0, E1 = 0.0;
+    bool have_e0 = false;             // E0 known: the state is the one an accepted cycle ended in
     while (left >= cyc) {
         st.cycles += 1;
-        lbch_status est = lbch_free_energy(sim, &E0, nullptr);
-        if (est != LBCH_OK) return est;
+        if (!have_e0) {
+            lbch_status est = lbch_free_energy(sim, &E0, nullptr);
+            if (est != LBCH_OK) return est;
+        }
         const int64_t step0 = sim->step;
-        // snapshot, prediction, mass projection, re-initialisation
+        // snapshot, jump, mass projection, re-initialisation
         tm.start();
         HIP_TRY(hipMemcpyAsync(snap, sim->f[sim->cur], fbytes, hipMemcpyDeviceToDevice, s));
         if (!o->dry_run) {
             ST_TRY(lbch_phi_device(sim, phi, LBCH_FP32));
-            ST_TRY(lbsg_predict(net, (const float*)phi, o->cond, o->ncond, ny, nx, (float*)phin));
+            if (o->extrapolate) {
+                // rate from one plain step (the state is re-initialised below)
+                ST_TRY(lbch_step(sim, 1));
+                ST_TRY(lbch_phi_device(sim, phi1, LBCH_FP32));
+                const float* base = (const float*)phi;
+                if (net) {
+                    ST_TRY(lbsg_predict(net, (const float*)phi, o->cond, o->ncond, ny, nx, (float*)phin));
+                    base = (const float*)phin;
+                }
+                HIP_TRY(launch_extrap_f32(base, (const float*)phi, (const float*)phi1, (float)o->jump, N,
+                                          (float*)phin, s));
+            } else {
+                ST_TRY(lbsg_predict(net, (const float*)phi, o->cond, o->ncond, ny, nx, (float*)phin));
+            }
             HIP_TRY(launch_sum_f32((const float*)phi, N, (double*)part, (double*)dsum, s));
             HIP_TRY(launch_sum_f32((const float*)phin, N, (double*)part, (double*)dsum + 1, s));
             HIP_TRY(launch_add_f32((float*)phin, N, (const double*)dsum, (const double*)dsum + 1, 1.0 / (double)N, s));
@@ -135,13 +171,17 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
         }
         st.ms_surrogate += tm.stop();
         tm.start();
-        ST_TRY(lbch_step(sim, o->dry_run ? cyc : o->correct_steps));
+        if (o->dry_run) {
+            ST_TRY(lbch_step(sim, cyc));
+        } else {
+            ST_TRY(correct(o->correct_steps));
+        }
         st.ms_correct += tm.stop();
         sim->step = step0 + cyc;
         // checks
         tm.start();
         bool accept = true;
-        est = lbch_free_energy(sim, &E1, nullptr);
+        lbch_status est = lbch_free_energy(sim, &E1, nullptr);
         if (est != LBCH_OK && est != LBCH_E_NONFINITE) return est;
         if (est == LBCH_E_NONFINITE || !(E1 <= E0 * (1.0 + o->tol_energy))) {
             accept = false;
@@ -185,7 +225,10 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
         if (accept) {
             st.accepted += 1;
             st.last_energy = E1;
+            E0 = E1;
+            have_e0 = true;
         } else {
+            have_e0 = false;
             tm.start();
             HIP_TRY(hipMemcpyAsync(sim->f[sim->cur], snap, fbytes, hipMemcpyDeviceToDevice, s));
             sim->step = step0;
@@ -203,5 +246,15 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
     }
     HIP_TRY(hipStreamSynchronize(s));
     if (stats) *stats = st;
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbch_extrapolate(const float* base, const float* phi_t, const float* phi_t1, double k,
+                                        int64_t n, float* out, void* hip_stream) {
+    if (!base || !phi_t || !phi_t1 || !out) return fail(LBCH_E_INVALID, "NULL argument");
+    if (n < 0) return fail(LBCH_E_INVALID, "n = %lld < 0", (long long)n);
+    if (!std::isfinite(k)) return fail(LBCH_E_INVALID, "k is not finite");
+    if (n == 0) return LBCH_OK;
+    HIP_TRY(launch_extrap_f32(base, phi_t, phi_t1, (float)k, n, out, (hipStream_t)hip_stream));
     return LBCH_OK;
 }

@@ -104,6 +104,10 @@ hipError_t launch_add_f32(float* x, long long n, const double* num, const double
                           hipStream_t s);
 hipError_t launch_copy_window(int precision, const void* src, const Grid& sg, int y0, int x0, void* dst,
                               const Grid& dg, hipStream_t s);
+hipError_t launch_extrap_f32(const float* base, const float* a, const float* b, float k, long long n, float* out,
+                             hipStream_t s);
+// cur += k (cur - prev) over `elems` elements (a multiple of 16 bytes) of population storage
+hipError_t launch_extrap_pop(int precision, void* cur, const void* prev, double k, long long elems, hipStream_t s);
 hipError_t launch_window_err(const float* win, int side, const float* big, int ny, int nx, int y0, int x0, int margin,
                              int interior, double* partials, double* out2, hipStream_t s);
 

@@ -1138,6 +1138,26 @@ __global__ void add_f32_k(float* __restrict__ x, long long n, const double* __re
         x[i] += shift;
 }
 
+// out = base + k (b - a): the rate-extrapolated jump (FP32 arithmetic, k exact in FP32 for integer jumps)
+__global__ void extrap_f32_k(const float* base, const float* __restrict__ a, const float* __restrict__ b,
+                             float k, long long n, float* out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = base[i] + k * (b[i] - a[i]);
+}
+
+// cur += k (cur - prev) over the nine population planes (a projective step of
+// the populations themselves; n16 = 16-byte chunks)
+template <typename V, typename T>
+__global__ void extrap_pop_k(V* __restrict__ cur, const V* __restrict__ prev, T k, long long n16) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16;
+         i += (long long)gridDim.x * blockDim.x) {
+        V c = cur[i];
+        const V q = prev[i];
+        c = c + k * (c - q);
+        cur[i] = c;
+    }
+}
+
 // dst (a window grid) <- the 9 population planes of src at rows y0.., columns x0.. (wrapped)
 template <typename T>
 __global__ void copy_window_k(const T* __restrict__ src, const Grid sg, int y0, int x0, T* __restrict__ dst,
@@ -1183,6 +1203,24 @@ hipError_t launch_sum_f32(const float* x, long long n, double* partials, double*
 hipError_t launch_add_f32(float* x, long long n, const double* num, const double* den_minus, double inv_n,
                           hipStream_t s) {
     add_f32_k<<<elementwise_blocks(n), 256, 0, s>>>(x, n, num, den_minus, inv_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_extrap_f32(const float* base, const float* a, const float* b, float k, long long n, float* out,
+                             hipStream_t s) {
+    extrap_f32_k<<<elementwise_blocks(n), 256, 0, s>>>(base, a, b, k, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_extrap_pop(int precision, void* cur, const void* prev, double k, long long elems, hipStream_t s) {
+    if (precision == 0) {
+        const long long n16 = elems / 2;
+        extrap_pop_k<f64x2, double><<<elementwise_blocks(n16), 256, 0, s>>>((f64x2*)cur, (const f64x2*)prev, k, n16);
+    } else {
+        const long long n16 = elems / 4;
+        extrap_pop_k<f32x4, float><<<elementwise_blocks(n16), 256, 0, s>>>((f32x4*)cur, (const f32x4*)prev, (float)k,
+                                                                           n16);
+    }
     return hipGetLastError();
 }
 

@@ -389,7 +389,8 @@ class HybridOpts(ctypes.Structure):
     _fields_ = [("jump", ctypes.c_int32), ("correct_steps", ctypes.c_int32), ("tol_energy", ctypes.c_double),
                 ("windows", ctypes.c_int32), ("window_interior", ctypes.c_int32), ("window_margin", ctypes.c_int32),
                 ("tol_window", ctypes.c_double), ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("ncond", ctypes.c_int32), ("cond", ctypes.c_float * 8), ("dry_run", ctypes.c_int32)]
+                ("ncond", ctypes.c_int32), ("cond", ctypes.c_float * 8), ("dry_run", ctypes.c_int32),
+                ("extrapolate", ctypes.c_int32), ("inner_steps", ctypes.c_int32), ("inner_jump", ctypes.c_int32)]
 
 
 class HybridStats(ctypes.Structure):
@@ -429,3 +430,14 @@ def hybrid_advance(sim: Sim, net, opts: HybridOpts, nsteps: int) -> HybridStats:
     _check(L.lbch_hybrid_advance(sim.handle, net._h if net is not None else None, ctypes.byref(opts), nsteps,
                                  ctypes.byref(st)), "lbch_hybrid_advance")
     return st
+
+
+def extrapolate(base_ptr: int, phi_t_ptr: int, phi_t1_ptr: int, k: float, n: int, out_ptr: int, stream=None):
+    """out = base + k (phi_t1 - phi_t) on FP32 device arrays (lbch_extrapolate)."""
+    L = lib()
+    L.lbch_extrapolate.restype = ctypes.c_int
+    L.lbch_extrapolate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+    _check(L.lbch_extrapolate(ctypes.c_void_p(base_ptr), ctypes.c_void_p(phi_t_ptr), ctypes.c_void_p(phi_t1_ptr), k, n,
+                              ctypes.c_void_p(out_ptr), _stream_handle(stream)), "lbch_extrapolate")
+

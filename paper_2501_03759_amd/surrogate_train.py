@@ -55,8 +55,13 @@ def run_params(spec: RunSpec, side: int, precision=lbch.FP32):
 
 
 def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: int, jump: int, crop: int,
-             crops_per_snapshot: int, seed: int, stream=None, log=print):
-    """Returns device tensors X [N, crop, crop, 1 + N_COND], Y [N, crop, crop] (torch float32)."""
+             crops_per_snapshot: int, seed: int, stream=None, log=print, extrapolate: bool = False,
+             amp: float = 0.05):
+    """Returns device tensors X [N, crop, crop, 1 + N_COND], Y [N, crop, crop] (torch float32).
+
+    Y is phi(t + jump); with extrapolate it is phi(t + jump) - jump (phi(t+1) - phi(t)), the residual
+    the network adds to the rate-extrapolated jump of the hybrid schedule (one plain step gives the
+    rate, as there)."""
     import torch
     rng = np.random.default_rng(seed)
     times = list(range(t_first, t_last + 1, every))
@@ -64,11 +69,15 @@ def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: i
     X = torch.empty((n, crop, crop, 1 + N_COND), dtype=torch.float32, device="cuda")
     Y = torch.empty((n, crop, crop), dtype=torch.float32, device="cuda")
     field = torch.empty((side, side), dtype=torch.float32, device="cuda")
+    per = len(runs) * crops_per_snapshot
+    if extrapolate:
+        T0 = torch.empty((per, crop, crop), dtype=torch.float32, device="cuda")
+        T1 = torch.empty_like(T0)
     params = [run_params(r, side) for r in runs]
     t0 = time.time()
     with lbch.Batch(params, stream) as b:
         for k, r in enumerate(runs):
-            b.init(k, inputs.spinodal(side, side, seed=r.seed, amp=0.05))
+            b.init(k, inputs.spinodal(side, side, seed=r.seed, amp=amp))
         t = 0
         row = 0
         for ts in times:
@@ -84,14 +93,26 @@ def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: i
                 cond = np.tile(conditioning(r.alpha, r.m, r.theta0), (crops_per_snapshot, 1))
                 b.phi_device(k, field.data_ptr(), lbch.FP32)
                 lbsg.gather(field.data_ptr(), side, side, yx, crop, cond,
-                            X[row + k * crops_per_snapshot].data_ptr(), None, stream)
-            b.step(jump)
+                            X[row + k * crops_per_snapshot].data_ptr(),
+                            T0[k * crops_per_snapshot].data_ptr() if extrapolate else None, stream)
+            steps = jump
+            if extrapolate:
+                b.step(1)
+                steps -= 1
+                for k in range(len(runs)):
+                    b.phi_device(k, field.data_ptr(), lbch.FP32)
+                    lbsg.gather(field.data_ptr(), side, side, offsets[k], crop, None, None,
+                                T1[k * crops_per_snapshot].data_ptr(), stream)
+            b.step(steps)
             t += jump
             for k, r in enumerate(runs):
                 b.phi_device(k, field.data_ptr(), lbch.FP32)
                 lbsg.gather(field.data_ptr(), side, side, offsets[k], crop, None, None,
                             Y[row + k * crops_per_snapshot].data_ptr(), stream)
-            row += len(runs) * crops_per_snapshot
+            if extrapolate:
+                lbch.extrapolate(Y[row].data_ptr(), T0.data_ptr(), T1.data_ptr(), -float(jump), per * crop * crop,
+                                 Y[row].data_ptr(), stream)
+            row += per
         b.synchronize()
     log(f"generated {n} pairs ({len(runs)} runs x {len(times)} snapshots x {crops_per_snapshot} crops) "
         f"in {time.time() - t0:.1f} s")
@@ -128,7 +149,9 @@ def train(net: lbsg.Surrogate, X, Y, epochs: int, batch: int, lr: float, margin:
 
 
 def evaluate(net: lbsg.Surrogate, X, Y, margin: int, batch: int = 16):
-    """Relative L2 error on the crop interiors: surrogate vs the identity map phi(t+K) ~ phi(t)."""
+    """Relative L2 error on the crop interiors: the network vs its input phi(t) as the prediction
+    (the identity map phi(t+K) ~ phi(t); for residual targets of generate(extrapolate=True), the
+    rate-extrapolated jump without the network)."""
     import torch
     n, crop = X.shape[0], X.shape[1]
     out = torch.empty((batch, crop, crop), dtype=torch.float32, device="cuda")

@@ -78,3 +78,66 @@ def test_accepted_jumps_conserve_mass_and_do_not_raise_energy():
     _, m1, _, _ = sim.moments(want_phi=False)
     assert abs(m1 - m0) <= 1e-3 * np.abs(sim.phi()).sum() * 1e-3
     assert np.all(np.diff(energies) <= 1e-3 * abs(energies[0]))
+
+
+def separated_sim(n, stream, steps=4000, seed=7):
+    # a phase-separated (coarsening) state: larger initial noise separates within a few
+    # thousand steps
+    L = lb()
+    d = inputs.C5
+    p = common.make_params(n, n, 1, eps_w=d["eps_w"], mobility=d["mobility"], alpha=d["alpha"], eps_reg=d["eps_reg"])
+    s = L.Sim(p, stream)
+    s.init(inputs.spinodal(n, n, seed=seed, amp=0.5))
+    s.step(steps)
+    return s
+
+
+@pytest.mark.parametrize("inner", [(0, 0), (4, 12)])
+def test_extrapolated_jumps_track_plain_run(inner):
+    # projective jumps (rate from one plain step, linear extrapolation, no network), with plain or
+    # projectively accelerated correction steps: every cycle accepted, mass kept to FP32
+    # round-off, the free energy does not rise between cycles and the field stays close to the
+    # plain run
+    import torch
+    L = lb()
+    stream = torch.cuda.Stream()
+    n = 256
+    a = separated_sim(n, stream)
+    b = separated_sim(n, stream)
+    _, m0, _, _ = a.moments(want_phi=False)
+    o = L.hybrid_opts(jump=60, correct_steps=30, windows=2, window_interior=64, window_margin=32, tol_window=1e-2,
+                      tol_energy=0.0, extrapolate=1, inner_steps=inner[0], inner_jump=inner[1])
+    energies = [a.free_energy()[0]]
+    accepted = 0
+    for _ in range(10):
+        st = L.hybrid_advance(a, None, o, 90)
+        accepted += st.accepted
+        assert st.cycles == 1 and st.max_window_err < 1e-2
+        energies.append(a.free_energy()[0])
+    b.step(900)
+    assert a.nstep == b.nstep == 4900
+    _, m1, _, _ = a.moments(want_phi=False)
+    pa, pb = a.phi(), b.phi()
+    rel = np.linalg.norm(pa - pb) / np.linalg.norm(pb)
+    print(f"accepted {accepted}/10, rel-L2 to plain {rel:.3e}, energies {energies[0]:.6f} -> {energies[-1]:.6f}")
+    assert accepted == 10
+    assert abs(m1 - m0) <= 1e-6 * np.abs(pa).sum()
+    assert np.all(np.diff(energies) <= 0.0)
+    assert rel < 5e-3
+
+
+def test_zero_residual_network_leaves_extrapolation_unchanged():
+    # an untrained network (zero head) adds an exactly zero residual to the extrapolated jump
+    import torch
+    from paper_2501_03759_amd import lbsg
+    L = lb()
+    stream = torch.cuda.Stream()
+    n = 128
+    a = separated_sim(n, stream, steps=3000)
+    b = separated_sim(n, stream, steps=3000)
+    net = lbsg.Surrogate((32, 32), 1, 1, n, n, train=False, seed=1, stream=stream)
+    o = L.hybrid_opts(jump=40, correct_steps=20, windows=0, tol_energy=1e-3, extrapolate=1)
+    sa = L.hybrid_advance(a, None, o, 3 * 60)
+    sb = L.hybrid_advance(b, net, o, 3 * 60)
+    assert sa.accepted == sb.accepted == 3
+    assert np.array_equal(a.phi(), b.phi())
