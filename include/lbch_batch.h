@@ -4,7 +4,8 @@
  * A batch holds `count` periodic D2Q9 grids of the anisotropic Cahn-Hilliard
  * lattice Boltzmann scheme (each member with its own grid size and its own
  * physical parameters of Sections 2-3, all in one precision) and advances all
- * of them with ONE persistent kernel launch per time step; chunks of steps are
+ * of them with ONE persistent kernel launch per time step, or per two time
+ * steps (the default, as lbch_set_time_blocking); chunks of launches are
  * replayed from a captured HIP graph when the batch has its own stream.  The
  * update applied to every member is exactly the lbch_step update (include
  * /lbch.h): a member's result is bitwise identical to a standalone simulation
@@ -55,7 +56,14 @@ lbch_status lbch_batch_moments(lbch_batch* batch, int32_t member, double* phi_ou
 lbch_status lbch_batch_free_energy(lbch_batch* batch, int32_t member, double* energy, double* terms4);
 lbch_status lbch_batch_phi_device(lbch_batch* batch, int32_t member, void* dst_dev, int32_t dtype);
 
-/* Launch shape: block_threads in {64, 128, 256, 512} for every member,
+/* Time steps per launch, 1 or 2 (default 2; an odd remainder of
+ * lbch_batch_step runs one single-step launch).  Bitwise identical results.
+ * depth not in {1, 2} -> LBCH_E_INVALID. */
+lbch_status lbch_batch_set_time_blocking(lbch_batch* batch, int32_t depth);
+lbch_status lbch_batch_get_time_blocking(const lbch_batch* batch, int32_t* depth);
+
+/* Launch shape of the current depth: block_threads in {64, 128, 256, 512}
+ * ({128, 256, 512} at depth 2, at most 256 in FP64) for every member,
  * rows_per_block >= 1 rows per tile (0 = default), persistent_blocks
  * workgroups in the persistent grid (0 = fill every CU).  Bitwise
  * independent of the choice. */
@@ -64,9 +72,10 @@ lbch_status lbch_batch_set_tiling(lbch_batch* batch, int32_t block_threads, int3
 lbch_status lbch_batch_get_tiling(const lbch_batch* batch, int32_t* block_threads, int32_t* rows_per_block,
                                   int32_t* persistent_blocks, int32_t* total_tiles);
 
-/* Times launch shapes (block_threads x rows_per_block) for this batch with
- * steps_per_trial launches each (writing the idle buffer: the state and step
- * counter are unchanged), keeps the fastest.  Synchronises. */
+/* Times launch shapes (depth x block_threads x rows_per_block) for this
+ * batch with steps_per_trial launches each (writing the idle buffer: the
+ * state and step counter are unchanged), keeps the fastest per step (and the
+ * fastest single-step shape for odd remainders).  Synchronises. */
 lbch_status lbch_batch_autotune(lbch_batch* batch, int32_t steps_per_trial, int32_t* block_threads,
                                 int32_t* rows_per_block, double* ms_per_step);
 

@@ -22,7 +22,16 @@ using namespace lbch;
 
 namespace {
 
-constexpr int kGraphSteps = 16;   // launches per captured graph (even: buffer parity preserved)
+constexpr int kGraphLaunches = 16;   // launches per captured graph (even: buffer parity preserved)
+
+// Launch configuration of one depth (time steps per launch): descriptors, the
+// tile -> member list and the persistent grid.
+struct BatchConfig {
+    int nt = 128, hc_user = 0, blocks_user = 0;
+    int total_tiles = 0, nblocks = 0;
+    void* d_members = nullptr;       // BatchMember<T>[count]
+    int* d_tile_member = nullptr;    // int[total_tiles]
+};
 
 struct Member {
     lbch_params p;
@@ -46,12 +55,10 @@ struct lbch_batch {
     int64_t step = 0;
     long long total_elems = 0;
     // tiling
-    int nt = 128, hc_user = 0, blocks_user = 0;
-    int total_tiles = 0, nblocks = 0;
+    int depth = 2;                   // time steps per launch (odd remainders use depth 1)
+    BatchConfig cfg[2];              // index depth - 1
     bool unit_all = true;
-    void* d_members = nullptr;       // BatchMember<T>[count]
-    int* d_tile_member = nullptr;    // int[total_tiles]
-    unsigned long long* d_counter = nullptr;
+    unsigned long long* d_counter = nullptr;   // work-queue counters, one per depth
     bool counter_dirty = true;
     // reductions
     double* phi64 = nullptr;
@@ -76,18 +83,19 @@ void drop_graphs(lbch_batch* b) {
 
 void free_all(lbch_batch* b) {
     drop_graphs(b);
-    for (void* p : {b->f[0], b->f[1], (void*)b->d_members, (void*)b->d_tile_member, (void*)b->d_counter,
+    for (void* p : {b->f[0], b->f[1], (void*)b->cfg[0].d_members, (void*)b->cfg[0].d_tile_member,
+                    (void*)b->cfg[1].d_members, (void*)b->cfg[1].d_tile_member, (void*)b->d_counter,
                     (void*)b->phi64, (void*)b->partials, (void*)b->result, (void*)b->bad})
         if (p) (void)hipFree(p);
 }
 
 template <typename T>
-BatchMember<T> make_desc(const Member& mm, const StepCoef<T>& c, int hc, int nt, int tile_begin) {
+BatchMember<T> make_desc(const Member& mm, const StepCoef<T>& c, int hc, int nt, int depth, int tile_begin) {
     BatchMember<T> d{};
     d.g = mm.g;
     d.base = mm.base;
     d.c = c;
-    const int W = nt - 8;
+    const int W = nt - 8 * depth;
     d.strips = (mm.g.nx + W - 1) / W;
     d.hc = std::min(hc, mm.g.ny);
     d.chunks = (mm.g.ny + d.hc - 1) / d.hc;
@@ -95,10 +103,11 @@ BatchMember<T> make_desc(const Member& mm, const StepCoef<T>& c, int hc, int nt,
     return d;
 }
 
-// (Re)builds descriptors, the tile list (largest members first) and the persistent grid.
-lbch_status configure(lbch_batch* b, int nt, int hc_user, int blocks_user) {
+// (Re)builds descriptors, the tile list (largest members first) and the persistent grid of one depth.
+lbch_status configure(lbch_batch* b, int depth, int nt, int hc_user, int blocks_user) {
     const int n = (int)b->m.size();
-    const int hc_default = 32;
+    BatchConfig& cf = b->cfg[depth - 1];
+    const int hc_default = depth == 2 ? 64 : 32;   // a two-step sweep restarts 14 rows per chunk
     const int hc = hc_user > 0 ? hc_user : hc_default;
     // order members by work, largest first, so the queue ends on small tiles
     std::vector<int> order(n);
@@ -112,33 +121,33 @@ lbch_status configure(lbch_batch* b, int nt, int hc_user, int blocks_user) {
     int tb = 0;
     for (int k : order) {
         const Member& mm = b->m[k];
-        dd[k] = make_desc<double>(mm, mm.cd, hc, nt, tb);
-        df[k] = make_desc<float>(mm, mm.cf, hc, nt, tb);
+        dd[k] = make_desc<double>(mm, mm.cd, hc, nt, depth, tb);
+        df[k] = make_desc<float>(mm, mm.cf, hc, nt, depth, tb);
         const int nt_tiles = dd[k].strips * dd[k].chunks;
         tile_member.insert(tile_member.end(), nt_tiles, k);
         tb += nt_tiles;
     }
-    b->total_tiles = tb;
+    cf.total_tiles = tb;
     drop_graphs(b);
-    if (b->d_members) (void)hipFree(b->d_members);
-    if (b->d_tile_member) (void)hipFree(b->d_tile_member);
-    b->d_members = nullptr;
-    b->d_tile_member = nullptr;
+    if (cf.d_members) (void)hipFree(cf.d_members);
+    if (cf.d_tile_member) (void)hipFree(cf.d_tile_member);
+    cf.d_members = nullptr;
+    cf.d_tile_member = nullptr;
     const size_t desc_bytes = b->precision == LBCH_FP64 ? n * sizeof(BatchMember<double>) : n * sizeof(BatchMember<float>);
-    HIP_TRY(hipMalloc(&b->d_members, desc_bytes));
-    HIP_TRY(hipMalloc((void**)&b->d_tile_member, tile_member.size() * sizeof(int)));
-    HIP_TRY(hipMemcpy(b->d_members, b->precision == LBCH_FP64 ? (const void*)dd.data() : (const void*)df.data(),
+    HIP_TRY(hipMalloc(&cf.d_members, desc_bytes));
+    HIP_TRY(hipMalloc((void**)&cf.d_tile_member, tile_member.size() * sizeof(int)));
+    HIP_TRY(hipMemcpy(cf.d_members, b->precision == LBCH_FP64 ? (const void*)dd.data() : (const void*)df.data(),
                       desc_bytes, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->d_tile_member, tile_member.data(), tile_member.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(cf.d_tile_member, tile_member.data(), tile_member.size() * sizeof(int), hipMemcpyHostToDevice));
     b->unit_all = true;
     for (const Member& mm : b->m)
         if (!(b->precision == LBCH_FP64 ? mm.cd.unit : mm.cf.unit)) b->unit_all = false;
-    int per_cu = batch_blocks_per_cu(b->precision, nt, b->unit_all);
+    int per_cu = batch_blocks_per_cu(b->precision, depth, nt, b->unit_all);
     int blocks = blocks_user > 0 ? blocks_user : per_cu * b->num_cus;
-    b->nblocks = std::max(1, std::min(blocks, b->total_tiles));
-    b->nt = nt;
-    b->hc_user = hc_user;
-    b->blocks_user = blocks_user;
+    cf.nblocks = std::max(1, std::min(blocks, cf.total_tiles));
+    cf.nt = nt;
+    cf.hc_user = hc_user;
+    cf.blocks_user = blocks_user;
     b->counter_dirty = true;
     return ok();
 }
@@ -165,15 +174,20 @@ const void* coef_of(const lbch_batch* b, int member) {
     return b->precision == LBCH_FP64 ? (const void*)&b->m[member].cd : (const void*)&b->m[member].cf;
 }
 
-lbch_status launch_one(lbch_batch* b, int from) {
-    HIP_TRY(launch_batch_step(b->precision, b->nt, b->unit_all, b->f[from], b->f[from ^ 1], b->d_members,
-                              b->d_tile_member, b->total_tiles, b->nblocks, b->d_counter, b->stream));
+hipError_t launch_depth(lbch_batch* b, int depth, int from) {
+    const BatchConfig& cf = b->cfg[depth - 1];
+    return launch_batch_step(b->precision, depth, cf.nt, b->unit_all, b->f[from], b->f[from ^ 1], cf.d_members,
+                             cf.d_tile_member, cf.total_tiles, cf.nblocks, b->d_counter + (depth - 1), b->stream);
+}
+
+lbch_status launch_one(lbch_batch* b, int depth, int from) {
+    HIP_TRY(launch_depth(b, depth, from));
     return ok();
 }
 
 lbch_status reset_counter(lbch_batch* b) {
     if (b->counter_dirty) {
-        HIP_TRY(launch_zero_u64(b->d_counter, 1, b->stream));
+        HIP_TRY(launch_zero_u64(b->d_counter, 2, b->stream));
         b->counter_dirty = false;
     }
     return ok();
@@ -224,7 +238,7 @@ extern "C" lbch_status lbch_batch_create(const lbch_params* members, int32_t cou
     if (e == hipSuccess) e = hipMalloc((void**)&b->partials, (size_t)kRedBlocks * 4 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&b->result, 8 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&b->bad, count * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 2 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(b->bad, 0, count * sizeof(unsigned));
     if (e != hipSuccess) {
         free_all(b);
@@ -233,7 +247,8 @@ extern "C" lbch_status lbch_batch_create(const lbch_params* members, int32_t cou
         return fail(e == hipErrorOutOfMemory ? LBCH_E_OOM : LBCH_E_DEVICE, "batch allocation failed: %s",
                     hipGetErrorString(e));
     }
-    lbch_status st = configure(b, 128, 0, 0);
+    lbch_status st = configure(b, 1, 128, 0, 0);
+    if (st == LBCH_OK) st = configure(b, 2, 128, 0, 0);
     if (st != LBCH_OK) {
         free_all(b);
         delete b;
@@ -288,16 +303,16 @@ extern "C" lbch_status lbch_batch_step(lbch_batch* b, int64_t nsteps) {
     if (nsteps < 0) return fail(LBCH_E_INVALID, "nsteps = %lld < 0", (long long)nsteps);
     st = reset_counter(b);
     if (st != LBCH_OK) return st;
+    const int depth = b->depth;
+    const int64_t graph_steps = (int64_t)kGraphLaunches * depth;
     int64_t left = nsteps;
-    if (b->stream != nullptr && left >= kGraphSteps) {
+    if (b->stream != nullptr && left >= graph_steps) {
         if (!b->exec[b->cur]) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             int from = b->cur;
-            for (int k = 0; k < kGraphSteps; ++k) {
-                hipError_t e = launch_batch_step(b->precision, b->nt, b->unit_all, b->f[from], b->f[from ^ 1],
-                                                 b->d_members, b->d_tile_member, b->total_tiles, b->nblocks,
-                                                 b->d_counter, b->stream);
+            for (int k = 0; k < kGraphLaunches; ++k) {
+                hipError_t e = launch_depth(b, depth, from);
                 if (e != hipSuccess) {
                     (void)hipStreamEndCapture(b->stream, &graph);
                     if (graph) (void)hipGraphDestroy(graph);
@@ -310,17 +325,19 @@ extern "C" lbch_status lbch_batch_step(lbch_batch* b, int64_t nsteps) {
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return fail(LBCH_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
         }
-        while (left >= kGraphSteps) {
+        while (left >= graph_steps) {
             HIP_TRY(hipGraphLaunch(b->exec[b->cur], b->stream));
-            left -= kGraphSteps;
-            b->step += kGraphSteps;
+            left -= graph_steps;
+            b->step += graph_steps;
         }
     }
-    for (; left > 0; --left) {
-        st = launch_one(b, b->cur);
+    while (left > 0) {
+        const int d = left >= depth ? depth : 1;
+        st = launch_one(b, d, b->cur);
         if (st != LBCH_OK) return st;
         b->cur ^= 1;
-        b->step += 1;
+        b->step += d;
+        left -= d;
     }
     return ok();
 }
@@ -410,24 +427,41 @@ extern "C" lbch_status lbch_batch_phi_device(lbch_batch* b, int32_t member, void
     return ok();
 }
 
+extern "C" lbch_status lbch_batch_set_time_blocking(lbch_batch* b, int32_t depth) {
+    if (!b) return fail(LBCH_E_INVALID, "batch handle is NULL");
+    if (depth != 1 && depth != 2) return fail(LBCH_E_INVALID, "time-blocking depth %d not in {1, 2}", depth);
+    if (depth != b->depth) drop_graphs(b);
+    b->depth = depth;
+    return ok();
+}
+
+extern "C" lbch_status lbch_batch_get_time_blocking(const lbch_batch* b, int32_t* depth) {
+    if (!b || !depth) return fail(LBCH_E_INVALID, "NULL argument");
+    *depth = b->depth;
+    return ok();
+}
+
 extern "C" lbch_status lbch_batch_set_tiling(lbch_batch* b, int32_t block_threads, int32_t rows_per_block,
                                              int32_t persistent_blocks) {
     if (!b) return fail(LBCH_E_INVALID, "batch handle is NULL");
     if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256 &&
         block_threads != 512)
         return fail(LBCH_E_INVALID, "block_threads %d not in {64, 128, 256, 512}", block_threads);
+    if (b->depth == 2 && (block_threads == 64 || (b->precision == LBCH_FP64 && block_threads == 512)))
+        return fail(LBCH_E_INVALID, "block_threads %d not available at time-blocking depth 2", block_threads);
     if (rows_per_block < 0 || persistent_blocks < 0) return fail(LBCH_E_INVALID, "negative tiling argument");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    return configure(b, block_threads ? block_threads : 128, rows_per_block, persistent_blocks);
+    return configure(b, b->depth, block_threads ? block_threads : 128, rows_per_block, persistent_blocks);
 }
 
 extern "C" lbch_status lbch_batch_get_tiling(const lbch_batch* b, int32_t* block_threads, int32_t* rows_per_block,
                                              int32_t* persistent_blocks, int32_t* total_tiles) {
     if (!b) return fail(LBCH_E_INVALID, "batch handle is NULL");
-    if (block_threads) *block_threads = b->nt;
-    if (rows_per_block) *rows_per_block = b->hc_user > 0 ? b->hc_user : 32;
-    if (persistent_blocks) *persistent_blocks = b->nblocks;
-    if (total_tiles) *total_tiles = b->total_tiles;
+    const BatchConfig& cf = b->cfg[b->depth - 1];
+    if (block_threads) *block_threads = cf.nt;
+    if (rows_per_block) *rows_per_block = cf.hc_user > 0 ? cf.hc_user : (b->depth == 2 ? 64 : 32);
+    if (persistent_blocks) *persistent_blocks = cf.nblocks;
+    if (total_tiles) *total_tiles = cf.total_tiles;
     return ok();
 }
 
@@ -448,43 +482,51 @@ extern "C" lbch_status lbch_batch_autotune(lbch_batch* b, int32_t steps_per_tria
     hipEvent_t a = nullptr, e2 = nullptr;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&e2));
-    float best = -1.0f;
-    int best_nt = b->nt, best_hc = b->hc_user;
-    for (int nt : {64, 128, 256}) {
-        for (int hc : {16, 32, 64, 128}) {
-            st = configure(b, nt, hc, b->blocks_user);
-            if (st == LBCH_OK) st = reset_counter(b);
+    float best[2] = {-1.0f, -1.0f};                 // per step, per depth
+    int best_nt[2] = {b->cfg[0].nt, b->cfg[1].nt}, best_hc[2] = {b->cfg[0].hc_user, b->cfg[1].hc_user};
+    for (int depth = 1; depth <= 2 && st == LBCH_OK; ++depth) {
+        for (int nt : {64, 128, 256}) {
+            if (depth == 2 && nt == 64) continue;
+            for (int hc : {16, 32, 64, 128}) {
+                if (depth == 2 && hc < 32) continue;
+                st = configure(b, depth, nt, hc, b->cfg[depth - 1].blocks_user);
+                if (st == LBCH_OK) st = reset_counter(b);
+                if (st != LBCH_OK) break;
+                // trials: state in f[cur] -> idle buffer, never swapped
+                st = launch_one(b, depth, b->cur);
+                hipError_t e = st == LBCH_OK ? hipEventRecord(a, b->stream) : hipErrorUnknown;
+                for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k) e = launch_depth(b, depth, b->cur);
+                if (e == hipSuccess) e = hipEventRecord(e2, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e2);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, e2);
+                if (e != hipSuccess) {
+                    st = fail(LBCH_E_DEVICE, "batch autotune trial failed: %s", hipGetErrorString(e));
+                    break;
+                }
+                ms /= (float)depth;
+                if (best[depth - 1] < 0.0f || ms < best[depth - 1]) {
+                    best[depth - 1] = ms;
+                    best_nt[depth - 1] = nt;
+                    best_hc[depth - 1] = hc;
+                }
+            }
             if (st != LBCH_OK) break;
-            // trials: state in f[cur] -> idle buffer, never swapped
-            st = launch_one(b, b->cur);
-            hipError_t e = st == LBCH_OK ? hipEventRecord(a, b->stream) : hipErrorUnknown;
-            for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k)
-                e = launch_batch_step(b->precision, b->nt, b->unit_all, b->f[b->cur], b->f[b->cur ^ 1], b->d_members,
-                                      b->d_tile_member, b->total_tiles, b->nblocks, b->d_counter, b->stream);
-            if (e == hipSuccess) e = hipEventRecord(e2, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e2);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, e2);
-            if (e != hipSuccess) {
-                st = fail(LBCH_E_DEVICE, "batch autotune trial failed: %s", hipGetErrorString(e));
-                break;
-            }
-            if (best < 0.0f || ms < best) {
-                best = ms;
-                best_nt = nt;
-                best_hc = hc;
-            }
         }
-        if (st != LBCH_OK) break;
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(e2);
     if (st != LBCH_OK) return st;
-    st = configure(b, best_nt, best_hc, b->blocks_user);
-    if (st != LBCH_OK) return st;
-    if (block_threads) *block_threads = best_nt;
-    if (rows_per_block) *rows_per_block = best_hc;
-    if (ms_per_step) *ms_per_step = best / steps_per_trial;
+    for (int depth = 1; depth <= 2; ++depth) {
+        st = configure(b, depth, best_nt[depth - 1], best_hc[depth - 1], b->cfg[depth - 1].blocks_user);
+        if (st != LBCH_OK) return st;
+    }
+    const int d = (best[1] >= 0.0f && best[1] < best[0]) ? 2 : 1;
+    if (d != b->depth) drop_graphs(b);
+    b->depth = d;
+    if (block_threads) *block_threads = best_nt[d - 1];
+    if (rows_per_block) *rows_per_block = best_hc[d - 1];
+    if (ms_per_step) *ms_per_step = best[d - 1] / steps_per_trial;
     return ok();
 }
 

@@ -80,11 +80,12 @@ struct BatchMember {
     int strips, hc, chunks, tile_begin;
 };
 
-hipError_t launch_batch_step(int precision, int nt, bool unit_all, const void* fin, void* fout, const void* members,
-                             const int* tile_member, int total_tiles, int nblocks, unsigned long long* ctr,
-                             hipStream_t s);
+// depth: time steps per launch (1 or 2); members' strips are nt - 8 * depth columns wide
+hipError_t launch_batch_step(int precision, int depth, int nt, bool unit_all, const void* fin, void* fout,
+                             const void* members, const int* tile_member, int total_tiles, int nblocks,
+                             unsigned long long* ctr, hipStream_t s);
 // resident workgroups per CU of the batch kernel (for sizing its persistent grid)
-int batch_blocks_per_cu(int precision, int nt, bool unit_all);
+int batch_blocks_per_cu(int precision, int depth, int nt, bool unit_all);
 // resident workgroups per CU of the step kernel of the given depth and shape
 int step_blocks_per_cu(int precision, int depth, int nt, bool unit, bool staged);
 

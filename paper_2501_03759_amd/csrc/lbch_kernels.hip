@@ -649,16 +649,26 @@ __global__ __launch_bounds__(NT) void step2_fused(const T* __restrict__ fin, T* 
 // between launches and works unchanged inside a captured graph.  Every
 // workgroup leaves the loop after its first take past the end.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, bool UNIT_ALL>
+template <typename T, int NT, int DEPTH>
+struct BatchLds;
+template <typename T, int NT>
+struct BatchLds<T, NT, 1> {
+    T phi[3][NT], qx[3][NT], qy[3][NT], w[3][NT], mb[3][NT];
+};
+template <typename T, int NT>
+struct BatchLds<T, NT, 2> {
+    Pass2Lds<T, NT> L1, L2;
+    T s13[2][2][NT], s56[3][2][NT], s78[2][NT];
+};
+
+// DEPTH time steps per launch (1 or 2); members' tiles are strips of
+// NT - 8 * DEPTH columns.
+template <typename T, int NT, bool UNIT_ALL, int DEPTH>
 __global__ __launch_bounds__(NT) void batch_step(const T* __restrict__ fin, T* __restrict__ fout,
                                                  const BatchMember<T>* __restrict__ members,
                                                  const int* __restrict__ tile_member, const int total_tiles,
                                                  unsigned long long* __restrict__ counter) {
-    __shared__ T s_phi[3][NT];
-    __shared__ T s_qx[3][NT];
-    __shared__ T s_qy[3][NT];
-    __shared__ T s_w[3][NT];
-    __shared__ T s_mb[3][NT];
+    __shared__ BatchLds<T, NT, DEPTH> sh;
     __shared__ int s_tile;
     const unsigned long long period = (unsigned long long)total_tiles + gridDim.x;
     for (;;) {
@@ -673,17 +683,27 @@ __global__ __launch_bounds__(NT) void batch_step(const T* __restrict__ fin, T* _
         const int local = tile - d.tile_begin;
         const int strip = local % d.strips;
         const int chunk = local / d.strips;
-        const int W = NT - 8;
+        constexpr int W = NT - 8 * DEPTH;
         const int x0 = strip * W;
         const int y0 = chunk * d.hc;
         const T* mfin = fin + d.base;
         T* mfout = fout + d.base;
-        if (UNIT_ALL || c.unit)
-            sweep_strip<T, NT, true, false>(mfin, mfout, g, x0, min(W, g.nx - x0), y0, min(d.hc, g.ny - y0), c,
-                                            s_phi, s_qx, s_qy, s_w, s_mb, nullptr);
-        else
-            sweep_strip<T, NT, false, false>(mfin, mfout, g, x0, min(W, g.nx - x0), y0, min(d.hc, g.ny - y0), c,
-                                             s_phi, s_qx, s_qy, s_w, s_mb, nullptr);
+        const int wl = min(W, g.nx - x0), hl = min(d.hc, g.ny - y0);
+        if constexpr (DEPTH == 1) {
+            if (UNIT_ALL || c.unit)
+                sweep_strip<T, NT, true, false>(mfin, mfout, g, x0, wl, y0, hl, c, sh.phi, sh.qx, sh.qy, sh.w, sh.mb,
+                                                nullptr);
+            else
+                sweep_strip<T, NT, false, false>(mfin, mfout, g, x0, wl, y0, hl, c, sh.phi, sh.qx, sh.qy, sh.w, sh.mb,
+                                                 nullptr);
+        } else {
+            if (UNIT_ALL || c.unit)
+                sweep_strip2<T, NT, true, false>(mfin, mfout, g, x0, wl, y0, hl, c, sh.L1, sh.L2, sh.s13, sh.s56,
+                                                 sh.s78, nullptr);
+            else
+                sweep_strip2<T, NT, false, false>(mfin, mfout, g, x0, wl, y0, hl, c, sh.L1, sh.L2, sh.s13, sh.s56,
+                                                  sh.s78, nullptr);
+        }
         __syncthreads();
     }
 }
@@ -953,44 +973,80 @@ hipError_t launch_step(int precision, const void* fin, void* fout, const Grid& g
 }
 
 
-template <typename T, bool UA>
-static hipError_t launch_batch_t(int nt, const T* fin, T* fout, const BatchMember<T>* m, const int* tm, int total,
+template <typename T, bool UA, int D>
+static hipError_t launch_batch_d(int nt, const T* fin, T* fout, const BatchMember<T>* m, const int* tm, int total,
                                  int nblocks, unsigned long long* ctr, hipStream_t s) {
     switch (nt) {
-        case 64: batch_step<T, 64, UA><<<nblocks, 64, 0, s>>>(fin, fout, m, tm, total, ctr); break;
-        case 128: batch_step<T, 128, UA><<<nblocks, 128, 0, s>>>(fin, fout, m, tm, total, ctr); break;
-        case 256: batch_step<T, 256, UA><<<nblocks, 256, 0, s>>>(fin, fout, m, tm, total, ctr); break;
-        case 512: batch_step<T, 512, UA><<<nblocks, 512, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        case 64:
+            if constexpr (D == 1) {
+                batch_step<T, 64, UA, D><<<nblocks, 64, 0, s>>>(fin, fout, m, tm, total, ctr);
+                break;
+            } else {
+                return hipErrorInvalidValue;
+            }
+        case 128: batch_step<T, 128, UA, D><<<nblocks, 128, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        case 256: batch_step<T, 256, UA, D><<<nblocks, 256, 0, s>>>(fin, fout, m, tm, total, ctr); break;
+        case 512:
+            // the float64 rings of a two-step sweep of 512 lanes exceed the LDS of one workgroup
+            if constexpr (D == 1 || sizeof(T) == 4) {
+                batch_step<T, 512, UA, D><<<nblocks, 512, 0, s>>>(fin, fout, m, tm, total, ctr);
+                break;
+            } else {
+                return hipErrorInvalidValue;
+            }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int precision, int nt, bool unit_all, const void* fin, void* fout, const void* members,
-                             const int* tile_member, int total_tiles, int nblocks, unsigned long long* ctr,
-                             hipStream_t s) {
+template <typename T, bool UA>
+static hipError_t launch_batch_t(int depth, int nt, const T* fin, T* fout, const BatchMember<T>* m, const int* tm,
+                                 int total, int nblocks, unsigned long long* ctr, hipStream_t s) {
+    if (depth == 2) return launch_batch_d<T, UA, 2>(nt, fin, fout, m, tm, total, nblocks, ctr, s);
+    if (depth == 1) return launch_batch_d<T, UA, 1>(nt, fin, fout, m, tm, total, nblocks, ctr, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(int precision, int depth, int nt, bool unit_all, const void* fin, void* fout,
+                             const void* members, const int* tile_member, int total_tiles, int nblocks,
+                             unsigned long long* ctr, hipStream_t s) {
     if (precision == 0) {
         auto f = unit_all ? launch_batch_t<double, true> : launch_batch_t<double, false>;
-        return f(nt, (const double*)fin, (double*)fout, (const BatchMember<double>*)members, tile_member,
+        return f(depth, nt, (const double*)fin, (double*)fout, (const BatchMember<double>*)members, tile_member,
                  total_tiles, nblocks, ctr, s);
     }
     auto f = unit_all ? launch_batch_t<float, true> : launch_batch_t<float, false>;
-    return f(nt, (const float*)fin, (float*)fout, (const BatchMember<float>*)members, tile_member, total_tiles,
+    return f(depth, nt, (const float*)fin, (float*)fout, (const BatchMember<float>*)members, tile_member, total_tiles,
              nblocks, ctr, s);
 }
 
-template <typename T, bool UA>
-static int occ_t(int nt) {
+template <typename T, bool UA, int D>
+static int occ_d(int nt) {
     int n = 0;
-    hipError_t e = hipSuccess;
+    hipError_t e = hipErrorInvalidValue;
     switch (nt) {
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 64, UA>, 64, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 128, UA>, 128, 0); break;
-        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 256, UA>, 256, 0); break;
-        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 512, UA>, 512, 0); break;
-        default: return 1;
+        case 64:
+            if constexpr (D == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 64, UA, D>, 64, 0);
+            break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 128, UA, D>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 256, UA, D>, 256, 0); break;
+        case 512:
+            if constexpr (D == 1 || sizeof(T) == 4)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step<T, 512, UA, D>, 512, 0);
+            break;
+        default: break;
     }
     return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+template <typename T, bool UA>
+static int occ_t(int depth, int nt) {
+    return depth == 2 ? occ_d<T, UA, 2>(nt) : occ_d<T, UA, 1>(nt);
+}
+
+int batch_blocks_per_cu(int precision, int depth, int nt, bool unit_all) {
+    if (precision == 0) return unit_all ? occ_t<double, true>(depth, nt) : occ_t<double, false>(depth, nt);
+    return unit_all ? occ_t<float, true>(depth, nt) : occ_t<float, false>(depth, nt);
 }
 
 template <typename T, bool UNIT, bool STAGED>
@@ -1023,11 +1079,6 @@ int step_blocks_per_cu(int precision, int depth, int nt, bool unit, bool staged)
     if (precision == 0) return unit ? occ_step_t<double, true, false>(depth, nt) : occ_step_t<double, false, false>(depth, nt);
     if (staged) return unit ? occ_step_t<float, true, true>(depth, nt) : occ_step_t<float, false, true>(depth, nt);
     return unit ? occ_step_t<float, true, false>(depth, nt) : occ_step_t<float, false, false>(depth, nt);
-}
-
-int batch_blocks_per_cu(int precision, int nt, bool unit_all) {
-    if (precision == 0) return unit_all ? occ_t<double, true>(nt) : occ_t<double, false>(nt);
-    return unit_all ? occ_t<float, true>(nt) : occ_t<float, false>(nt);
 }
 
 hipError_t launch_init(int precision, const void* phi0, int phi_dtype, void* fout, const Grid& g, const void* coef,

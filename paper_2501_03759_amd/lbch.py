@@ -111,6 +111,8 @@ _SIGNATURES = {
     "lbch_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "lbch_batch_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "lbch_batch_set_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "lbch_batch_get_time_blocking": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "lbch_diag_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
 }
 
@@ -377,6 +379,14 @@ class Batch:
         _check(lib().lbch_batch_autotune(self._h, steps_per_trial, ctypes.byref(a), ctypes.byref(r),
                                          ctypes.byref(ms)), "lbch_batch_autotune")
         return a.value, r.value, ms.value
+
+    def set_time_blocking(self, depth: int):
+        _check(lib().lbch_batch_set_time_blocking(self._h, depth), "lbch_batch_set_time_blocking")
+
+    def time_blocking(self) -> int:
+        d = ctypes.c_int32()
+        _check(lib().lbch_batch_get_time_blocking(self._h, ctypes.byref(d)), "lbch_batch_get_time_blocking")
+        return d.value
 
     @property
     def nodes(self) -> int:

@@ -28,8 +28,9 @@ def standalone(p, phi0, nsteps):
         return s.phi()
 
 
+@pytest.mark.parametrize("depth", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_ragged_batch_matches_standalone_bitwise(precision):
+def test_ragged_batch_matches_standalone_bitwise(precision, depth):
     import torch
     L = lb()
     rng = np.random.default_rng(4)
@@ -46,9 +47,13 @@ def test_ragged_batch_matches_standalone_bitwise(precision):
         fields.append(inputs.spinodal(nx, ny, seed=100 + k, amp=0.3, mean=0.05))
     stream = torch.cuda.Stream()
     with L.Batch(params, stream) as b:
+        b.set_time_blocking(depth)
+        assert b.time_blocking() == depth
         for k, f in enumerate(fields):
             b.init(k, f)
-        b.step(45)          # 2 graph replays of 16 + 13 plain launches
+        # depth 1: 2 graph replays of 16 launches + 13 launches; depth 2: 1 replay of 16 two-step
+        # launches + 6 two-step launches + 1 single-step launch
+        b.step(45)
         got = [b.phi(k) for k in range(len(shapes))]
         assert b.nstep == 45
     for k in range(len(shapes)):
@@ -77,11 +82,15 @@ def test_batch_tiling_and_autotune_bitwise():
     fields = [inputs.spinodal(nx, ny, seed=70 + k, amp=0.3) for k, (ny, nx) in enumerate(shapes)]
     ref = None
     with L.Batch(params) as b:
-        for cfg in [(128, 0, 0), (64, 7, 3), (256, 50, 1), (512, 16, 0)]:
+        for depth, cfg in [(1, (128, 0, 0)), (1, (64, 7, 3)), (1, (256, 50, 1)), (1, (512, 16, 0)),
+                           (2, (128, 0, 0)), (2, (256, 33, 1)), (2, (512, 70, 0)), (2, (128, 5, 0))]:
+            b.set_time_blocking(depth)
             for k, f in enumerate(fields):
                 b.init(k, f)
             b.set_tiling(*cfg)
-            b.step(20)
+            b.step(20 if cfg[1] != 5 else 19)
+            if cfg[1] == 5:
+                b.step(1)
             got = [b.phi(k) for k in range(3)]
             if ref is None:
                 ref = got
@@ -92,7 +101,7 @@ def test_batch_tiling_and_autotune_bitwise():
         b.step(5)
         before = [b.phi(k) for k in range(3)]
         nt, hc, ms = b.autotune(2)
-        assert ms > 0 and nt in (64, 128, 256)
+        assert ms > 0 and nt in (64, 128, 256) and b.time_blocking() in (1, 2)
         after = [b.phi(k) for k in range(3)]
         for x, y in zip(before, after):
             assert np.array_equal(x, y)
@@ -116,13 +125,21 @@ def test_batch_errors():
             b.step(1)
         assert ei.value.status == L.E_STATE
         with pytest.raises(L.LbchError) as ei:
+            b.set_time_blocking(3)
+        assert ei.value.status == L.E_INVALID
+        b.set_time_blocking(2)
+        with pytest.raises(L.LbchError):
+            b.set_tiling(512, 0, 0)        # float64 rings of 512 lanes do not fit in LDS
+        with pytest.raises(L.LbchError):
+            b.set_tiling(64, 0, 0)
+        with pytest.raises(L.LbchError) as ei:
             b.init(2, np.zeros((16, 16)))
         assert ei.value.status == L.E_INVALID
 
 
 def test_ensemble_workload_sampled_members():
     # The 512-member ensemble (sides log-uniform in [64, 512], alpha ~ U[0, 0.3], m in {4, 6},
-    # spinodal / droplet 50/50), FP32, one persistent launch per step; sampled members
+    # spinodal / droplet 50/50), FP32, one persistent launch per two steps; sampled members
     # are checked bitwise against standalone runs and mass is conserved for all.
     import torch
     L = lb()
