@@ -204,6 +204,111 @@ def hybrid_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def ensemble_workload(args):
+    """Throughput of the ragged ensemble: 512 periodic members (side log-uniform in [64, 512],
+    alpha ~ U[0, 0.3], m in {4, 6}, spinodal / droplet 50/50, seed 3), FP32, advanced by one
+    persistent launch per two steps (graphs of 16 launches), launch shape from the autotuner."""
+    import torch
+
+    from paper_2501_03759_amd import inputs, lbch
+
+    mems = inputs.ensemble_members(512, seed=3)
+    params = [lbch.default_params(nx=m["side"], ny=m["side"], precision=lbch.FP32,
+                                  sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(1.5)), mobility=0.1,
+                                  alpha=m["alpha"], aniso_m=m["m"], eps_reg=0.03) for m in mems]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    b = lbch.Batch(params, stream)
+    for k, m in enumerate(mems):
+        b.init(k, inputs.member_phi0(m))
+    nt, hc, _ = b.autotune(3)
+    depth = b.time_blocking()
+    nodes = b.nodes
+    b.step(args.warmup)
+    b.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    b.step(args.steps)
+    end.record(stream)
+    end.synchronize()
+    ms_step = start.elapsed_time(end) / args.steps
+    b.close()
+    launch_ms = ms_step * depth
+    alg = 72 * nodes * depth
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS, 512-member ragged ensemble (1 GPU)", "value": round(nodes / (ms_step * 1e-3) / 1e6, 1),
+        "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded ragged spinodal / droplet members, seed 3)",
+        "config": {"workload": "ensemble-512-ragged-fp32", "members": len(mems), "nodes": nodes,
+                   "time_steps_per_launch": depth, "tiling": [nt, hc]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "batch_step",
+                     "launch_ms": round(launch_ms, 4), "bytes_per_update": 72,
+                     "min_bytes_GBs": round(72 * nodes / (launch_ms * 1e-3) / 1e9, 1)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def surrogate_workload(args):
+    """Throughput of the surrogate network's forward and training step on 16 periodic 256 x 256
+    patches: the 5-level U-Net (32, 64, 128, 256, 256 channels), inputs phi plus 4 conditioning
+    planes, BF16 MFMA with FP32 accumulation.  FLOPs are the network's own 3x3 and 1x1
+    convolutions (2 per multiply-add, real input channels); a training step counts 3x forward."""
+    import torch
+
+    from paper_2501_03759_amd import lbsg
+
+    chans, c_in, B, hw = (32, 64, 128, 256, 256), 5, 16, 256
+    flops = 0.0
+    prev = c_in
+    for l, c in enumerate(chans):
+        flops += 18.0 * (prev * c + c * c) * (hw >> l) ** 2
+        prev = c
+    for l in range(len(chans) - 2, -1, -1):
+        flops += 18.0 * ((chans[l + 1] + chans[l]) * chans[l] + chans[l] * chans[l]) * (hw >> l) ** 2
+    flops = (flops + 2.0 * chans[0] * hw * hw) * B
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((B, hw, hw, c_in), device="cuda", generator=g)
+    t = torch.randn((B, hw, hw), device="cuda", generator=g)
+    out = torch.empty((B, hw, hw), device="cuda")
+    net = lbsg.Surrogate(chans, c_in, B, hw, hw, train=True, seed=0, stream=stream, out_scale=0.02)
+    torch.cuda.synchronize()
+    res = {}
+    for what, fn, mult in [("forward", lambda: net.forward(x.data_ptr(), B, hw, hw, out.data_ptr()), 1.0),
+                           ("train_step", lambda: net.train_step(x.data_ptr(), t.data_ptr(), B, hw, hw, 0, 1e-4,
+                                                                 want_loss=False), 3.0)]:
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e.record(stream)
+        e.synchronize()
+        ms = a.elapsed_time(e) / args.steps
+        res[what] = (ms, mult * flops / (ms * 1e-3) / 1e12)
+    net.close()
+    fwd_ms, fwd_tf = res["forward"]
+    out_line = {
+        "metric": "surrogate forward TFLOP/s, 16 x 256^2 patches (1 GPU)", "value": round(fwd_tf, 1),
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fwd_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded normal inputs)",
+        "config": {"workload": "unet5-32-256-b16x256x256", "chans": list(chans), "in_ch": c_in,
+                   "flop_per_forward": flops},
+        "roofline": {"bound": "mfma", "achieved": round(fwd_tf, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(fwd_tf / 2500.0, 4), "traffic": None, "kernel": "conv3_fwd_k (all layers)"},
+        "train_step": {"ms": round(res["train_step"][0], 3), "TFLOP/s": round(res["train_step"][1], 1)},
+    }
+    print(json.dumps(out_line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,8 +319,9 @@ def main():
     ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per kernel launch")
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["step", "hybrid"], default="step",
-                    help="step: throughput of lbch_step (the default line); hybrid: time-to-t of the jump schedule")
+    ap.add_argument("--workload", choices=["step", "hybrid", "ensemble", "surrogate"], default="step",
+                    help="step: throughput of lbch_step (the default line); hybrid: time-to-t of the jump "
+                         "schedule; ensemble: the 512-member batch; surrogate: the network's MFMA throughput")
     ap.add_argument("--hybrid-warm", type=int, default=80000)
     ap.add_argument("--hybrid-steps", type=int, default=200000)
     ap.add_argument("--hybrid-jump", type=int, default=200)
@@ -233,6 +339,12 @@ def main():
 
     if args.workload == "hybrid":
         hybrid_workload(args)
+        return
+    if args.workload == "ensemble":
+        ensemble_workload(args)
+        return
+    if args.workload == "surrogate":
+        surrogate_workload(args)
         return
 
     import torch

@@ -193,13 +193,46 @@ __global__ void wgrad_reduce_k(const float* __restrict__ part, float* __restrict
 }
 
 // Column sums over pixels (bias gradients): part[s][c] = sum_{p in split s} G[p][c]
-template <typename T>
-__global__ void colsum_part_k(const T* __restrict__ G, long long P, int C, int S, float* __restrict__ part) {
-    const int s = blockIdx.x;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float acc = 0.f;
-        for (long long p = s; p < P; p += S) acc += (float)G[p * C + c];
-        part[(size_t)s * C + c] = acc;
+// Column sums of a row-major [P][C] BF16 matrix, optionally weighted per row
+// (part[s][c] = scale sum_{p in block s} wt[p] G[p][c], and with a weight also
+// part[s][C] = scale sum wt[p]).  Block s owns a contiguous range of rows;
+// thread t reads 16-byte chunk t % Q (Q = C / 8) of rows t / Q, t / Q + R, ...
+// (R = 256 / Q), so a wave reads whole rows; the R row-lanes of a chunk are
+// then summed through LDS.  C must be a multiple of 8, at most 512.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void colsum_part_k(const __bf16* __restrict__ G, const float* __restrict__ wt,
+                                                     long long P, int C, float scale, float* __restrict__ part) {
+    __shared__ float sh[256 * 8];
+    __shared__ float shw[256];
+    const int Q = C / 8, R = 256 / Q;
+    const int t = threadIdx.x, q = t % Q, r0 = t / Q;
+    const long long rows = (P + gridDim.x - 1) / gridDim.x;
+    const long long p0 = blockIdx.x * rows, p1 = p0 + rows < P ? p0 + rows : P;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float accw = 0.f;
+    if (r0 < R) {
+        for (long long p = p0 + r0; p < p1; p += R) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(G + p * C + q * 8);
+            const float w = WEIGHTED ? wt[p] : 1.f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] += w * (float)v[i];
+            if (WEIGHTED) accw += w;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sh[t * 8 + i] = acc[i];
+    shw[t] = (q == 0 && r0 < R) ? accw : 0.f;
+    __syncthreads();
+    // element c of a chunk-row lives at sh[(r * Q + c / 8) * 8 + c % 8] = sh[r * C + c]
+    for (int c = t; c < C; c += 256) {
+        float sum = 0.f;
+        for (int r = 0; r < R; ++r) sum += sh[r * C + c];
+        part[(size_t)blockIdx.x * (C + (WEIGHTED ? 1 : 0)) + c] = scale * sum;
+    }
+    if (WEIGHTED && t == 0) {
+        float sum = 0.f;
+        for (int k = 0; k < 256; ++k) sum += shw[k];
+        part[(size_t)blockIdx.x * (C + 1) + C] = scale * sum;
     }
 }
 
@@ -372,18 +405,19 @@ __global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict
     }
 }
 
-// with gs = scale g: dd[p][c] = gs[p] w[c]; part[s][c] = sum_{p in split} gs[p] d[p][c] (c < C),
-// part[s][C] = sum gs
-__global__ void head_bwd_k(const float* __restrict__ g, const __bf16* __restrict__ d, const float* __restrict__ w,
-                           __bf16* __restrict__ dd, long long P, int C, int S, float scale, float* __restrict__ part) {
-    const int s = blockIdx.x;
-    for (long long p = s * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)S * blockDim.x)
-        for (int c = 0; c < C; ++c) dd[p * C + c] = (__bf16)(scale * g[p] * w[c]);
-    // reductions: thread c handles column c (and C the bias)
-    for (int c = threadIdx.x; c <= C; c += blockDim.x) {
-        float acc = 0.f;
-        for (long long p = s; p < P; p += S) acc += c < C ? g[p] * (float)d[p * C + c] : g[p];
-        part[(size_t)s * (C + 1) + c] = scale * acc;
+// data gradient of the 1x1 head: dd[p][c] = scale g[p] w[c] (8 channels per thread)
+__global__ void head_dd_k(const float* __restrict__ g, const float* __restrict__ w, __bf16* __restrict__ dd,
+                          long long P, int C, float scale) {
+    const int Q = C / 8;
+    const long long n = P * Q;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / Q;
+        const int q = (int)(i - p * Q);
+        const float gs = scale * g[p];
+        bf16x8 v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (__bf16)(gs * w[q * 8 + k]);
+        *reinterpret_cast<bf16x8*>(dd + p * C + q * 8) = v;
     }
 }
 
@@ -510,7 +544,8 @@ hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int
 }
 
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s) {
-    colsum_part_k<__bf16><<<S, 256, 0, s>>>(G, P, C, S, part);
+    if (C % 8 != 0 || C > 512) return hipErrorInvalidValue;
+    colsum_part_k<false><<<S, 256, 0, s>>>(G, nullptr, P, C, 1.f, part);
     colsum_reduce_k<<<(C + 255) / 256, 256, 0, s>>>(part, S, C, out);
     return hipGetLastError();
 }
@@ -583,8 +618,10 @@ hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float
 
 hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float scale,
                     float* part, float* grad_wb, hipStream_t s) {
-    head_bwd_k<<<S, 256, 0, s>>>(g, d, w, dd, P, C, S, scale, part);
-    colsum_reduce_k<<<1, 256, 0, s>>>(part, S, C + 1, grad_wb);
+    if (C % 8 != 0 || C > 512) return hipErrorInvalidValue;
+    head_dd_k<<<grid_for(P * (C / 8)), 256, 0, s>>>(g, w, dd, P, C, scale);
+    colsum_part_k<true><<<S, 256, 0, s>>>(d, g, P, C, scale, part);
+    colsum_reduce_k<<<(C + 256) / 256, 256, 0, s>>>(part, S, C + 1, grad_wb);
     return hipGetLastError();
 }
 

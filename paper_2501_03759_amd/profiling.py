@@ -54,18 +54,36 @@ def kernel_stats(d):
     return out
 
 
+def stats_only(args):
+    """Kernel statistics of one traced run, as a short Markdown table."""
+    stats = kernel_stats(args.trace)
+    lines = [f"# rocprofv3 summary: {args.title}", "", "Command:", ""]
+    lines += ["    " + c for c in args.command.split(";;")]
+    lines += ["", "Kernel statistics (--kernel-trace --stats):", "",
+              "| kernel | calls | avg ms | % time |", "|---|---|---|---|"]
+    for st in stats[:12]:
+        lines.append(f"| {st['name'][:100]} | {st['calls']} | {st['avg_ns'] / 1e6:.4f} | {st['pct']:.1f} |")
+    with open(args.out + ".md", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--nodes", type=int, required=True)
+    ap.add_argument("--fetch", help="FETCH_SIZE run (omit for a kernel-statistics summary only)")
+    ap.add_argument("--write", help="WRITE_SIZE run")
+    ap.add_argument("--nodes", type=int, default=0)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per launch of the step kernel")
     ap.add_argument("--command", required=True, help="the profiled command lines (for the summary header)")
     ap.add_argument("--out", required=True, help="output prefix, e.g. profiles/step2_fused_spinodal8192_fp32")
+    ap.add_argument("--title", default="", help="summary title (stats-only mode)")
     args = ap.parse_args()
     STEP_KERNEL = STEP_KERNELS[args.depth]
+    if not args.fetch:
+        stats_only(args)
+        return
 
     esize = 4 if args.precision == "fp32" else 8
     kib = 1024.0
