@@ -26,18 +26,23 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const 
 //   Y[n,y,x,co] = act(bias[co] + sum_{tap,ci} W[co][tap][ci] X[n, y+dy, x+dx, ci])
 // GEMM view per workgroup: M = TC output channels, N = a 16x16 pixel tile,
 // K = 9 taps x Ci.  The A operand (weights, 8 consecutive ci per lane) and
-// the B operand (pixels, 8 consecutive ci per lane) are both read from LDS:
-// the pixel tile with its periodic 1-pixel halo is staged once per 32-channel
-// chunk, the weights one tap row (3 taps) at a time.  Each wave owns 4 pixel
-// rows x TC channels (4 x TC/16 MFMA tiles); the result fragment of a lane is
-// 4 consecutive output channels of one pixel (one 8-byte store).
+// the B operand (pixels, 8 consecutive ci per lane) are both read from LDS.
+// Per 32-channel chunk the workgroup stages the pixel tile with its periodic
+// 1-pixel halo and the weights of all nine taps (two barriers per chunk);
+// the global loads of the next chunk are issued into registers before the
+// matrix-core work on the current one, so they overlap it.  Each wave owns 4
+// pixel rows x TC channels (4 x TC/16 MFMA tiles); the result fragment of a
+// lane is 4 consecutive output channels of one pixel (one 8-byte store).
 // ---------------------------------------------------------------------------
 template <int TC, bool RELU>
 __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ Wt,
                                                    const float* __restrict__ bias, __bf16* __restrict__ Y, int H,
                                                    int Wd, int Ci, int Co) {
+    constexpr int NXQ = 18 * 18 * 4;              // 16-byte chunks of the pixel tile
+    constexpr int NWQ = 9 * TC * 4;               // 16-byte chunks of the weights
+    constexpr int RX = (NXQ + 255) / 256, RW = (NWQ + 255) / 256;
     __shared__ __align__(16) __bf16 sx[18 * 18 * kPadC];
-    __shared__ __align__(16) __bf16 sw[3 * TC * kPadC];
+    __shared__ __align__(16) __bf16 sw[9 * TC * kPadC];
     constexpr int CB = TC / 16;
     const int tiles_x = Wd / 16, tiles_y = H / 16;
     int b = blockIdx.x;
@@ -54,23 +59,52 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
 #pragma unroll
         for (int c = 0; c < CB; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // per-thread source offsets (chunk-independent parts); indices past the
+    // end are clamped to the last chunk (loaded, never stored)
+    long long xoff[RX];
+    long long woff[RW];
+#pragma unroll
+    for (int i = 0; i < RX; ++i) {
+        const int q = min((int)threadIdx.x + i * 256, NXQ - 1);
+        const int px = q >> 2, part = q & 3;
+        const int py = px / 18, pxx = px - py * 18;
+        const int y = wrap(ty0 - 1 + py, H), x = wrap(tx0 - 1 + pxx, Wd);
+        xoff[i] = (((long long)n * H + y) * Wd + x) * Ci + part * 8;
+    }
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int q = min((int)threadIdx.x + i * 256, NWQ - 1);
+        const int row = q >> 2, part = q & 3;
+        const int tap = row / TC, co = row - tap * TC;
+        woff[i] = ((long long)(co0 + co) * 9 + tap) * Ci + part * 8;
+    }
+    bf16x8 rx[RX], rw[RW];
+#pragma unroll
+    for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X + xoff[i]);
+#pragma unroll
+    for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + woff[i]);
+
     for (int cc = 0; cc < Ci; cc += 32) {
-        for (int q = threadIdx.x; q < 18 * 18 * 4; q += 256) {
-            const int px = q >> 2, part = q & 3;
-            const int py = px / 18, pxx = px - py * 18;
-            const int y = wrap(ty0 - 1 + py, H), x = wrap(tx0 - 1 + pxx, Wd);
-            *reinterpret_cast<bf16x8*>(sx + px * kPadC + part * 8) =
-                *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + cc + part * 8);
+        __syncthreads();                          // every wave is done with the previous chunk
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {
+            const int q = (int)threadIdx.x + i * 256;
+            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + (q >> 2) * kPadC + (q & 3) * 8) = rx[i];
         }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int q = (int)threadIdx.x + i * 256;
+            if (q < NWQ) *reinterpret_cast<bf16x8*>(sw + (q >> 2) * kPadC + (q & 3) * 8) = rw[i];
+        }
+        __syncthreads();
+        if (cc + 32 < Ci) {                       // next chunk in flight during the MFMAs
+#pragma unroll
+            for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X + xoff[i] + cc + 32);
+#pragma unroll
+            for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + woff[i] + cc + 32);
+        }
+#pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
-            __syncthreads();
-            for (int q = threadIdx.x; q < 3 * TC * 4; q += 256) {
-                const int row = q >> 2, part = q & 3;
-                const int kx = row / TC, co = row - kx * TC;
-                *reinterpret_cast<bf16x8*>(sw + row * kPadC + part * 8) = *reinterpret_cast<const bf16x8*>(
-                    Wt + ((size_t)(co0 + co) * 9 + ky * 3 + kx) * Ci + cc + part * 8);
-            }
-            __syncthreads();
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
                 bf16x8 bfr[4];
@@ -79,13 +113,13 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
                     bfr[r] = *reinterpret_cast<const bf16x8*>(sx + ((wave * 4 + r + ky) * 18 + l16 + kx) * kPadC + kb * 8);
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
-                    const bf16x8 afr = *reinterpret_cast<const bf16x8*>(sw + (kx * TC + c * 16 + l16) * kPadC + kb * 8);
+                    const bf16x8 afr =
+                        *reinterpret_cast<const bf16x8*>(sw + ((ky * 3 + kx) * TC + c * 16 + l16) * kPadC + kb * 8);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(afr, bfr[r], acc[r][c]);
                 }
             }
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -271,13 +305,20 @@ __global__ void pack_wflip_k(const float* __restrict__ W, __bf16* __restrict__ W
 }
 
 // ------------------------------------------------------------- elementwise
+// Every activation tensor is [pixels][C] BF16 with C a multiple of 8: these
+// kernels move 8 channels (16 bytes) per thread and index by chunk.
+
 // fp32 [P][cin] -> bf16 [P][cpad] (zero padded channels)
 __global__ void pack_input_k(const float* __restrict__ x, __bf16* __restrict__ out, long long P, int cin, int cpad) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P * cpad;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long p = i / cpad;
-        const int c = (int)(i % cpad);
-        out[i] = (__bf16)(c < cin ? x[p * cin + c] : 0.f);
+    const int Q = cpad / 8;
+    const long long n = P * Q;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / Q;
+        const int c0 = (int)(i - p * Q) * 8;
+        bf16x8 v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (__bf16)(c0 + k < cin ? x[p * cin + c0 + k] : 0.f);
+        *reinterpret_cast<bf16x8*>(out + p * cpad + c0) = v;
     }
 }
 
@@ -286,112 +327,162 @@ __global__ void pack_input_k(const float* __restrict__ x, __bf16* __restrict__ o
 // copy of phi used by the residual head (xin with one channel).
 __global__ void pack_phi_cond_k(const float* __restrict__ phi, const float* __restrict__ cond, int ncond,
                                 __bf16* __restrict__ out, float* __restrict__ xin, long long P, int cpad) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P * cpad;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long p = i / cpad;
-        const int c = (int)(i % cpad);
-        float v = 0.f;
-        if (c == 0) {
-            v = phi[p];
-            xin[p] = v;
-        } else if (c <= ncond) {
-            v = cond[c - 1];
+    const int Q = cpad / 8;
+    const long long n = P * Q;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / Q;
+        const int c0 = (int)(i - p * Q) * 8;
+        bf16x8 v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k;
+            float f = 0.f;
+            if (c == 0) {
+                f = phi[p];
+                xin[p] = f;
+            } else if (c <= ncond) {
+                f = cond[c - 1];
+            }
+            v[k] = (__bf16)f;
         }
-        out[i] = (__bf16)v;
+        *reinterpret_cast<bf16x8*>(out + p * cpad + c0) = v;
     }
 }
 
 __global__ void avgpool2_k(const __bf16* __restrict__ x, __bf16* __restrict__ y, int N, int H, int Wd, int C) {
-    const int Ho = H / 2, Wo = Wd / 2;
-    const long long total = (long long)N * Ho * Wo * C;
+    const int Ho = H / 2, Wo = Wd / 2, Q = C / 8;
+    const long long total = (long long)N * Ho * Wo * Q;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        long long q = i / C;
-        const int xo = (int)(q % Wo);
-        q /= Wo;
-        const int yo = (int)(q % Ho);
-        const int n = (int)(q / Ho);
-        auto at = [&](int yy, int xx) { return (float)x[(((size_t)n * H + yy) * Wd + xx) * C + c]; };
-        y[i] = (__bf16)(0.25f * ((at(2 * yo, 2 * xo) + at(2 * yo, 2 * xo + 1)) +
-                                 (at(2 * yo + 1, 2 * xo) + at(2 * yo + 1, 2 * xo + 1))));
+        const long long po = i / Q;
+        const int c0 = (int)(i - po * Q) * 8;
+        const int xo = (int)(po % Wo);
+        const long long r = po / Wo;
+        const int yo = (int)(r % Ho);
+        const long long nn = r / Ho;
+        const __bf16* b0 = x + ((nn * H + 2 * yo) * Wd + 2 * xo) * C + c0;
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(b0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(b0 + C);
+        const bf16x8 c = *reinterpret_cast<const bf16x8*>(b0 + (long long)Wd * C);
+        const bf16x8 d = *reinterpret_cast<const bf16x8*>(b0 + (long long)Wd * C + C);
+        bf16x8 o;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            o[k] = (__bf16)(0.25f * (((float)a[k] + (float)b[k]) + ((float)c[k] + (float)d[k])));
+        *reinterpret_cast<bf16x8*>(y + po * C + c0) = o;
     }
 }
 
 // dx (N,H,W,C) (+)= avgpool2 adjoint of dy (N,H/2,W/2,C)
 __global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict__ dx, int N, int H, int Wd, int C,
                                int accumulate) {
-    const long long total = (long long)N * H * Wd * C;
+    const int Q = C / 8;
+    const long long total = (long long)N * H * Wd * Q;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        long long q = i / C;
-        const int x = (int)(q % Wd);
-        q /= Wd;
-        const int y = (int)(q % H);
-        const int n = (int)(q / H);
-        float v = 0.25f * (float)dy[(((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c];
-        if (accumulate) v += (float)dx[i];
-        dx[i] = (__bf16)v;
+        const long long p = i / Q;
+        const int c0 = (int)(i - p * Q) * 8;
+        const int x = (int)(p % Wd);
+        const long long r = p / Wd;
+        const int y = (int)(r % H);
+        const long long nn = r / H;
+        const bf16x8 g = *reinterpret_cast<const bf16x8*>(dy + ((nn * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c0);
+        bf16x8 o;
+        if (accumulate) {
+            const bf16x8 old = *reinterpret_cast<const bf16x8*>(dx + p * C + c0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] = (__bf16)(0.25f * (float)g[k] + (float)old[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] = (__bf16)(0.25f * (float)g[k]);
+        }
+        *reinterpret_cast<bf16x8*>(dx + p * C + c0) = o;
     }
 }
 
 // z[..., 0:Cu] = up2(u), z[..., Cu:Cu+Cs] = s     (u: N,H/2,W/2,Cu; s, z: N,H,W)
 __global__ void up2_concat_k(const __bf16* __restrict__ u, const __bf16* __restrict__ sk, __bf16* __restrict__ z,
                              int N, int H, int Wd, int Cu, int Cs) {
-    const int C = Cu + Cs;
-    const long long total = (long long)N * H * Wd * C;
+    const int C = Cu + Cs, Q = C / 8, Qu = Cu / 8;
+    const long long total = (long long)N * H * Wd * Q;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long p = i / C;
-        const int x = (int)(p % Wd);
-        const long long q = p / Wd;
-        const int y = (int)(q % H);
-        const int n = (int)(q / H);
-        z[i] = c < Cu ? u[(((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + c] : sk[p * Cs + (c - Cu)];
+        const long long p = i / Q;
+        const int q = (int)(i - p * Q);
+        bf16x8 v;
+        if (q < Qu) {
+            const int x = (int)(p % Wd);
+            const long long r = p / Wd;
+            const int y = (int)(r % H);
+            const long long nn = r / H;
+            v = *reinterpret_cast<const bf16x8*>(u + ((nn * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + q * 8);
+        } else {
+            v = *reinterpret_cast<const bf16x8*>(sk + p * Cs + (q - Qu) * 8);
+        }
+        *reinterpret_cast<bf16x8*>(z + p * C + q * 8) = v;
     }
 }
 
 // adjoint of up2_concat: du = sum of the 2x2 block of dz[..., :Cu]; dsk (+)= dz[..., Cu:]
 __global__ void up2_concat_bwd_k(const __bf16* __restrict__ dz, __bf16* __restrict__ du, __bf16* __restrict__ dsk,
                                  int N, int H, int Wd, int Cu, int Cs, int accumulate) {
-    const int C = Cu + Cs;
+    const int C = Cu + Cs, Qu = Cu / 8, Qs = Cs / 8;
     const int Ho = H / 2, Wo = Wd / 2;
-    const long long tu = (long long)N * Ho * Wo * Cu;
-    const long long ts = (long long)N * H * Wd * Cs;
+    const long long tu = (long long)N * Ho * Wo * Qu;
+    const long long ts = (long long)N * H * Wd * Qs;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tu + ts;
          i += (long long)gridDim.x * blockDim.x) {
         if (i < tu) {
-            const int c = (int)(i % Cu);
-            long long q = i / Cu;
-            const int xo = (int)(q % Wo);
-            q /= Wo;
-            const int yo = (int)(q % Ho);
-            const int n = (int)(q / Ho);
-            float v = 0.f;
+            const long long po = i / Qu;
+            const int c0 = (int)(i - po * Qu) * 8;
+            const int xo = (int)(po % Wo);
+            const long long r = po / Wo;
+            const int yo = (int)(r % Ho);
+            const long long nn = r / Ho;
+            float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int bb = 0; bb < 2; ++bb)
-                    v += (float)dz[(((size_t)n * H + 2 * yo + a) * Wd + 2 * xo + bb) * C + c];
-            du[i] = (__bf16)v;
+                for (int bb = 0; bb < 2; ++bb) {
+                    const bf16x8 g = *reinterpret_cast<const bf16x8*>(
+                        dz + ((nn * H + 2 * yo + a) * Wd + 2 * xo + bb) * C + c0);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc[k] += (float)g[k];
+                }
+            bf16x8 o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] = (__bf16)acc[k];
+            *reinterpret_cast<bf16x8*>(du + po * Cu + c0) = o;
         } else {
             const long long j = i - tu;
-            const int c = (int)(j % Cs);
-            const long long p = j / Cs;
-            float v = (float)dz[p * C + Cu + c];
-            if (accumulate) v += (float)dsk[j];
-            dsk[j] = (__bf16)v;
+            const long long p = j / Qs;
+            const int c0 = (int)(j - p * Qs) * 8;
+            const bf16x8 g = *reinterpret_cast<const bf16x8*>(dz + p * C + Cu + c0);
+            bf16x8 o;
+            if (accumulate) {
+                const bf16x8 old = *reinterpret_cast<const bf16x8*>(dsk + p * Cs + c0);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) o[k] = (__bf16)((float)g[k] + (float)old[k]);
+            } else {
+                o = g;
+            }
+            *reinterpret_cast<bf16x8*>(dsk + p * Cs + c0) = o;
         }
     }
 }
 
-// g = dy * (y > 0)   (ReLU backward from the stored post-activation)
+// g = dy * (y > 0)   (ReLU backward from the stored post-activation); n8 = chunks of 8
 __global__ void relu_bwd_k(const __bf16* __restrict__ dy, const __bf16* __restrict__ y, __bf16* __restrict__ g,
-                           long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        g[i] = (float)y[i] > 0.f ? dy[i] : (__bf16)0.f;
+                           long long n8) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n8;
+         i += (long long)gridDim.x * blockDim.x) {
+        const bf16x8 a = reinterpret_cast<const bf16x8*>(dy)[i];
+        const bf16x8 b = reinterpret_cast<const bf16x8*>(y)[i];
+        bf16x8 o;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = (float)b[k] > 0.f ? a[k] : (__bf16)0.f;
+        reinterpret_cast<bf16x8*>(g)[i] = o;
+    }
 }
 
 // head: out[p] = phi[p] + scale (b + sum_c w[c] d[p][c])   (phi = input channel 0, fp32)
@@ -400,7 +491,11 @@ __global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict
                            float scale) {
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
         float acc = b[0];
-        for (int c = 0; c < C; ++c) acc += w[c] * (float)d[p * C + c];
+        for (int c0 = 0; c0 < C; c0 += 8) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(d + p * C + c0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += w[c0 + k] * (float)v[k];
+        }
         out[p] = xin[p * cin] + scale * acc;
     }
 }
@@ -572,46 +667,54 @@ hipError_t pack_wflip(const float* W, __bf16* Wf, int Co, int Ci, hipStream_t s)
 }
 
 hipError_t pack_input(const float* x, __bf16* out, long long P, int cin, int cpad, hipStream_t s) {
-    pack_input_k<<<grid_for(P * cpad), 256, 0, s>>>(x, out, P, cin, cpad);
+    if (cpad % 8 != 0) return hipErrorInvalidValue;
+    pack_input_k<<<grid_for(P * cpad / 8), 256, 0, s>>>(x, out, P, cin, cpad);
     return hipGetLastError();
 }
 
 hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16* out, float* xin, long long P, int cpad,
                          hipStream_t s) {
-    pack_phi_cond_k<<<grid_for(P * cpad), 256, 0, s>>>(phi, cond, ncond, out, xin, P, cpad);
+    if (cpad % 8 != 0) return hipErrorInvalidValue;
+    pack_phi_cond_k<<<grid_for(P * cpad / 8), 256, 0, s>>>(phi, cond, ncond, out, xin, P, cpad);
     return hipGetLastError();
 }
 
 hipError_t avgpool2(const __bf16* x, __bf16* y, int N, int H, int Wd, int C, hipStream_t s) {
-    avgpool2_k<<<grid_for((long long)N * H * Wd * C / 4), 256, 0, s>>>(x, y, N, H, Wd, C);
+    if (C % 8 != 0) return hipErrorInvalidValue;
+    avgpool2_k<<<grid_for((long long)N * H * Wd * C / 32), 256, 0, s>>>(x, y, N, H, Wd, C);
     return hipGetLastError();
 }
 
 hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s) {
-    avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0);
+    if (C % 8 != 0) return hipErrorInvalidValue;
+    avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C / 8), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t up2_concat(const __bf16* u, const __bf16* sk, __bf16* z, int N, int H, int Wd, int Cu, int Cs,
                       hipStream_t s) {
-    up2_concat_k<<<grid_for((long long)N * H * Wd * (Cu + Cs)), 256, 0, s>>>(u, sk, z, N, H, Wd, Cu, Cs);
+    if (Cu % 8 != 0 || Cs % 8 != 0) return hipErrorInvalidValue;
+    up2_concat_k<<<grid_for((long long)N * H * Wd * (Cu + Cs) / 8), 256, 0, s>>>(u, sk, z, N, H, Wd, Cu, Cs);
     return hipGetLastError();
 }
 
 hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
                           bool accumulate, hipStream_t s) {
-    const long long n = (long long)N * (H / 2) * (Wd / 2) * Cu + (long long)N * H * Wd * Cs;
+    if (Cu % 8 != 0 || Cs % 8 != 0) return hipErrorInvalidValue;
+    const long long n = ((long long)N * (H / 2) * (Wd / 2) * Cu + (long long)N * H * Wd * Cs) / 8;
     up2_concat_bwd_k<<<grid_for(n), 256, 0, s>>>(dz, du, dsk, N, H, Wd, Cu, Cs, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s) {
-    relu_bwd_k<<<grid_for(n), 256, 0, s>>>(dy, y, g, n);
+    if (n % 8 != 0) return hipErrorInvalidValue;
+    relu_bwd_k<<<grid_for(n / 8), 256, 0, s>>>(dy, y, g, n / 8);
     return hipGetLastError();
 }
 
 hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
                     long long P, int C, float scale, hipStream_t s) {
+    if (C % 8 != 0) return hipErrorInvalidValue;
     head_fwd_k<<<grid_for(P), 256, 0, s>>>(d, w, b, xin, cin, out, P, C, scale);
     return hipGetLastError();
 }
