@@ -71,6 +71,50 @@ def test_time_blocking_is_bitwise(precision, rates, shape):
                 assert np.array_equal(got, ref[nsteps]), (tiling, loader, nsteps)
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (3, 2), (13, 5)])
+def test_degenerate_grids_against_oracle(shape):
+    # grids smaller than one strip or one stencil radius: every lane and every pipeline row
+    # wraps onto the same few nodes; both depths, odd step count, FP64
+    nx, ny = shape
+    p = common.make_params(nx, ny, 0, width=4.0, alpha=0.3, s=inputs.C1_RATES_DISTINCT)
+    phi0 = inputs.spinodal(nx, ny, seed=31, amp=0.4)
+    want = common.oracle_phi(phi0, p, 21)
+    for depth in (1, 2):
+        got = run_gpu(p, phi0, 21, depth=depth)
+        assert np.abs(got - want).max() <= FP64_TOL, depth
+
+
+def test_isotropic_limit_without_regularisation_against_oracle():
+    # alpha = 0 (gamma = 1 everywhere) and no regularisation: the pure Cahn-Hilliard limit
+    p = common.make_params(72, 40, 0, width=4.0, alpha=0.0, regularization=0)
+    phi0 = inputs.spinodal(72, 40, seed=2, amp=0.3)
+    want = common.oracle_phi(phi0, p, 150)
+    assert np.abs(run_gpu(p, phi0, 150) - want).max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_uniform_field_is_steady(precision):
+    # grad phi = 0 everywhere: the floor reading (gamma = 1, gamma' = 0) on every node, and a
+    # uniform field is an exact steady state of the scheme
+    p = common.make_params(64, 48, precision, width=4.0, alpha=0.3)
+    phi0 = np.full((48, 64), 0.37)
+    got = run_gpu(p, phi0, 40)
+    assert np.abs(got - 0.37).max() <= (1e-14 if precision == 0 else 1e-6)
+    want = common.oracle_phi(phi0, p, 40)
+    assert np.abs(got - want).max() <= (FP64_TOL if precision == 0 else 1e-6)
+
+
+def test_zero_steps_is_a_no_op():
+    L = lb()
+    p = common.make_params(40, 24, 0, width=4.0)
+    phi0 = inputs.spinodal(40, 24, seed=3, amp=0.3)
+    with L.Sim(p) as s:
+        s.init(phi0)
+        before = s.phi()
+        s.step(0)
+        assert s.nstep == 0 and np.array_equal(s.phi(), before)
+
+
 def test_time_blocking_errors():
     L = lb()
     with L.Sim(common.make_params(96, 64, 0, width=4.0)) as s:
