@@ -324,8 +324,8 @@ def main():
                          "schedule; ensemble: the 512-member batch; surrogate: the network's MFMA throughput")
     ap.add_argument("--hybrid-warm", type=int, default=80000)
     ap.add_argument("--hybrid-steps", type=int, default=200000)
-    ap.add_argument("--hybrid-jump", type=int, default=200)
-    ap.add_argument("--hybrid-correct", type=int, default=64)
+    ap.add_argument("--hybrid-jump", type=int, default=400)
+    ap.add_argument("--hybrid-correct", type=int, default=128)
     ap.add_argument("--hybrid-chunk", type=int, default=10000)
     ap.add_argument("--hybrid-inner", type=str, default="4,16",
                     help="inner_steps,inner_jump: projective steps of the populations inside the correction phase")
