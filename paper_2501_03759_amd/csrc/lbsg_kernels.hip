@@ -212,17 +212,29 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
 
 // dW[co][ci][ky][kx] (FP32 parameter layout, only the first ci_real input
 // channels) = sum_s P[s][co][tap][ci].
-__global__ void wgrad_reduce_k(const float* __restrict__ part, float* __restrict__ dW, int S, int Co, int Ci,
-                               int ci_real) {
-    const long long total = (long long)Co * ci_real * 9;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int tap = (int)(i % 9);
-        const int ci = (int)((i / 9) % ci_real);
-        const int co = (int)(i / (9LL * ci_real));
-        float acc = 0.f;
-        for (int s = 0; s < S; ++s) acc += part[(((size_t)s * Co + co) * 9 + tap) * Ci + ci];
-        dW[i] = acc;
+// dW[co][ci][tap] = sum_s part[s][co][tap][ci] (ci < ci_real).  A block owns 32
+// consecutive partial entries e = (co * 9 + tap) * Ci + ci; its 8 lanes of 32
+// threads take every 8th split, then a fixed-order tree adds the lanes
+// (deterministic).
+__global__ __launch_bounds__(256) void wgrad_reduce_k(const float* __restrict__ part, float* __restrict__ dW, int S,
+                                                      int Co, int Ci, int ci_real) {
+    __shared__ float sh[8][32];
+    const long long E = (long long)Co * 9 * Ci;
+    const int el = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const long long e = (long long)blockIdx.x * 32 + el;
+    float acc = 0.f;
+    if (e < E)
+        for (int s = sl; s < S; s += 8) acc += part[(size_t)s * E + e];
+    sh[sl][el] = acc;
+    __syncthreads();
+    if (sl == 0 && e < E) {
+        const float v = ((sh[0][el] + sh[1][el]) + (sh[2][el] + sh[3][el])) +
+                        ((sh[4][el] + sh[5][el]) + (sh[6][el] + sh[7][el]));
+        const int ci = (int)(e % Ci);
+        const long long r = e / Ci;
+        const int tap = (int)(r % 9);
+        const int co = (int)(r / 9);
+        if (ci < ci_real) dW[((size_t)co * ci_real + ci) * 9 + tap] = v;
     }
 }
 
@@ -270,12 +282,23 @@ __global__ __launch_bounds__(256) void colsum_part_k(const __bf16* __restrict__ 
     }
 }
 
-__global__ void colsum_reduce_k(const float* __restrict__ part, int S, int C, float* __restrict__ out) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
-        float acc = 0.f;
-        for (int s = 0; s < S; ++s) acc += part[(size_t)s * C + c];
-        out[c] = acc;
+// out[c] = sum_s part[s][c] for c < C: a block owns 4 columns; 64 lanes per
+// column take every 64th split, then a fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void colsum_reduce_k(const float* __restrict__ part, int S, int C,
+                                                       float* __restrict__ out) {
+    __shared__ float sh[4][64];
+    const int cl = threadIdx.x & 3, sl = threadIdx.x >> 2;
+    const int c = blockIdx.x * 4 + cl;
+    float acc = 0.f;
+    if (c < C)
+        for (int s = sl; s < S; s += 64) acc += part[(size_t)s * C + c];
+    sh[cl][sl] = acc;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (sl < w) sh[cl][sl] += sh[cl][sl + w];
+        __syncthreads();
     }
+    if (sl == 0 && c < C) out[c] = sh[cl][0];
 }
 
 // ----------------------------------------------------------- weight packing
@@ -634,14 +657,14 @@ hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N
 }
 
 hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s) {
-    wgrad_reduce_k<<<grid_for((long long)Co * ci_real * 9), 256, 0, s>>>(part, dW, S, Co, Ci, ci_real);
+    wgrad_reduce_k<<<(int)(((long long)Co * 9 * Ci + 31) / 32), 256, 0, s>>>(part, dW, S, Co, Ci, ci_real);
     return hipGetLastError();
 }
 
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s) {
     if (C % 8 != 0 || C > 512) return hipErrorInvalidValue;
     colsum_part_k<false><<<S, 256, 0, s>>>(G, nullptr, P, C, 1.f, part);
-    colsum_reduce_k<<<(C + 255) / 256, 256, 0, s>>>(part, S, C, out);
+    colsum_reduce_k<<<(C + 3) / 4, 256, 0, s>>>(part, S, C, out);
     return hipGetLastError();
 }
 
@@ -724,7 +747,7 @@ hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd,
     if (C % 8 != 0 || C > 512) return hipErrorInvalidValue;
     head_dd_k<<<grid_for(P * (C / 8)), 256, 0, s>>>(g, w, dd, P, C, scale);
     colsum_part_k<true><<<S, 256, 0, s>>>(d, g, P, C, scale, part);
-    colsum_reduce_k<<<(C + 256) / 256, 256, 0, s>>>(part, S, C + 1, grad_wb);
+    colsum_reduce_k<<<(C + 4) / 4, 256, 0, s>>>(part, S, C + 1, grad_wb);
     return hipGetLastError();
 }
 
