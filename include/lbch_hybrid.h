@@ -1,6 +1,6 @@
 /*
  * lbch_hybrid.h — jump-accelerated time stepping with the lattice Boltzmann
- * scheme as fallback and judge.
+ * scheme as fallback and reference.
  *
  * One cycle advances a simulation by jump + correct_steps time steps:
  *   1. free energy E0 of the current state (eq 7, discrete; the E1 of the

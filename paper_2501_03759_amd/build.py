@@ -1,6 +1,6 @@
 """Builds liblbch.so (the HIP kernels plus the C-ABI layer) in-tree for gfx950.
 
-Usage: python -m paper_2501_03759_amd.build  (or __graft_entry__.build()).
+Usage: python -m paper_2501_03759_amd.build
 Always recompiles.  The library is placed next to this file.
 """
 from __future__ import annotations

@@ -124,8 +124,8 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                               "(python -m paper_2501_03759_amd.build); there is no CPU fallback")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2501_03759_amd.build; "
+                               "there is no CPU fallback")
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(handle, name)

@@ -1,5 +1,5 @@
 """The surrogate-jump / lattice Boltzmann schedule: the plain scheme is the fallback and the
-judge.  Shadow windows reproduce the plain run; an all-reject run is bitwise the plain run;
+reference.  Shadow windows reproduce the plain run; an all-reject run is bitwise the plain run;
 accepted jumps conserve mass exactly and keep the free energy from rising."""
 import numpy as np
 import pytest
