@@ -71,6 +71,19 @@ def test_time_blocking_is_bitwise(precision, rates, shape):
                 assert np.array_equal(got, ref[nsteps]), (tiling, loader, nsteps)
 
 
+@pytest.mark.parametrize("alpha", [0.1, 0.3])
+def test_paper_parameter_droplet_eq39(alpha):
+    # the paper's own parameters (Section 4, eq 39: M = 0.1, Willmore eps = 0.03, D = 5,
+    # sigma = 0.01) on its droplet test: R = 25 on 100 x 100, phi0 = tanh(2 (R - r) / D)
+    L = lb()
+    p = L.default_params(precision=L.FP64, alpha=alpha)
+    phi0 = inputs.droplet_width(25.0, 5.0, 100, 100)
+    want = common.oracle_phi(phi0, p, 501)
+    for depth in (1, 2):
+        got = run_gpu(p, phi0, 501, depth=depth)
+        assert np.abs(got - want).max() <= FP64_TOL, depth
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (3, 2), (13, 5)])
 def test_degenerate_grids_against_oracle(shape):
     # grids smaller than one strip or one stencil radius: every lane and every pipeline row
