@@ -252,6 +252,63 @@ def ensemble_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def step3d_workload(args):
+    """Throughput of the D3Q15 step (eq 21): a periodic n^3 box (default 256^3) of spinodal noise
+    U(-0.05, 0.05) from seed 5 with the parameters of the two-dimensional workload (alpha = 0.2,
+    Willmore eps = 0.03, M = 0.1, D = 2 sqrt(2) 1.5, sigma = 0.01), one launch per step.
+    Algorithmic bytes per update: 15 populations read + 15 written."""
+    import torch
+
+    from paper_2501_03759_amd import inputs, lbch
+
+    d = inputs.C5
+    n = args.n3
+    prec = lbch.FP32 if args.precision == "fp32" else lbch.FP64
+    esize = 4 if prec == lbch.FP32 else 8
+    p = lbch.default_params(nx=n, ny=n, nz=n, lattice=lbch.D3Q15, precision=prec,
+                            sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"])),
+                            mobility=d["mobility"], alpha=d["alpha"], eps_reg=d["eps_reg"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sim = lbch.Sim(p, stream)
+    if args.tiling:
+        sim.set_tiling(*(int(v) for v in args.tiling.split(",")))
+    phi0 = inputs.spinodal3(n, n, n, seed=d["seed"], amp=d["amp"])
+    sim.init(phi0)
+    del phi0
+    sim.step(args.warmup)
+    sim.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    end.synchronize()
+    ms_step = start.elapsed_time(end) / args.steps
+    _, mass, lo, hi = sim.moments(want_phi=False)
+    tiling = sim.tiling()
+    sim.close()
+    nodes = n ** 3
+    bytes_per_update = 30 * esize
+    achieved = bytes_per_update * nodes / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS & % HBM peak, D3Q15 (1 GPU)", "value": round(nodes / (ms_step * 1e-3) / 1e6, 1),
+        "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == lbch.FP32 else "f64",
+        "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
+        "config": {"workload": f"spinodal-{n}^3-d3q15-{args.precision}", "grid": [n, n, n], "lattice": "D3Q15",
+                   "alpha": d["alpha"], "regularization": "willmore", "eps_reg": d["eps_reg"],
+                   "mobility": d["mobility"], "time_steps_per_launch": 1, "tiling": list(tiling)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "step3_fused",
+                     "launch_ms": round(ms_step, 4), "updates_per_launch": nodes,
+                     "bytes_per_update": bytes_per_update},
+        "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def surrogate_workload(args):
     """Throughput of the surrogate network's forward and training step on 16 periodic 256 x 256
     patches: the 5-level U-Net (32, 64, 128, 256, 256 channels), inputs phi plus 4 conditioning
@@ -319,7 +376,8 @@ def main():
     ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per kernel launch")
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["step", "hybrid", "ensemble", "surrogate"], default="step",
+    ap.add_argument("--n3", type=int, default=256, help="box side of the D3Q15 workload")
+    ap.add_argument("--workload", choices=["step", "step3d", "hybrid", "ensemble", "surrogate"], default="step",
                     help="step: throughput of lbch_step (the default line); hybrid: time-to-t of the jump "
                          "schedule; ensemble: the 512-member batch; surrogate: the network's MFMA throughput")
     ap.add_argument("--hybrid-warm", type=int, default=80000)
@@ -345,6 +403,9 @@ def main():
         return
     if args.workload == "surrogate":
         surrogate_workload(args)
+        return
+    if args.workload == "step3d":
+        step3d_workload(args)
         return
 
     import torch

@@ -4,8 +4,8 @@
  * anisotropic Cahn-Hilliard equation with the lattice Boltzmann method"
  * (arXiv 2501.03759).
  *
- * One simulation = one periodic D2Q9 grid whose populations live in HBM in
- * the library's own buffers.  Every call returns an lbch_status (0 = OK,
+ * One simulation = one periodic D2Q9 grid (or one D3Q15 box, eq 21) whose
+ * populations live in HBM in the library's own buffers.  Every call returns an lbch_status (0 = OK,
  * < 0 = error); no C++ exception crosses the ABI and lbch_last_error()
  * returns a thread-local message describing the last failure.
  *
@@ -31,19 +31,19 @@
 extern "C" {
 #endif
 
-#define LBCH_ABI_VERSION 1
+#define LBCH_ABI_VERSION 2
 
 typedef enum lbch_status {
     LBCH_OK = 0,
     LBCH_E_INVALID = -1,      /* bad argument or parameter */
-    LBCH_E_UNSUPPORTED = -2,  /* valid in the paper but not built (3D lattice, non-periodic) */
+    LBCH_E_UNSUPPORTED = -2,  /* valid in the paper but not built (non-periodic, 3D options below) */
     LBCH_E_OOM = -3,          /* device or host allocation failed */
     LBCH_E_DEVICE = -4,       /* HIP runtime error */
     LBCH_E_NONFINITE = -5,    /* the state holds NaN/Inf (results still written) */
     LBCH_E_STATE = -6         /* call out of order (e.g. step before init) */
 } lbch_status;
 
-enum { LBCH_D2Q9 = 0, LBCH_D3Q15 = 1 /* eq 21: reserved, returns LBCH_E_UNSUPPORTED */ };
+enum { LBCH_D2Q9 = 0 /* eq 20 */, LBCH_D3Q15 = 1 /* eq 21 (see below) */ };
 enum { LBCH_FP64 = 0, LBCH_FP32 = 1 };
 enum { LBCH_BC_PERIODIC = 0 /* Section 4: periodic boundaries */ };
 enum {
@@ -61,7 +61,9 @@ enum {
 /*
  * Problem statement (Sections 2-3).  Fill with lbch_params_default() and
  * override fields.
- *   nx, ny        grid nodes (>= 1 each, nx*ny*9 < 2^31), row-major [ny][nx].
+ *   nx, ny, nz    grid nodes (>= 1 each); nz = 1 on D2Q9.  Fields are
+ *                 row-major [ny][nx] (D2Q9) or [nz][ny][nx] (D3Q15); the
+ *                 row-padded population storage must stay below 2^31 entries.
  *   dx, dt        lattice spacing and time step (> 0).
  *   mobility      M of eq 10 (> 0); sets s_3 = s_5 = 1/(M/(c_s^2 dt) + 1/2)
  *                 (relation stated after eq 38), which must lie in (0, 2).
@@ -78,10 +80,23 @@ enum {
  *   q_form        LBCH_Q_DERIVED or LBCH_Q_LITERAL (see above).
  *   grad_floor    |grad phi| <= grad_floor  =>  gamma = 1 and no tangential
  *                 term (the normal of eq 2 is undefined); >= 0.
+ *
+ * D3Q15 (eq 21: velocities 0, the six faces, the eight body diagonals;
+ * weights 2/9, 1/9, 1/72).  The same step on a periodic nx x ny x nz box:
+ * eq 26 stencils over the 15 velocities, the cubic anisotropy of eq 6 with
+ * d = 3, gamma = 1 + alpha (4 sum_a n_a^4 - 3), and the MRT collision on the
+ * 15-moment basis obtained by Gram-Schmidt orthogonalisation of 1, |c|^2,
+ * |c|^4, c_x, |c|^2 c_x, c_y, |c|^2 c_y, c_z, |c|^2 c_z, 3c_x^2 - |c|^2,
+ * c_y^2 - c_z^2, c_x c_y, c_y c_z, c_x c_z, c_x c_y c_z, whose flux rows relax
+ * at s_j from the mobility.  Only the case where every other rate is 1 is
+ * built (s[1], s[2], s[4], s[6], s[7], s[8] must be 1, else
+ * LBCH_E_UNSUPPORTED), and aniso_m must be 4 with aniso_theta0 = 0.  One
+ * launch per step (time-blocking depth 1); ensembles, the autotuner and the
+ * hybrid schedule return LBCH_E_UNSUPPORTED for D3Q15.
  */
 typedef struct lbch_params {
     int32_t abi_version;      /* must equal LBCH_ABI_VERSION */
-    int32_t lattice;          /* LBCH_D2Q9 */
+    int32_t lattice;          /* LBCH_D2Q9 or LBCH_D3Q15 */
     int32_t precision;        /* LBCH_FP64 (verification) or LBCH_FP32 (production) */
     int32_t boundary;         /* LBCH_BC_PERIODIC */
     int32_t nx, ny;
@@ -95,7 +110,7 @@ typedef struct lbch_params {
     double aniso_theta0;
     double eps_reg;
     int32_t q_form;
-    int32_t reserved0;        /* must be 0 */
+    int32_t nz;               /* 1 on D2Q9 */
     double grad_floor;
 } lbch_params;
 
@@ -129,7 +144,7 @@ const char* lbch_last_error(void);
 
 /* Simulation lifecycle. ------------------------------------------------------ */
 
-/* Validates p, allocates two population buffers (9 planes each, structure of
+/* Validates p, allocates two population buffers (9 or 15 planes, structure of
  * arrays, rows padded) plus reduction scratch on the current HIP device and
  * binds the simulation to hip_stream (a hipStream_t; NULL = null stream).
  * *out is set only on success. */
@@ -140,13 +155,14 @@ lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_sim** out);
 lbch_status lbch_destroy(lbch_sim* sim);
 
 /* Sets the populations to the equilibrium of eq 18 at the initial order
- * parameter phi0 (host, float64, row-major [ny][nx], n = nx*ny entries),
+ * parameter phi0 (host, float64, row-major [ny][nx] or [nz][ny][nx],
+ * n = nx*ny*nz entries),
  * with mu_alpha of eq 16 evaluated by the eq 26b stencil and no source term
  * (the paper does not state the initial populations).  Resets the step
  * counter to 0.  Non-finite phi0 -> LBCH_E_INVALID.  Synchronises. */
 lbch_status lbch_init(lbch_sim* sim, const double* phi0, int64_t n);
 
-/* Same from device memory: phi0_dev holds nx*ny values of dtype LBCH_FP64
+/* Same from device memory: phi0_dev holds nx*ny*nz values of dtype LBCH_FP64
  * or LBCH_FP32, dense row-major.  Stream-ordered, does not synchronise and
  * does not inspect the values (a non-finite input surfaces as
  * LBCH_E_NONFINITE from the next lbch_moments). */
@@ -169,30 +185,30 @@ lbch_status lbch_synchronize(lbch_sim* sim);
 /* Reductions (synchronise). -------------------------------------------------- */
 
 /* phi = sum_i f_i (eq 22) of the current state.  phi_out (host, nullable)
- * receives nx*ny float64 values row-major; mass = sum phi dx^2 (conserved,
- * eq 34); phi_min / phi_max.  Sums are accumulated in float64 in a fixed
+ * receives nx*ny*nz float64 values row-major; mass = sum phi dx^d (d = 2 or
+ * 3; conserved, eq 34); phi_min / phi_max.  Sums are accumulated in float64 in a fixed
  * order (deterministic).  Any pointer may be NULL.  A non-finite value in
  * the state -> LBCH_E_NONFINITE (outputs still written). */
 lbch_status lbch_moments(lbch_sim* sim, double* phi_out, double* mass,
                          double* phi_min, double* phi_max);
 
 /* Discrete free energy of eq 7 at the current phi: sum over nodes of
- * dx^2 [gamma (kappa/2 |grad phi|^2 + F(phi)) + eps/2 G(phi)] with the
+ * dx^d [gamma (kappa/2 |grad phi|^2 + F(phi)) + eps/2 G(phi)] with the
  * eq 26 stencils, F of eq 4 and G of eq 8 / eq 9.  terms4 (nullable)
  * receives {gradient, bulk, regularisation, total}.  float64 throughout.
  * Non-finite -> LBCH_E_NONFINITE. */
 lbch_status lbch_free_energy(lbch_sim* sim, double* energy, double* terms4);
 
 /* Writes phi of the current state to device memory (dtype LBCH_FP64 or
- * LBCH_FP32, nx*ny dense row-major).  Stream-ordered, no synchronisation. */
+ * LBCH_FP32, nx*ny*nz dense row-major).  Stream-ordered, no synchronisation. */
 lbch_status lbch_phi_device(lbch_sim* sim, void* dst_dev, int32_t dtype);
 
 /* Checkpoint / resume. ------------------------------------------------------- */
 
 /* Size in bytes of a saved state: a fixed header (magic, ABI version, grid,
  * precision, step, parameters) followed by the pre-collision populations
- * f_i(x, t) of eq 17 as 9 dense planes [9][ny][nx] in the simulation's
- * precision. */
+ * f_i(x, t) of eq 17 as dense planes [9][ny][nx] (D2Q9) or [15][nz][ny][nx]
+ * (D3Q15, directions in the order of eq 21a) in the simulation's precision. */
 lbch_status lbch_state_bytes(const lbch_sim* sim, int64_t* bytes);
 
 /* Saves to dst (host memory if dst_is_device == 0, else device memory), which
@@ -212,7 +228,8 @@ lbch_status lbch_load_state(lbch_sim* sim, const void* src, int32_t src_is_devic
  * chip and writes the state two steps later; lbch_step with an odd count
  * finishes with one single-step launch).  Results are bitwise identical for
  * both depths.  Default 2.  Changing the depth restores the default tiling
- * of that depth.  depth not in {1, 2} -> LBCH_E_INVALID. */
+ * of that depth.  depth not in {1, 2} -> LBCH_E_INVALID; D3Q15 runs depth 1
+ * only (2 -> LBCH_E_UNSUPPORTED). */
 lbch_status lbch_set_time_blocking(lbch_sim* sim, int32_t depth);
 lbch_status lbch_get_time_blocking(const lbch_sim* sim, int32_t* depth);
 
@@ -221,7 +238,9 @@ lbch_status lbch_get_time_blocking(const lbch_sim* sim, int32_t* depth);
  * workgroup owns a strip of block_threads - 8 * depth columns;
  * rows_per_block >= 1 rows of that strip are swept per workgroup.  The
  * result is bitwise independent of the choice.  0 for either argument
- * restores the built-in default for the grid. */
+ * restores the built-in default for the grid.  D3Q15: block_threads is 0 or
+ * 512 (32 x 16 lanes, 26 x 10 nodes stored per workgroup) and
+ * rows_per_block is the number of z slabs swept per workgroup. */
 lbch_status lbch_set_tiling(lbch_sim* sim, int32_t block_threads, int32_t rows_per_block);
 lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t* rows_per_block);
 
@@ -230,7 +249,7 @@ lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t
  * the current state and writing the idle buffer, so the state and the step
  * counter are unchanged), keeps the fastest per step (depth and tiling) and
  * returns its tiling and time per step.  Synchronises.  Before init ->
- * LBCH_E_STATE. */
+ * LBCH_E_STATE; D3Q15 -> LBCH_E_UNSUPPORTED. */
 lbch_status lbch_autotune(lbch_sim* sim, int32_t steps_per_trial, int32_t* block_threads,
                           int32_t* rows_per_block, double* ms_per_step);
 

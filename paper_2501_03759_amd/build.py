@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbch.so")
 
-SOURCES = ["lbch_kernels.hip", "lbch_api.cpp", "lbch_batch.cpp", "lbsg_kernels.hip", "lbsg_net.cpp", "lbch_hybrid.cpp"]
+SOURCES = ["lbch_kernels.hip", "lbch3_kernels.hip", "lbch_api.cpp", "lbch_batch.cpp", "lbsg_kernels.hip", "lbsg_net.cpp", "lbch_hybrid.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -68,6 +68,7 @@ extern "C" lbch_status lbch_params_default(lbch_params* p) {
     p->boundary = LBCH_BC_PERIODIC;
     p->nx = 100;
     p->ny = 100;
+    p->nz = 1;
     p->dx = 1.0;
     p->dt = 1.0;
     p->mobility = 0.1;
@@ -96,15 +97,18 @@ extern "C" lbch_status lbch_params_validate(const lbch_params* p) {
     if (!p) return fail(LBCH_E_INVALID, "params pointer is NULL");
     if (p->abi_version != LBCH_ABI_VERSION)
         return fail(LBCH_E_INVALID, "abi_version %d != %d", p->abi_version, LBCH_ABI_VERSION);
-    if (p->lattice == LBCH_D3Q15) return fail(LBCH_E_UNSUPPORTED, "D3Q15 (eq 21) is not built");
-    if (p->lattice != LBCH_D2Q9) return fail(LBCH_E_INVALID, "unknown lattice %d", p->lattice);
+    if (p->lattice != LBCH_D2Q9 && p->lattice != LBCH_D3Q15)
+        return fail(LBCH_E_INVALID, "unknown lattice %d", p->lattice);
+    const bool d3 = p->lattice == LBCH_D3Q15;
     if (p->boundary != LBCH_BC_PERIODIC) return fail(LBCH_E_UNSUPPORTED, "only periodic boundaries are built");
     if (p->precision != LBCH_FP64 && p->precision != LBCH_FP32)
         return fail(LBCH_E_INVALID, "unknown precision %d", p->precision);
     if (p->nx < 1 || p->ny < 1) return fail(LBCH_E_INVALID, "grid %d x %d must be >= 1 x 1", p->nx, p->ny);
+    if (!d3 && p->nz != 1) return fail(LBCH_E_INVALID, "nz = %d on the D2Q9 lattice (must be 1)", p->nz);
+    if (d3 && p->nz < 1) return fail(LBCH_E_INVALID, "nz = %d must be >= 1", p->nz);
     const long long pitch = ((long long)p->nx + 63) / 64 * 64;
-    if (pitch * (long long)p->ny * 9 >= (1LL << 31))
-        return fail(LBCH_E_INVALID, "grid %d x %d exceeds 2^31 population entries", p->nx, p->ny);
+    if (pitch * (long long)p->ny * p->nz * (d3 ? 15 : 9) >= (1LL << 31))
+        return fail(LBCH_E_INVALID, "grid %d x %d x %d exceeds 2^31 population entries", p->nx, p->ny, p->nz);
     if (!(p->dx > 0) || !(p->dt > 0) || !isfin(p->dx) || !isfin(p->dt))
         return fail(LBCH_E_INVALID, "dx, dt must be positive and finite");
     if (!(p->mobility > 0) || !isfin(p->mobility)) return fail(LBCH_E_INVALID, "mobility must be > 0");
@@ -125,7 +129,14 @@ extern "C" lbch_status lbch_params_validate(const lbch_params* p) {
     if (p->q_form != LBCH_Q_DERIVED && p->q_form != LBCH_Q_LITERAL)
         return fail(LBCH_E_INVALID, "unknown q_form %d", p->q_form);
     if (!(p->grad_floor >= 0) || !isfin(p->grad_floor)) return fail(LBCH_E_INVALID, "grad_floor must be >= 0");
-    if (p->reserved0 != 0) return fail(LBCH_E_INVALID, "reserved0 must be 0");
+    if (d3) {
+        // the D3Q15 kernel implements the collision with every free rate 1
+        for (int k : {1, 2, 4, 6, 7, 8})
+            if (p->s[k] != 1.0)
+                return fail(LBCH_E_UNSUPPORTED, "D3Q15 needs every free relaxation rate = 1 (s[%d] = %g)", k, p->s[k]);
+        if (p->aniso_m != 4 || p->aniso_theta0 != 0.0)
+            return fail(LBCH_E_UNSUPPORTED, "D3Q15 has the cubic anisotropy of eq 6 only (aniso_m 4, theta0 0)");
+    }
     return ok();
 }
 
@@ -277,15 +288,50 @@ static Tiling sim_tiling(const lbch_sim* s, int depth, int nt, int hc) {
     return t;
 }
 
+template <typename T>
+void fill_coef3(const lbch_params* p, StepCoef3<T>& c) {
+    const double dx = p->dx, dt = p->dt, cc = dx / dt;
+    c.gf = (T)(1.0 / 3.0 / dx);
+    c.gd = (T)(1.0 / 24.0 / dx);
+    c.lf = (T)(2.0 / 3.0 / (dx * dx));
+    c.ld = (T)(1.0 / 12.0 / (dx * dx));
+    c.lc = (T)(14.0 / 3.0 / (dx * dx));
+    c.kappa = (T)p->kappa;
+    c.beta4 = (T)(4.0 * p->beta);
+    c.eps = (T)(p->regularization == LBCH_REG_NONE ? 0.0 : p->eps_reg);
+    c.alpha = (T)p->alpha;
+    c.alpha16 = (T)(16.0 * p->alpha);
+    c.floor2 = (T)(p->grad_floor * p->grad_floor);
+    c.u = (T)((1.0 - s_j_of(p)) / 10.0);
+    c.v = (T)(dt * cc / 6.0);
+    c.hd = (T)(dt * cc / 2.0);
+    c.w0 = (T)(2.0 / 9.0);
+    c.wf = (T)(1.0 / 9.0);
+    c.wd = (T)(1.0 / 72.0);
+    c.reg = p->regularization;
+    c.qform = p->q_form;
+}
+
 template void fill_coef<double>(const lbch_params*, StepCoef<double>&);
 template void fill_coef<float>(const lbch_params*, StepCoef<float>&);
+template void fill_coef3<double>(const lbch_params*, StepCoef3<double>&);
+template void fill_coef3<float>(const lbch_params*, StepCoef3<float>&);
 
 }  // namespace lbch
 
 namespace {
 
 const void* coef_ptr(const lbch_sim* s) {
+    if (s->d3) return s->precision == LBCH_FP64 ? (const void*)&s->c3d : (const void*)&s->c3f;
     return s->precision == LBCH_FP64 ? (const void*)&s->cd : (const void*)&s->cf;
+}
+
+lbch_status step_launch(lbch_sim* s, const Tiling& t) {
+    hipError_t e = s->d3 ? launch_step3(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g3, s->t3, coef_ptr(s),
+                                        s->stream)
+                         : launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);
+    if (e != hipSuccess) return fail(LBCH_E_DEVICE, "step launch failed: %s", hipGetErrorString(e));
+    return LBCH_OK;
 }
 
 lbch_status check_sim(const lbch_sim* s) {
@@ -334,9 +380,12 @@ extern "C" lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_
     s->g.ny = p->ny;
     s->g.pitch = (p->nx + 63) / 64 * 64;
     s->g.pad_ = 0;
-    // planes padded by 256 elements so that the nine planes do not alias in
-    // the same DRAM channel at power-of-two sizes
+    // planes padded by 256 elements so that the population planes do not
+    // alias in the same DRAM channel at power-of-two sizes
     s->g.plane = (long long)s->g.pitch * p->ny + 256;
+    s->d3 = p->lattice == LBCH_D3Q15;
+    s->nq = s->d3 ? 15 : 9;
+    s->nodes = (long long)p->nx * p->ny * p->nz;
     fill_coef<double>(p, s->cd);
     fill_coef<float>(p, s->cf);
     fill_red(p, s->rc);
@@ -347,14 +396,30 @@ extern "C" lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_
             s->cus = cus;
         (void)hipGetLastError();
     }
-    // two steps per launch by default (each population crosses HBM once per
-    // two updates); single-step launches finish odd step counts
-    s->t1 = sim_tiling(s, 1, 0, 0);
-    s->t = sim_tiling(s, 2, 0, 0);
-    const size_t fbytes = (size_t)s->g.plane * 9 * s->esize;
+    long long plane = s->g.plane;
+    if (s->d3) {
+        s->g3.nx = p->nx;
+        s->g3.ny = p->ny;
+        s->g3.nz = p->nz;
+        s->g3.pitch = s->g.pitch;
+        s->g3.slab = (long long)s->g.pitch * p->ny;
+        s->g3.plane = s->g3.slab * p->nz + 256;
+        plane = s->g3.plane;
+        fill_coef3<double>(p, s->c3d);
+        fill_coef3<float>(p, s->c3f);
+        s->t3 = make_tiling3(p->nx, p->ny, p->nz, 0, s->cus * step3_blocks_per_cu(s->precision));
+        s->t1.depth = 1;
+        s->t.depth = 1;
+    } else {
+        // two steps per launch by default (each population crosses HBM once
+        // per two updates); single-step launches finish odd step counts
+        s->t1 = sim_tiling(s, 1, 0, 0);
+        s->t = sim_tiling(s, 2, 0, 0);
+    }
+    const size_t fbytes = (size_t)plane * s->nq * s->esize;
     hipError_t e = hipSuccess;
     if ((e = hipMalloc(&s->f[0], fbytes)) != hipSuccess || (e = hipMalloc(&s->f[1], fbytes)) != hipSuccess ||
-        (e = hipMalloc((void**)&s->phi64, (size_t)p->nx * p->ny * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&s->phi64, (size_t)s->nodes * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&s->partials, (size_t)kRedBlocks * 4 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&s->result, 8 * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&s->bad, sizeof(unsigned))) != hipSuccess) {
@@ -381,11 +446,11 @@ extern "C" lbch_status lbch_init_device(lbch_sim* s, const void* phi0_dev, int32
     if (st != LBCH_OK) return st;
     if (!phi0_dev) return fail(LBCH_E_INVALID, "phi0 pointer is NULL");
     if (dtype != LBCH_FP64 && dtype != LBCH_FP32) return fail(LBCH_E_INVALID, "unknown dtype %d", dtype);
-    if (n != (int64_t)s->g.nx * s->g.ny)
-        return fail(LBCH_E_INVALID, "n = %lld but the grid has %lld nodes", (long long)n,
-                    (long long)s->g.nx * s->g.ny);
+    if (n != (int64_t)s->nodes)
+        return fail(LBCH_E_INVALID, "n = %lld but the grid has %lld nodes", (long long)n, (long long)s->nodes);
     HIP_TRY(launch_zero_u32(s->bad, 1, s->stream));
-    HIP_TRY(launch_init(s->precision, phi0_dev, dtype, s->f[0], s->g, coef_ptr(s), s->bad, s->stream));
+    if (s->d3) HIP_TRY(launch_init3(s->precision, phi0_dev, dtype, s->f[0], s->g3, coef_ptr(s), s->bad, s->stream));
+    else HIP_TRY(launch_init(s->precision, phi0_dev, dtype, s->f[0], s->g, coef_ptr(s), s->bad, s->stream));
     s->cur = 0;
     s->step = 0;
     s->initialized = true;
@@ -396,11 +461,11 @@ extern "C" lbch_status lbch_init(lbch_sim* s, const double* phi0, int64_t n) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
     if (!phi0) return fail(LBCH_E_INVALID, "phi0 pointer is NULL");
-    const int64_t nn = (int64_t)s->g.nx * s->g.ny;
+    const int64_t nn = (int64_t)s->nodes;
     if (n != nn) return fail(LBCH_E_INVALID, "n = %lld but the grid has %lld nodes", (long long)n, (long long)nn);
     for (int64_t i = 0; i < nn; ++i)
         if (!std::isfinite(phi0[i])) return fail(LBCH_E_INVALID, "phi0[%lld] is not finite", (long long)i);
-    // stage through the reduction scratch (float64, nx*ny)
+    // stage through the reduction scratch (float64, one value per node)
     HIP_TRY(hipMemcpyAsync(s->phi64, phi0, (size_t)nn * sizeof(double), hipMemcpyHostToDevice, s->stream));
     st = lbch_init_device(s, s->phi64, LBCH_FP64, n);
     if (st != LBCH_OK) return st;
@@ -415,13 +480,13 @@ extern "C" lbch_status lbch_step(lbch_sim* s, int64_t nsteps) {
     int64_t k = 0;
     if (s->t.depth == 2) {
         for (; k + 2 <= nsteps; k += 2) {
-            HIP_TRY(launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t, coef_ptr(s), s->stream));
+            if ((st = step_launch(s, s->t)) != LBCH_OK) return st;
             s->cur ^= 1;
             s->step += 2;
         }
     }
     for (; k < nsteps; ++k) {
-        HIP_TRY(launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t1, coef_ptr(s), s->stream));
+        if ((st = step_launch(s, s->t1)) != LBCH_OK) return st;
         s->cur ^= 1;
         s->step += 1;
     }
@@ -448,7 +513,10 @@ namespace {
 
 // phi (float64) into s->phi64 and {sum, min, max, nonfinite} into host out4.
 lbch_status phi_reduce(lbch_sim* s, double out4[4]) {
-    HIP_TRY(launch_moments(s->precision, s->f[s->cur], s->g, s->phi64, 0, s->partials, kRedBlocks, s->stream));
+    if (s->d3)
+        HIP_TRY(launch_moments3(s->precision, s->f[s->cur], s->g3, s->phi64, 0, s->partials, kRedBlocks, s->stream));
+    else
+        HIP_TRY(launch_moments(s->precision, s->f[s->cur], s->g, s->phi64, 0, s->partials, kRedBlocks, s->stream));
     const int kinds[4] = {0, 1, 2, 0};
     HIP_TRY(launch_finalize(s->partials, kRedBlocks, 4, kinds, s->result, s->stream));
     HIP_TRY(hipMemcpyAsync(out4, s->result, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -467,9 +535,8 @@ extern "C" lbch_status lbch_moments(lbch_sim* s, double* phi_out, double* mass, 
     double r[4];
     st = phi_reduce(s, r);
     if (st != LBCH_OK) return st;
-    if (phi_out)
-        HIP_TRY(hipMemcpy(phi_out, s->phi64, (size_t)s->g.nx * s->g.ny * sizeof(double), hipMemcpyDeviceToHost));
-    if (mass) *mass = r[0] * s->p.dx * s->p.dx;
+    if (phi_out) HIP_TRY(hipMemcpy(phi_out, s->phi64, (size_t)s->nodes * sizeof(double), hipMemcpyDeviceToHost));
+    if (mass) *mass = r[0] * s->p.dx * s->p.dx * (s->d3 ? s->p.dx : 1.0);
     if (phi_min) *phi_min = r[1];
     if (phi_max) *phi_max = r[2];
     if (r[3] != 0.0) return fail(LBCH_E_NONFINITE, "state holds %.0f non-finite phi values", r[3]);
@@ -482,13 +549,14 @@ extern "C" lbch_status lbch_free_energy(lbch_sim* s, double* energy, double* ter
     double r[4];
     st = phi_reduce(s, r);
     if (st != LBCH_OK) return st;
-    HIP_TRY(launch_energy(s->phi64, s->g, s->rc, s->partials, kRedBlocks, s->stream));
+    if (s->d3) HIP_TRY(launch_energy3(s->phi64, s->g3, s->c3d, s->partials, kRedBlocks, s->stream));
+    else HIP_TRY(launch_energy(s->phi64, s->g, s->rc, s->partials, kRedBlocks, s->stream));
     const int kinds[4] = {0, 0, 0, 0};
     HIP_TRY(launch_finalize(s->partials, kRedBlocks, 4, kinds, s->result, s->stream));
     double e[4];
     HIP_TRY(hipMemcpyAsync(e, s->result, 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    const double a = s->rc.area;
+    const double a = s->rc.area * (s->d3 ? s->p.dx : 1.0);   // dx^2 or dx^3
     const double tg = e[0] * a, tb = e[1] * a, tr = e[2] * a;
     if (energy) *energy = tg + tb + tr;
     if (terms4) {
@@ -506,7 +574,9 @@ extern "C" lbch_status lbch_phi_device(lbch_sim* s, void* dst, int32_t dtype) {
     if (st != LBCH_OK) return st;
     if (!dst) return fail(LBCH_E_INVALID, "dst is NULL");
     if (dtype != LBCH_FP64 && dtype != LBCH_FP32) return fail(LBCH_E_INVALID, "unknown dtype %d", dtype);
-    HIP_TRY(launch_moments(s->precision, s->f[s->cur], s->g, dst, dtype, s->partials, kRedBlocks, s->stream));
+    if (s->d3) HIP_TRY(launch_moments3(s->precision, s->f[s->cur], s->g3, dst, dtype, s->partials, kRedBlocks,
+                                       s->stream));
+    else HIP_TRY(launch_moments(s->precision, s->f[s->cur], s->g, dst, dtype, s->partials, kRedBlocks, s->stream));
     return ok();
 }
 
@@ -515,7 +585,7 @@ extern "C" lbch_status lbch_state_bytes(const lbch_sim* s, int64_t* bytes) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
     if (!bytes) return fail(LBCH_E_INVALID, "bytes pointer is NULL");
-    *bytes = (int64_t)sizeof(StateHeader) + (int64_t)9 * s->g.nx * s->g.ny * (int64_t)s->esize;
+    *bytes = (int64_t)sizeof(StateHeader) + (int64_t)s->nq * s->nodes * (int64_t)s->esize;
     return ok();
 }
 
@@ -531,10 +601,11 @@ extern "C" lbch_status lbch_save_state(lbch_sim* s, void* dst, int32_t dst_is_de
     h.ny = s->g.ny;
     h.step = s->step;
     h.params = s->p;
-    const size_t body = (size_t)9 * s->g.nx * s->g.ny * s->esize;
+    const size_t body = (size_t)s->nq * s->nodes * s->esize;
     // the idle population buffer holds the dense copy
     void* tmp = s->f[s->cur ^ 1];
-    HIP_TRY(launch_gather(s->precision, s->f[s->cur], s->g, tmp, s->stream));
+    if (s->d3) HIP_TRY(launch_gather3(s->precision, s->f[s->cur], s->g3, tmp, s->stream));
+    else HIP_TRY(launch_gather(s->precision, s->f[s->cur], s->g, tmp, s->stream));
     if (dst_is_device) {
         HIP_TRY(hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
         HIP_TRY(hipMemcpyAsync((char*)dst + sizeof h, tmp, body, hipMemcpyDeviceToDevice, s->stream));
@@ -555,14 +626,18 @@ extern "C" lbch_status lbch_load_state(lbch_sim* s, const void* src, int32_t src
     else std::memcpy(&h, src, sizeof h);
     if (std::memcmp(h.magic, "LBCHST01", 8) != 0) return fail(LBCH_E_INVALID, "not an lbch state (bad magic)");
     if (h.abi_version != LBCH_ABI_VERSION) return fail(LBCH_E_INVALID, "state ABI %d", h.abi_version);
-    if (h.precision != s->precision || h.nx != s->g.nx || h.ny != s->g.ny)
-        return fail(LBCH_E_INVALID, "state is %dx%d precision %d, simulation is %dx%d precision %d", h.nx, h.ny,
-                    h.precision, s->g.nx, s->g.ny, s->precision);
-    const size_t body = (size_t)9 * s->g.nx * s->g.ny * s->esize;
+    if (h.precision != s->precision || h.nx != s->g.nx || h.ny != s->g.ny || h.params.lattice != s->p.lattice ||
+        h.params.nz != s->p.nz)
+        return fail(LBCH_E_INVALID,
+                    "state is %dx%dx%d lattice %d precision %d, simulation is %dx%dx%d lattice %d precision %d", h.nx,
+                    h.ny, h.params.nz, h.params.lattice, h.precision, s->g.nx, s->g.ny, s->p.nz, s->p.lattice,
+                    s->precision);
+    const size_t body = (size_t)s->nq * s->nodes * s->esize;
     void* tmp = s->f[s->cur ^ 1];
     HIP_TRY(hipMemcpyAsync(tmp, (const char*)src + sizeof h, body,
                            src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(launch_scatter(s->precision, tmp, s->g, s->f[s->cur], s->stream));
+    if (s->d3) HIP_TRY(launch_scatter3(s->precision, tmp, s->g3, s->f[s->cur], s->stream));
+    else HIP_TRY(launch_scatter(s->precision, tmp, s->g, s->f[s->cur], s->stream));
     HIP_TRY(launch_zero_u32(s->bad, 1, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->step = h.step;
@@ -575,6 +650,10 @@ extern "C" lbch_status lbch_set_time_blocking(lbch_sim* s, int32_t depth) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
     if (depth != 1 && depth != 2) return fail(LBCH_E_INVALID, "time-blocking depth %d not in {1, 2}", depth);
+    if (s->d3) {
+        if (depth != 1) return fail(LBCH_E_UNSUPPORTED, "D3Q15 steps one time step per launch");
+        return ok();
+    }
     s->t = sim_tiling(s, depth, 0, 0);
     if (depth == 1) s->t1 = s->t;
     return ok();
@@ -591,6 +670,13 @@ extern "C" lbch_status lbch_get_time_blocking(const lbch_sim* s, int32_t* depth)
 extern "C" lbch_status lbch_set_tiling(lbch_sim* s, int32_t block_threads, int32_t rows_per_block) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
+    if (s->d3) {
+        if (block_threads != 0 && block_threads != kTile3X * kTile3Y)
+            return fail(LBCH_E_INVALID, "D3Q15 block_threads %d not in {0, %d}", block_threads, kTile3X * kTile3Y);
+        if (rows_per_block < 0) return fail(LBCH_E_INVALID, "rows_per_block %d < 0", rows_per_block);
+        s->t3 = make_tiling3(s->g3.nx, s->g3.ny, s->g3.nz, rows_per_block, s->cus * step3_blocks_per_cu(s->precision));
+        return ok();
+    }
     const int depth = s->t.depth;
     if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256 &&
         block_threads != 512)
@@ -619,8 +705,8 @@ extern "C" lbch_status lbch_set_row_loader(lbch_sim* s, int32_t mode) {
 extern "C" lbch_status lbch_get_tiling(const lbch_sim* s, int32_t* block_threads, int32_t* rows_per_block) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
-    if (block_threads) *block_threads = s->t.nt;
-    if (rows_per_block) *rows_per_block = s->t.hc;
+    if (block_threads) *block_threads = s->d3 ? kTile3X * kTile3Y : s->t.nt;
+    if (rows_per_block) *rows_per_block = s->d3 ? s->t3.hz : s->t.hc;
     return ok();
 }
 
@@ -640,6 +726,7 @@ extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32
     lbch_status st = check_init(s);
     if (st != LBCH_OK) return st;
     if (steps_per_trial < 1) return fail(LBCH_E_INVALID, "steps_per_trial %d < 1", steps_per_trial);
+    if (s->d3) return fail(LBCH_E_UNSUPPORTED, "the autotuner covers the D2Q9 kernels only");
     // Trials read the current state and write the idle buffer, so the state is untouched.
     const int nts[4] = {64, 128, 256, 512};
     const int hcs[7] = {8, 16, 32, 64, 128, 256, 512};

@@ -202,6 +202,8 @@ extern "C" lbch_status lbch_batch_create(const lbch_params* members, int32_t cou
     for (int k = 0; k < count; ++k) {
         lbch_status st = lbch_params_validate(&members[k]);
         if (st != LBCH_OK) return st;
+        if (members[k].lattice != LBCH_D2Q9)
+            return fail(LBCH_E_UNSUPPORTED, "member %d: ensembles hold D2Q9 grids only", k);
         if (members[k].precision != members[0].precision)
             return fail(LBCH_E_INVALID, "member %d precision differs from member 0", k);
     }
@@ -534,6 +536,7 @@ lbch_status lbch_batch_load_window(lbch_batch* b, int member, const lbch_sim* s,
     lbch_status st = check_member(b, member);
     if (st != LBCH_OK) return st;
     if (!s || !s->initialized) return fail(LBCH_E_STATE, "source simulation not initialised");
+    if (s->d3) return fail(LBCH_E_UNSUPPORTED, "windows are taken from D2Q9 simulations only");
     if (s->precision != b->precision) return fail(LBCH_E_INVALID, "precision mismatch");
     HIP_TRY(launch_copy_window(b->precision, s->f[s->cur], s->g, y0, x0, member_ptr(b, b->cur, member),
                                b->m[member].g, b->stream));

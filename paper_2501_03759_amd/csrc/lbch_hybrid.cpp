@@ -81,6 +81,7 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
                                            lbch_hybrid_stats* stats) {
     if (!sim || !o || (!net && !o->dry_run && !o->extrapolate)) return fail(LBCH_E_INVALID, "NULL argument");
     if (!sim->initialized) return fail(LBCH_E_STATE, "simulation not initialised");
+    if (sim->d3) return fail(LBCH_E_UNSUPPORTED, "the hybrid schedule runs on D2Q9 simulations only");
     if (o->jump < 1 || o->correct_steps < 0 || !(o->tol_energy >= 0) || o->windows < 0 || o->window_interior < 1 ||
         o->window_margin < 0 || !(o->tol_window > 0) || o->check_every < 1 || o->ncond < 0 || o->ncond > 8 ||
         o->inner_steps < 0 || o->inner_jump < 0 || nsteps < 0)

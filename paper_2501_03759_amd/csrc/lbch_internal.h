@@ -112,6 +112,51 @@ hipError_t launch_extrap_pop(int precision, void* cur, const void* prev, double 
 hipError_t launch_window_err(const float* win, int side, const float* big, int ny, int nx, int y0, int x0, int margin,
                              int interior, double* partials, double* out2, hipStream_t s);
 
+// ---- three-dimensional lattice (D3Q15, eq 21; lbch3_kernels.hip) ----
+// 15 population planes of nz slabs of ny rows of `pitch` elements.
+struct Grid3 {
+    int nx, ny, nz, pitch;
+    long long slab;       // elements between consecutive z slabs (pitch * ny)
+    long long plane;      // elements between consecutive population planes
+};
+
+// x-y tiles of (kTile3X - 6) x (kTile3Y - 6) nodes, each swept over `hz`
+// consecutive slabs; tiles are x-fastest, then y, then z chunk, and are
+// dealt to the 8 XCDs in contiguous ranges of `per_xcd`.
+struct Tiling3 {
+    int tiles_x, tiles_y, hz, zchunks, ntiles, per_xcd, nblocks;
+};
+
+constexpr int kTile3X = 32, kTile3Y = 16;
+
+// Per-step constants of the D3Q15 step in the working precision.
+template <typename T>
+struct StepCoef3 {
+    T gf, gd;             // gradient eq 26a: face (1/3)/dx, body diagonal (1/24)/dx
+    T lf, ld, lc;         // Laplacian eq 26b: (2/3)/dx^2, (1/12)/dx^2, (14/3)/dx^2
+    T kappa, beta4, eps, alpha, alpha16, floor2;
+    T u;                  // (1 - s_j) / 10
+    T v;                  // dt c / 6
+    T hd;                 // dt c / 2
+    T w0, wf, wd;         // eq 21b weights
+    int reg, qform;
+};
+
+template <typename T>
+void fill_coef3(const lbch_params* p, StepCoef3<T>& c);
+Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots);
+int step3_blocks_per_cu(int precision);
+hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3& g, const Tiling3& t,
+                        const void* coef, hipStream_t s);
+hipError_t launch_init3(int precision, const void* phi0, int phi_dtype, void* fout, const Grid3& g, const void* coef,
+                        unsigned* bad, hipStream_t s);
+hipError_t launch_moments3(int precision, const void* fin, const Grid3& g, void* phi_out, int out_dtype,
+                           double* partials, int nparts, hipStream_t s);
+hipError_t launch_energy3(const double* phi, const Grid3& g, const StepCoef3<double>& c, double* partials,
+                          int nparts, hipStream_t s);
+hipError_t launch_gather3(int precision, const void* fin, const Grid3& g, void* dense, hipStream_t s);
+hipError_t launch_scatter3(int precision, const void* dense, const Grid3& g, void* fout, hipStream_t s);
+
 }  // namespace lbch
 
 // The simulation handle (opaque in the C ABI).
@@ -136,6 +181,15 @@ struct lbch_sim {
     lbch::RedCoef rc{};
     int user_nt = 0, user_hc = 0, user_loader = 0;
     int cus = 256;                   // compute units of the device
+    // D3Q15 (lattice == LBCH_D3Q15): the 2D fields above other than the
+    // buffers, stream and counters are unused
+    bool d3 = false;
+    lbch::Grid3 g3{};
+    lbch::Tiling3 t3{};
+    lbch::StepCoef3<double> c3d{};
+    lbch::StepCoef3<float> c3f{};
+    long long nodes = 0;             // nx * ny * nz
+    int nq = 9;                      // populations per node
 };
 
 // Ensemble helper used by the hybrid schedule: member `member` of batch b

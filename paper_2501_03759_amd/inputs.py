@@ -10,6 +10,7 @@ Workloads (lattice units, dx = dt = 1, periodic):
 * spinodal: phi = mean + i.i.d. U(-amp, amp) from numpy's PCG64 seeded
   generator (the random initial state of eq 42, at a small amplitude).
 * two droplets of eq 41 (sum of two tanh discs plus one).
+* three-dimensional ball, spinodal and wavy-layer fields ([nz][ny][nx]).
 """
 from __future__ import annotations
 
@@ -45,6 +46,31 @@ def two_droplets(nx: int, ny: int, width_D: float, drops=((28, 35, 40), (9, 70, 
         r = np.hypot(min_image(x - x0, nx), min_image(y - y0, ny))
         out += np.tanh(2.0 * (R - r) / width_D)
     return out
+
+
+def sphere(nx: int, ny: int, nz: int, radius: float, eps_w: float, centre=None) -> np.ndarray:
+    """Three-dimensional tanh ball, [nz][ny][nx]; default centre (nx // 2, ny // 2, nz // 2)."""
+    cx, cy, cz = (nx // 2, ny // 2, nz // 2) if centre is None else centre
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt(min_image(x - cx, nx) ** 2 + min_image(y - cy, ny) ** 2 + min_image(z - cz, nz) ** 2)
+    return np.tanh((radius - r) / (math.sqrt(2.0) * eps_w))
+
+
+def wavy_slab(nx: int, ny: int, nz: int, eps_w: float, z_lo: float, z_hi: float, amp: float = 1.0) -> np.ndarray:
+    """A layer phi ~ +1 between two tanh interfaces normal to z, [nz][ny][nx]; the lower
+    interface is displaced by amp (sin(2 pi x / nx) + 0.7 cos(2 pi y / ny)), the upper by
+    amp / 2 sin(2 pi (x + y) / nx)."""
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    lo = z_lo + amp * (np.sin(2 * np.pi * x / nx) + 0.7 * np.cos(2 * np.pi * y / ny))
+    hi = z_hi + 0.5 * amp * np.sin(2 * np.pi * (x + y) / nx)
+    w = math.sqrt(2.0) * eps_w
+    return np.tanh((z - lo) / w) - np.tanh((z - hi) / w) - 1.0
+
+
+def spinodal3(nx: int, ny: int, nz: int, seed: int, amp: float = 0.05, mean: float = 0.0) -> np.ndarray:
+    """mean + U(-amp, amp), float64, [nz][ny][nx]."""
+    rng = np.random.default_rng(seed)
+    return mean + rng.uniform(-amp, amp, size=(nz, ny, nx))
 
 
 def spinodal(nx: int, ny: int, seed: int, amp: float = 0.05, mean: float = 0.0) -> np.ndarray:

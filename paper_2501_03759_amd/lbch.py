@@ -26,7 +26,7 @@ FP64, FP32 = 0, 1
 BC_PERIODIC = 0
 REG_NONE, REG_LINEAR, REG_WILLMORE = 0, 1, 2
 Q_DERIVED, Q_LITERAL = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class LbchError(RuntimeError):
@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
         ("aniso_theta0", ctypes.c_double),
         ("eps_reg", ctypes.c_double),
         ("q_form", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
         ("grad_floor", ctypes.c_double),
     ]
 
@@ -185,7 +185,8 @@ class Sim:
         self.params = params
         self._h = ctypes.c_void_p()
         _check(lib().lbch_create(ctypes.byref(params), _stream_handle(stream), ctypes.byref(self._h)), "lbch_create")
-        self.nx, self.ny = params.nx, params.ny
+        self.nx, self.ny, self.nz = params.nx, params.ny, params.nz
+        self.shape = (params.nz, params.ny, params.nx) if params.lattice == D3Q15 else (params.ny, params.nx)
 
     def close(self):
         if self._h:
@@ -228,7 +229,7 @@ class Sim:
         _check(lib().lbch_synchronize(self._h), "lbch_synchronize")
 
     def moments(self, want_phi: bool = True, check: bool = True):
-        phi = np.empty((self.ny, self.nx), dtype=np.float64) if want_phi else None
+        phi = np.empty(self.shape, dtype=np.float64) if want_phi else None
         mass, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         st = lib().lbch_moments(self._h, _dp(phi.ctypes.data) if want_phi else None, ctypes.byref(mass),
                                 ctypes.byref(lo), ctypes.byref(hi))

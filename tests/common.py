@@ -6,7 +6,7 @@ import math
 
 import numpy as np
 
-from oracle import lbm
+from oracle import lbm, lbm3
 from paper_2501_03759_amd import inputs
 
 REG_NAMES = {0: "none", 1: "linear", 2: "willmore"}
@@ -57,4 +57,30 @@ def sampled_oracle_phi(phi0: np.ndarray, p, nsteps: int, points) -> np.ndarray:
         op = oracle_params(p)
         op.nx = op.ny = 2 * h + 1
         out.append(lbm.phi_of(lbm.run(win, op, nsteps))[h, h])
+    return np.array(out)
+
+
+def oracle_params3(p) -> lbm3.Params:
+    """The D3Q15 problem for the three-dimensional oracle (every free rate 1)."""
+    return lbm3.Params(nx=p.nx, ny=p.ny, nz=p.nz, kappa=p.kappa, beta=p.beta, mobility=p.mobility, alpha=p.alpha,
+                       reg=REG_NAMES[p.regularization], eps_reg=p.eps_reg, q_form=QFORM_NAMES[p.q_form],
+                       grad_floor=p.grad_floor, dx=p.dx, dt=p.dt)
+
+
+def oracle_phi3(phi0, p, nsteps) -> np.ndarray:
+    return lbm3.phi_of(lbm3.run(phi0, oracle_params3(p), nsteps))
+
+
+def sampled_oracle_phi3(phi0: np.ndarray, p, nsteps: int, points) -> np.ndarray:
+    """phi after nsteps at the given (z, y, x) nodes of a large periodic box, each from an
+    oracle run on a periodic cube around the node (same dependence radius 4k + 2 as in 2D)."""
+    h = 4 * nsteps + 3
+    nz, ny, nx = phi0.shape
+    out = []
+    for (z, y, x) in points:
+        idx = (np.arange(z - h, z + h + 1) % nz, np.arange(y - h, y + h + 1) % ny, np.arange(x - h, x + h + 1) % nx)
+        win = phi0[np.ix_(*idx)]
+        op = oracle_params3(p)
+        op.nx = op.ny = op.nz = 2 * h + 1
+        out.append(lbm3.phi_of(lbm3.run(win, op, nsteps))[h, h, h])
     return np.array(out)

@@ -68,7 +68,9 @@ def test_sigma_width():
     ("aniso_m", 0, lbch.E_INVALID),
     ("aniso_m", 9, lbch.E_INVALID),
     ("aniso_m", 6, lbch.OK),
-    ("lattice", lbch.D3Q15, lbch.E_UNSUPPORTED),
+    ("lattice", lbch.D3Q15, lbch.OK),
+    ("lattice", 2, lbch.E_INVALID),
+    ("nz", 2, lbch.E_INVALID),          # D2Q9 grids have nz = 1
     ("boundary", 1, lbch.E_UNSUPPORTED),
     ("precision", 7, lbch.E_INVALID),
     ("kappa", 0.0, lbch.E_INVALID),
@@ -109,3 +111,25 @@ def test_create_rejects_invalid_without_gpu():
     with pytest.raises(lbch.LbchError) as ei:
         lbch.Sim(p)
     assert ei.value.status == lbch.E_INVALID
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("nz", 0, lbch.E_INVALID),
+    ("nz", 40, lbch.OK),
+    ("nx", 1024, lbch.E_INVALID),       # 1024^2 x 1024 x 15 entries exceed the 2^31 index range
+    ("aniso_m", 6, lbch.E_UNSUPPORTED),
+    ("aniso_theta0", 0.1, lbch.E_UNSUPPORTED),
+])
+def test_validate_d3q15(field, value, status):
+    p = lbch.default_params(lattice=lbch.D3Q15, nz=16)
+    if field == "nx":
+        p.ny = p.nz = 1024
+    setattr(p, field, value)
+    assert lbch.validate(p) == status
+
+
+def test_validate_d3q15_free_rates():
+    p = lbch.default_params(lattice=lbch.D3Q15, nz=16, s=(0.0, 1.0, 1.0, 1.7, 1.0, 1.7, 1.0, 1.0, 1.0))
+    assert lbch.validate(p) == lbch.OK                  # s0, s3, s5 ignored
+    p = lbch.default_params(lattice=lbch.D3Q15, nz=16, s=(1.0, 1.2, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0))
+    assert lbch.validate(p) == lbch.E_UNSUPPORTED
