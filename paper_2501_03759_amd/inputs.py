@@ -56,6 +56,23 @@ def sphere(nx: int, ny: int, nz: int, radius: float, eps_w: float, centre=None) 
     return np.tanh((radius - r) / (math.sqrt(2.0) * eps_w))
 
 
+def sphere_width(n: int, radius: float, width_D: float, centre=None) -> np.ndarray:
+    """Eq 43 form on an n^3 box: tanh(2 (R - r) / D), default centre (n/2, n/2, n/2)."""
+    c = (n // 2,) * 3 if centre is None else centre
+    return sphere(n, n, n, radius, width_D / (2.0 * math.sqrt(2.0)), c)
+
+
+def two_spheres(n: int, width_D: float, balls=((28, 45, 40, 40), (12, 75, 75, 75))) -> np.ndarray:
+    """Two-ball form of the paper's second 3D test: sum_i tanh(2 (R_i - r_i) / D) + 1 with
+    (R_i, x_i, y_i, z_i), r_i the minimum-image distance."""
+    z, y, x = np.mgrid[0:n, 0:n, 0:n].astype(np.float64)
+    out = np.ones((n, n, n))
+    for (R, x0, y0, z0) in balls:
+        r = np.sqrt(min_image(x - x0, n) ** 2 + min_image(y - y0, n) ** 2 + min_image(z - z0, n) ** 2)
+        out += np.tanh(2.0 * (R - r) / width_D)
+    return out
+
+
 def wavy_slab(nx: int, ny: int, nz: int, eps_w: float, z_lo: float, z_hi: float, amp: float = 1.0) -> np.ndarray:
     """A layer phi ~ +1 between two tanh interfaces normal to z, [nz][ny][nx]; the lower
     interface is displaced by amp (sin(2 pi x / nx) + 0.7 cos(2 pi y / ny)), the upper by

@@ -145,6 +145,24 @@ def test_full_size_sampled():
     assert np.abs(np.array([got[q] for q in pts]) - want).max() <= 1e-6
 
 
+@pytest.mark.parametrize("alpha", [0.1, 0.3])
+def test_paper_droplet_eq43_sampled(alpha):
+    # the paper's 3D droplet (Section 4, eq 43: R = 25 on 100^3, phi0 = tanh(2 (R - r) / D))
+    # with the parameters of eq 39 (M = 0.1, Willmore eps = 0.03, D = 5, sigma = 0.01), FP64,
+    # five steps at the launch shape of the full box, sampled on and off the interface
+    L = lb()
+    n = 100
+    p = L.default_params(lattice=L.D3Q15, nx=n, ny=n, nz=n, precision=L.FP64, alpha=alpha)
+    phi0 = inputs.sphere_width(n, 25.0, 5.0, centre=(50, 50, 50))
+    with L.Sim(p) as s:
+        s.init(phi0)
+        s.step(5)
+        got = s.phi()
+    pts = [(50, 50, 75), (50, 75, 50), (75, 50, 50), (64, 64, 64), (50, 50, 50), (0, 0, 0), (33, 58, 71)]
+    want = common.sampled_oracle_phi3(phi0, p, 5, pts)
+    assert np.abs(np.array([got[q] for q in pts]) - want).max() <= FP64_TOL
+
+
 def test_unsupported_options():
     L = lb()
     p = params3(30, 12, 8, 1)
