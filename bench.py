@@ -270,6 +270,7 @@ def step3d_workload(args):
                             mobility=d["mobility"], alpha=d["alpha"], eps_reg=d["eps_reg"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    copy = copy_ceiling(torch, lbch, stream)
     sim = lbch.Sim(p, stream)
     if args.tiling:
         sim.set_tiling(*(int(v) for v in args.tiling.split(",")))
@@ -305,6 +306,7 @@ def step3d_workload(args):
                      "launch_ms": round(ms_step, 4), "updates_per_launch": nodes,
                      "bytes_per_update": bytes_per_update},
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
+        "hbm_copy": copy,
     }
     print(json.dumps(out), flush=True)
 

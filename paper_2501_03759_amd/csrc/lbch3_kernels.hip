@@ -32,6 +32,10 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+template <typename T> __device__ __forceinline__ T recip(T x);
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
 // gamma of eq 6 (d = 3) and h_a with |grad phi| (P grad_n gamma)_a = p_a h_a:
 // n_a^2 = p_a^2 / |p|^2, s4 = sum n_a^4, gamma = 1 + alpha (4 s4 - 3),
 // h_a = 16 alpha (n_a^2 - s4).  gamma = 1, h = 0 where |grad phi| <= floor.
@@ -41,7 +45,7 @@ __device__ __forceinline__ void aniso3(T px, T py, T pz, const StepCoef3<T>& c, 
     gamma = T(1);
     hx = hy = hz = T(0);
     if (g2 > c.floor2) {
-        const T inv = T(1) / g2;
+        const T inv = recip<T>(g2);
         const T a = px * px * inv, b = py * py * inv, d = pz * pz * inv;
         const T s4 = (a * a + b * b) + d * d;
         gamma = T(1) + c.alpha * (T(4) * s4 - T(3));
@@ -119,6 +123,13 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
     // pull sources: column x - e_ix, row y - e_iy (wrapped once per lane)
     const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    // 32-bit in-slab byte offsets of the nine (x, y) sources (a slab holds
+    // fewer than 2^31 / 15 elements); the slab and plane parts of every
+    // address are uniform over the workgroup
+    constexpr unsigned ES = sizeof(T);
+    const unsigned rc = (unsigned)(y * g.pitch), rm = (unsigned)(ym * g.pitch), rp = (unsigned)(yp * g.pitch);
+    const unsigned oxy[9] = {(rc + x) * ES,  (rc + xm) * ES, (rc + xp) * ES, (rm + x) * ES, (rp + x) * ES,
+                             (rm + xm) * ES, (rp + xp) * ES, (rp + xm) * ES, (rm + xp) * ES};
     const int niter = hl + 6;
 
     T red[U][4];      // phi, j_x, j_y, j_z of the pulled node (A -> D)
@@ -130,10 +141,13 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
         const int zm = zr == 0 ? g.nz - 1 : zr - 1, zp = zr == g.nz - 1 ? 0 : zr + 1;
 #pragma unroll
         for (int i = 0; i < 15; ++i) {
-            const int xs = kEX[i] > 0 ? xm : (kEX[i] < 0 ? xp : x);
-            const int ys = kEY[i] > 0 ? ym : (kEY[i] < 0 ? yp : y);
+            // source (x - e_ix, y - e_iy): index into oxy
+            const int sx = kEX[i] > 0 ? 1 : (kEX[i] < 0 ? 2 : 0);
+            const int sy = kEY[i] > 0 ? 1 : (kEY[i] < 0 ? 2 : 0);
+            const int k = sy == 0 ? sx : (sx == 0 ? 2 + sy : (sx == sy ? 4 + sx : (sy == 2 ? 7 : 8)));
             const int zs = kEZ[i] > 0 ? zm : (kEZ[i] < 0 ? zp : zr);
-            b[i] = fin[(long long)i * g.plane + (long long)zs * g.slab + (long long)ys * g.pitch + xs];
+            const char* __restrict__ base = (const char*)(fin + ((long long)i * g.plane + (long long)zs * g.slab));
+            b[i] = *(const T*)(base + oxy[k]);
         }
     };
 
@@ -227,9 +241,11 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                     }
                     if (store_lane) {
                         const int rd = z0 - 6 + j;
-                        T* __restrict__ q = fout + ((long long)rd * g.slab + (long long)y * g.pitch + x);
 #pragma unroll
-                        for (int i = 0; i < 15; ++i) q[(long long)i * g.plane] = o[i];
+                        for (int i = 0; i < 15; ++i) {
+                            char* __restrict__ q = (char*)(fout + ((long long)i * g.plane + (long long)rd * g.slab));
+                            *(T*)(q + oxy[0]) = o[i];
+                        }
                     }
                 }
             }
@@ -415,25 +431,36 @@ int blocks3(long long n) {
 }
 }  // namespace
 
-int step3_blocks_per_cu(int precision) {
+namespace {
+template <typename T, int TX, int TY>
+int occ3() {
     int n = 0;
-    hipError_t e = precision == 0
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step3_fused<double, kTile3X, kTile3Y>, kTile3X * kTile3Y, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step3_fused<float, kTile3X, kTile3Y>, kTile3X * kTile3Y, 0);
-    if (e != hipSuccess || n < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step3_fused<T, TX, TY>, TX * TY, 0) != hipSuccess || n < 1) {
         (void)hipGetLastError();
         n = 1;
     }
     return n;
 }
+}  // namespace
+
+bool tile3_supported(int precision, int tx, int ty) {
+    return (tx == 32 && ty == 16) || (precision == 1 && tx == 32 && ty == 32);
+}
+
+int step3_blocks_per_cu(int precision, int tx, int ty) {
+    if (precision == 0) return occ3<double, 32, 16>();
+    return ty == 32 ? occ3<float, 32, 32>() : occ3<float, 32, 16>();
+}
 
 // hz = 0: the sweep length that minimises rounds * (hz + 6), where a round is
 // one wave of `slots` resident workgroups and hz + 6 the iterations of a
 // sweep (6 start-up slabs), over hz in [4, nz].
-Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots) {
+Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty) {
     Tiling3 t{};
-    t.tiles_x = (nx + kTile3X - 7) / (kTile3X - 6);
-    t.tiles_y = (ny + kTile3Y - 7) / (kTile3Y - 6);
+    t.tx = tx;
+    t.ty = ty;
+    t.tiles_x = (nx + tx - 7) / (tx - 6);
+    t.tiles_y = (ny + ty - 7) / (ty - 6);
     const long long cols = (long long)t.tiles_x * t.tiles_y;
     if (hz <= 0) {
         if (slots <= 0) slots = 256;
@@ -458,12 +485,17 @@ Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots) {
 
 hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3& g, const Tiling3& t,
                         const void* coef, hipStream_t s) {
-    if (precision == 0)
-        step3_fused<double, kTile3X, kTile3Y><<<t.nblocks, kTile3X * kTile3Y, 0, s>>>(
-            (const double*)fin, (double*)fout, g, t, *(const StepCoef3<double>*)coef);
-    else
-        step3_fused<float, kTile3X, kTile3Y><<<t.nblocks, kTile3X * kTile3Y, 0, s>>>(
-            (const float*)fin, (float*)fout, g, t, *(const StepCoef3<float>*)coef);
+    if (!tile3_supported(precision, t.tx, t.ty)) return hipErrorInvalidValue;
+    if (precision == 0) {
+        step3_fused<double, 32, 16><<<t.nblocks, 512, 0, s>>>((const double*)fin, (double*)fout, g, t,
+                                                              *(const StepCoef3<double>*)coef);
+    } else if (t.ty == 32) {
+        step3_fused<float, 32, 32><<<t.nblocks, 1024, 0, s>>>((const float*)fin, (float*)fout, g, t,
+                                                              *(const StepCoef3<float>*)coef);
+    } else {
+        step3_fused<float, 32, 16><<<t.nblocks, 512, 0, s>>>((const float*)fin, (float*)fout, g, t,
+                                                             *(const StepCoef3<float>*)coef);
+    }
     return hipGetLastError();
 }
 

@@ -312,6 +312,14 @@ void fill_coef3(const lbch_params* p, StepCoef3<T>& c) {
     c.qform = p->q_form;
 }
 
+// D3Q15 tiling: block_threads 512 = 32 x 16 lanes, 1024 = 32 x 32 (FP32
+// only); 0 = the default of the precision.  hz = 0: the sweep-length model.
+static Tiling3 sim_tiling3(const lbch_sim* s, int block_threads, int hz) {
+    if (block_threads == 0) block_threads = s->precision == LBCH_FP32 ? 1024 : 512;
+    const int tx = 32, ty = block_threads / 32;
+    return make_tiling3(s->g3.nx, s->g3.ny, s->g3.nz, hz, s->cus * step3_blocks_per_cu(s->precision, tx, ty), tx, ty);
+}
+
 template void fill_coef<double>(const lbch_params*, StepCoef<double>&);
 template void fill_coef<float>(const lbch_params*, StepCoef<float>&);
 template void fill_coef3<double>(const lbch_params*, StepCoef3<double>&);
@@ -407,7 +415,7 @@ extern "C" lbch_status lbch_create(const lbch_params* p, void* hip_stream, lbch_
         plane = s->g3.plane;
         fill_coef3<double>(p, s->c3d);
         fill_coef3<float>(p, s->c3f);
-        s->t3 = make_tiling3(p->nx, p->ny, p->nz, 0, s->cus * step3_blocks_per_cu(s->precision));
+        s->t3 = sim_tiling3(s, 0, 0);
         s->t1.depth = 1;
         s->t.depth = 1;
     } else {
@@ -671,10 +679,11 @@ extern "C" lbch_status lbch_set_tiling(lbch_sim* s, int32_t block_threads, int32
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
     if (s->d3) {
-        if (block_threads != 0 && block_threads != kTile3X * kTile3Y)
-            return fail(LBCH_E_INVALID, "D3Q15 block_threads %d not in {0, %d}", block_threads, kTile3X * kTile3Y);
+        if (block_threads != 0 && (block_threads % 32 != 0 || !tile3_supported(s->precision, 32, block_threads / 32)))
+            return fail(LBCH_E_INVALID, "D3Q15 block_threads %d not in {0, 512%s}", block_threads,
+                        s->precision == LBCH_FP32 ? ", 1024" : "");
         if (rows_per_block < 0) return fail(LBCH_E_INVALID, "rows_per_block %d < 0", rows_per_block);
-        s->t3 = make_tiling3(s->g3.nx, s->g3.ny, s->g3.nz, rows_per_block, s->cus * step3_blocks_per_cu(s->precision));
+        s->t3 = sim_tiling3(s, block_threads, rows_per_block);
         return ok();
     }
     const int depth = s->t.depth;
@@ -705,7 +714,7 @@ extern "C" lbch_status lbch_set_row_loader(lbch_sim* s, int32_t mode) {
 extern "C" lbch_status lbch_get_tiling(const lbch_sim* s, int32_t* block_threads, int32_t* rows_per_block) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
-    if (block_threads) *block_threads = s->d3 ? kTile3X * kTile3Y : s->t.nt;
+    if (block_threads) *block_threads = s->d3 ? s->t3.tx * s->t3.ty : s->t.nt;
     if (rows_per_block) *rows_per_block = s->d3 ? s->t3.hz : s->t.hc;
     return ok();
 }

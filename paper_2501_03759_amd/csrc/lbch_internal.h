@@ -120,14 +120,13 @@ struct Grid3 {
     long long plane;      // elements between consecutive population planes
 };
 
-// x-y tiles of (kTile3X - 6) x (kTile3Y - 6) nodes, each swept over `hz`
-// consecutive slabs; tiles are x-fastest, then y, then z chunk, and are
-// dealt to the 8 XCDs in contiguous ranges of `per_xcd`.
+// Workgroups of tx x ty lanes store x-y tiles of (tx - 6) x (ty - 6) nodes,
+// each swept over `hz` consecutive slabs; tiles are x-fastest, then y, then
+// z chunk, and are dealt to the 8 XCDs in contiguous ranges of `per_xcd`.
+// Built shapes: 32 x 16 (both precisions) and 32 x 32 (FP32).
 struct Tiling3 {
-    int tiles_x, tiles_y, hz, zchunks, ntiles, per_xcd, nblocks;
+    int tx, ty, tiles_x, tiles_y, hz, zchunks, ntiles, per_xcd, nblocks;
 };
-
-constexpr int kTile3X = 32, kTile3Y = 16;
 
 // Per-step constants of the D3Q15 step in the working precision.
 template <typename T>
@@ -144,8 +143,9 @@ struct StepCoef3 {
 
 template <typename T>
 void fill_coef3(const lbch_params* p, StepCoef3<T>& c);
-Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots);
-int step3_blocks_per_cu(int precision);
+Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty);
+bool tile3_supported(int precision, int tx, int ty);
+int step3_blocks_per_cu(int precision, int tx, int ty);
 hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3& g, const Tiling3& t,
                         const void* coef, hipStream_t s);
 hipError_t launch_init3(int precision, const void* phi0, int phi_dtype, void* fout, const Grid3& g, const void* coef,

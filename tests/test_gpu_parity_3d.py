@@ -27,11 +27,11 @@ def params3(nx, ny, nz, precision=0, **kw):
     return common.make_params(nx, ny, precision, lattice=lb().D3Q15, nz=nz, **kw)
 
 
-def run3(p, phi0, nsteps, hz=None):
+def run3(p, phi0, nsteps, hz=None, threads=0):
     L = lb()
     with L.Sim(p) as s:
-        if hz is not None:
-            s.set_tiling(0, hz)
+        if hz is not None or threads:
+            s.set_tiling(threads, hz or 0)
         s.init(phi0)
         s.step(nsteps)
         return s.phi()
@@ -70,8 +70,9 @@ def test_wavy_layer_fp32_1000_steps():
     p = params3(nx, ny, nz, 1, alpha=0.3)
     phi0 = inputs.wavy_slab(nx, ny, nz, 1.5, 6.0, 18.0)
     want = common.oracle_phi3(phi0, p, 1000)
-    got = run3(p, phi0, 1000)
-    assert np.abs(got - want).max() <= FP32_TOL
+    for threads in (512, 1024):
+        got = run3(p, phi0, 1000, threads=threads)
+        assert np.abs(got - want).max() <= FP32_TOL, threads
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -80,9 +81,11 @@ def test_z_sweep_length_is_bitwise(precision):
     p = params3(nx, ny, nz, precision, alpha=0.3)
     phi0 = inputs.spinodal3(nx, ny, nz, seed=11, amp=0.2)
     ref = run3(p, phi0, 40)
-    for hz in (1, 4, 7, 19):
-        print(f"case hz={hz} precision={precision}", flush=True)
-        assert np.array_equal(run3(p, phi0, 40, hz), ref), hz
+    shapes = (512, 1024) if precision == 1 else (512,)
+    for threads in shapes:
+        for hz in (1, 4, 7, 19):
+            print(f"case threads={threads} hz={hz} precision={precision}", flush=True)
+            assert np.array_equal(run3(p, phi0, 40, hz, threads), ref), (threads, hz)
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 2, 1), (1, 1, 7), (5, 13, 2), (27, 11, 3)])
@@ -163,6 +166,51 @@ def test_paper_droplet_eq43_sampled(alpha):
     assert np.abs(np.array([got[q] for q in pts]) - want).max() <= FP64_TOL
 
 
+def _zero_crossing(profile, step):
+    """Distance from the first node to where a profile falling from > 0 to < 0 crosses zero
+    (linear interpolation between nodes spaced `step` apart)."""
+    k = int(np.argmax(profile < 0))
+    assert k > 0 and profile[k - 1] >= 0
+    return step * (k - 1 + profile[k - 1] / (profile[k - 1] - profile[k]))
+
+
+def test_paper_droplet_eq43_becomes_octahedral():
+    # Qualitative behaviour the paper reports for its 3D droplet (Section 4, eq 43, eq 39
+    # parameters): with the cubic anisotropy of eq 6 the ball deforms towards a shape with
+    # corners along the axes (where gamma is largest) and flat sides facing the body
+    # diagonals, while mass is conserved and the free energy decreases; without anisotropy it
+    # stays a ball.  FP32, 100^3, 40000 steps.
+    L = lb()
+    n, c = 100, 50
+    radii = {}
+    for alpha in (0.0, 0.3):
+        p = L.default_params(lattice=L.D3Q15, nx=n, ny=n, nz=n, precision=L.FP32, alpha=alpha)
+        with L.Sim(p) as s:
+            s.init(inputs.sphere_width(n, 25.0, 5.0, centre=(c, c, c)))
+            _, m0, _, _ = s.moments(want_phi=False)
+            energies = [s.free_energy()[0]]
+            for _ in range(8):
+                s.step(5000)
+                energies.append(s.free_energy()[0])
+            phi, m1, _, _ = s.moments()
+        print(f"case alpha={alpha} energies={energies}", flush=True)
+        assert all(b <= a for a, b in zip(energies, energies[1:])), energies
+        assert abs(m1 - m0) <= 1e-4 * abs(m0)
+        # cubic symmetry: axis permutations and the reflection x -> 2c - x
+        refl = np.roll(phi[:, :, ::-1], 2 * c + 1 - n, axis=2)
+        for other in (phi.transpose(1, 0, 2), phi.transpose(2, 1, 0), refl):
+            assert np.abs(phi - other).max() <= 1e-3
+        ax = _zero_crossing(phi[c, c, c:], 1.0)
+        diag = _zero_crossing(np.array([phi[c + k, c + k, c + k] for k in range(n - c)]), 3 ** 0.5)
+        radii[alpha] = (ax, diag)
+    print(f"case radii (axis, diagonal) {radii}", flush=True)
+    ax0, dg0 = radii[0.0]
+    ax3, dg3 = radii[0.3]
+    assert abs(ax0 - dg0) <= 0.6, radii                  # still a ball
+    # corners along the axes, flat towards the diagonals (measured: +3.4 and -0.9 nodes)
+    assert ax3 >= ax0 + 2.0 and dg3 <= dg0 - 0.5, radii
+
+
 def test_unsupported_options():
     L = lb()
     p = params3(30, 12, 8, 1)
@@ -172,11 +220,14 @@ def test_unsupported_options():
         assert ei.value.status == L.E_UNSUPPORTED
         s.set_time_blocking(1)
         assert s.time_blocking() == 1
-        with pytest.raises(L.LbchError) as ei:
-            s.set_tiling(256, 0)
-        assert ei.value.status == L.E_INVALID
-        s.set_tiling(0, 3)
+        for bad in (256, 520, 2048):
+            with pytest.raises(L.LbchError) as ei:
+                s.set_tiling(bad, 0)
+            assert ei.value.status == L.E_INVALID
+        s.set_tiling(512, 3)
         assert s.tiling() == (512, 3)
+        s.set_tiling(0, 3)
+        assert s.tiling() == (1024, 3)
         s.init(inputs.spinodal3(30, 12, 8, seed=1))
         with pytest.raises(L.LbchError) as ei:
             s.autotune(1)
@@ -184,3 +235,8 @@ def test_unsupported_options():
     with pytest.raises(L.LbchError) as ei:
         L.Batch([p])
     assert ei.value.status == L.E_UNSUPPORTED
+    with L.Sim(params3(30, 12, 8, 0)) as s:
+        with pytest.raises(L.LbchError) as ei:
+            s.set_tiling(1024, 0)                  # 32 x 32 lanes exceed the LDS in FP64
+        assert ei.value.status == L.E_INVALID
+        assert s.tiling()[0] == 512
