@@ -30,17 +30,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(n_nodes: int, precision: str, depth: int):
+def measured_traffic(n_nodes: int, precision: str, depth: int, lattice: str = "d2q9"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
     the current kernel source at this size and depth; else None."""
-    from paper_2501_03759_amd.profiling import STEP_KERNELS, kernel_hash
-    side = int(round(n_nodes ** 0.5))
-    path = os.path.join(ROOT, "profiles", f"{STEP_KERNELS[depth]}_spinodal{side}_{precision}.json")
+    from paper_2501_03759_amd.profiling import STEP_KERNEL_3D, STEP_KERNELS, kernel_hash
+    if lattice == "d3q15":
+        side = int(round(n_nodes ** (1.0 / 3.0)))
+        path = os.path.join(ROOT, "profiles", f"{STEP_KERNEL_3D}_spinodal{side}_{precision}.json")
+    else:
+        side = int(round(n_nodes ** 0.5))
+        path = os.path.join(ROOT, "profiles", f"{STEP_KERNELS[depth]}_spinodal{side}_{precision}.json")
     try:
         rec = json.load(open(path))
     except Exception:
         return None
-    if (rec.get("kernel_sha256_16") != kernel_hash() or rec.get("nodes") != n_nodes
+    if (rec.get("kernel_sha256_16") != kernel_hash(lattice) or rec.get("nodes") != n_nodes
             or rec.get("precision") != precision or rec.get("depth", 1) != depth):
         return None
     return rec.get("bytes_per_launch")
@@ -302,7 +306,8 @@ def step3d_workload(args):
                    "alpha": d["alpha"], "regularization": "willmore", "eps_reg": d["eps_reg"],
                    "mobility": d["mobility"], "time_steps_per_launch": 1, "tiling": list(tiling)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "step3_fused",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(nodes, args.precision, 1, "d3q15"), "kernel": "step3_fused",
                      "launch_ms": round(ms_step, 4), "updates_per_launch": nodes,
                      "bytes_per_update": bytes_per_update},
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},

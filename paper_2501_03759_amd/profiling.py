@@ -20,13 +20,16 @@ import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_03759_amd", "csrc", "lbch_kernels.hip")
+KERNEL_SRC_3D = os.path.join(ROOT, "paper_2501_03759_amd", "csrc", "lbch3_kernels.hip")
 STEP_KERNELS = {1: "step_fused", 2: "step2_fused"}   # by time steps per launch
+STEP_KERNEL_3D = "step3_fused"
 COPY_KERNEL = "copy16_k"
 COPY_BYTES = 1 << 30          # bench.py's copy_ceiling buffer
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(lattice: str = "d2q9") -> str:
+    src = KERNEL_SRC_3D if lattice == "d3q15" else KERNEL_SRC
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
 def _one(pattern):
@@ -76,11 +79,16 @@ def main():
     ap.add_argument("--nodes", type=int, default=0)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per launch of the step kernel")
+    ap.add_argument("--lattice", default="d2q9", choices=["d2q9", "d3q15"])
     ap.add_argument("--command", required=True, help="the profiled command lines (for the summary header)")
     ap.add_argument("--out", required=True, help="output prefix, e.g. profiles/step2_fused_spinodal8192_fp32")
     ap.add_argument("--title", default="", help="summary title (stats-only mode)")
     args = ap.parse_args()
-    STEP_KERNEL = STEP_KERNELS[args.depth]
+    d3 = args.lattice == "d3q15"
+    if d3:
+        args.depth = 1
+    STEP_KERNEL = STEP_KERNEL_3D if d3 else STEP_KERNELS[args.depth]
+    q = 15 if d3 else 9
     if not args.fetch:
         stats_only(args)
         return
@@ -95,14 +103,15 @@ def main():
     w_step = statistics.median(counter_values(args.write, "WRITE_SIZE", STEP_KERNEL)) * kib * write_scale
     stats = kernel_stats(args.trace)
     step = [s for s in stats if STEP_KERNEL in s["name"]][0]
-    # algorithmic bytes: 9 populations read + 9 written per lattice update
+    # algorithmic bytes: q populations read + q written per lattice update
     # (the one-step figure), times the updates of one launch; the launch's
     # own minimum traffic is one read and one write of the state
-    alg = 18 * esize * args.nodes * args.depth
-    min_traffic = 18 * esize * args.nodes
+    alg = 2 * q * esize * args.nodes * args.depth
+    min_traffic = 2 * q * esize * args.nodes
     rec = {
         "kernel": step["name"],
-        "kernel_sha256_16": kernel_hash(),
+        "kernel_sha256_16": kernel_hash(args.lattice),
+        "lattice": args.lattice,
         "nodes": args.nodes,
         "precision": args.precision,
         "depth": args.depth,
@@ -130,7 +139,7 @@ def main():
               f"- copy-kernel calibration: FETCH_SIZE x {fetch_scale:.3f}, WRITE_SIZE x {write_scale:.3f} "
               f"(the copy moves {COPY_BYTES} B each way)",
               f"- fetched {f_step / 1e9:.3f} GB, written {w_step / 1e9:.3f} GB per launch of {args.depth} "
-              f"time step(s); algorithmic {alg / 1e9:.3f} GB (72 B FP32 / 144 B FP64 per lattice update x "
+              f"time step(s); algorithmic {alg / 1e9:.3f} GB ({2 * q * esize} B per lattice update x "
               f"{args.depth} updates per node); ratio {rec['traffic_over_algorithmic']:.3f}; one read + one write "
               f"of the state = {min_traffic / 1e9:.3f} GB (measured / that = {(f_step + w_step) / min_traffic:.3f})",
               f"- average duration {rec['avg_duration_ms']:.4f} ms -> {rec['achieved_alg_GBs']:.0f} GB/s algorithmic, "
