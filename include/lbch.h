@@ -135,6 +135,21 @@ lbch_status lbch_params_validate(const lbch_params* p);
 /* The nine relaxation rates actually used (s_3 = s_5 from the mobility). */
 lbch_status lbch_relaxation_rates(const lbch_params* p, double s_out[9]);
 
+/* Collision variants (Section 3: the paper chooses MRT for its stability and
+ * shows no alternative).  All three are rate choices of eq 17 / eq 25 on D2Q9:
+ *   LBCH_COLLISION_MRT  the free rates s[1], s[2], s[4], s[6], s[7], s[8] = 1;
+ *   LBCH_COLLISION_SRT  every rate = s_j (single relaxation time, BGK);
+ *   LBCH_COLLISION_TRT  the moments even under c -> -c (e, eps, p_xx, p_xy:
+ *                       s[1], s[2], s[7], s[8]) at s_+, the odd ones (s[4],
+ *                       s[6], and the fluxes) at s_j, where magic > 0 is
+ *                       Lambda = (1/s_+ - 1/2)(1/s_j - 1/2).
+ * s_j comes from the mobility, dx and dt already in p (set them first).
+ * magic is read for TRT only.  Unknown model, magic <= 0 or non-finite, or a
+ * resulting rate outside (0, 2) -> LBCH_E_INVALID (p unchanged).  D3Q15
+ * simulations accept MRT only (lbch_params_validate). */
+enum { LBCH_COLLISION_MRT = 0, LBCH_COLLISION_SRT = 1, LBCH_COLLISION_TRT = 2 };
+lbch_status lbch_params_set_collision(lbch_params* p, int32_t model, double magic);
+
 /* Library ABI version (LBCH_ABI_VERSION it was built with). */
 int32_t lbch_abi_version(void);
 

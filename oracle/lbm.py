@@ -109,6 +109,27 @@ def relaxation_rates(p: Params) -> np.ndarray:
     return s
 
 
+def collision_free_rates(model: str, p: Params, magic: float = 0.25) -> tuple:
+    """Free rates of the collision variants, for the given mobility and lattice units.
+
+    The paper picks MRT for stability (Section 3) without showing the alternatives:
+    * 'mrt': every rate other than the fluxes' is 1 (the default reading of the free rates).
+    * 'srt': one rate for every moment, the flux rate s_j (BGK).
+    * 'trt': rates by parity under c -> -c: the moments even in c (rows 1, 2, 7, 8 of eq 23:
+      e, eps, p_xx, p_xy) relax at s_plus, the odd ones (rows 3-6: j and q) at s_j, with
+      the magic number (1/s_plus - 1/2)(1/s_j - 1/2) = magic.
+    Entry 0 (phi, conserved) is set like the others and has no effect."""
+    s_j = relaxation_rates(p)[3]
+    if model == "mrt":
+        return (1.0,) * 9
+    if model == "srt":
+        return (s_j,) * 9
+    if model == "trt":
+        s_plus = 1.0 / (0.5 + magic / (1.0 / s_j - 0.5))
+        return (s_plus, s_plus, s_plus, s_j, s_j, s_j, s_j, s_plus, s_plus)
+    raise ValueError(model)
+
+
 # --------------------------------------------------------------- stencils --
 def neighbour(chi: np.ndarray, i: int) -> np.ndarray:
     """chi(x + c_i dt) on the periodic grid (Section 4 uses periodic boundaries)."""

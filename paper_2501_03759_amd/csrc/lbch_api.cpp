@@ -147,6 +147,31 @@ extern "C" lbch_status lbch_relaxation_rates(const lbch_params* p, double s_out[
     return ok();
 }
 
+extern "C" lbch_status lbch_params_set_collision(lbch_params* p, int32_t model, double magic) {
+    if (!p) return fail(LBCH_E_INVALID, "params pointer is NULL");
+    if (!(p->mobility > 0) || !(p->dx > 0) || !(p->dt > 0) || !isfin(p->mobility) || !isfin(p->dx) ||
+        !isfin(p->dt))
+        return fail(LBCH_E_INVALID, "mobility, dx, dt must be positive and finite");
+    const double sj = s_j_of(p);
+    double s[9];
+    if (model == LBCH_COLLISION_MRT) {
+        for (double& v : s) v = 1.0;
+    } else if (model == LBCH_COLLISION_SRT) {
+        for (double& v : s) v = sj;
+    } else if (model == LBCH_COLLISION_TRT) {
+        if (!(magic > 0) || !isfin(magic)) return fail(LBCH_E_INVALID, "magic = %g must be > 0", magic);
+        const double sp = 1.0 / (0.5 + magic / (1.0 / sj - 0.5));
+        if (!(sp > 0 && sp < 2)) return fail(LBCH_E_INVALID, "TRT rate s_+ = %g outside (0, 2)", sp);
+        const double tr[9] = {sp, sp, sp, sj, sj, sj, sj, sp, sp};
+        for (int k = 0; k < 9; ++k) s[k] = tr[k];
+    } else {
+        return fail(LBCH_E_INVALID, "unknown collision model %d", model);
+    }
+    if (!(sj > 0 && sj < 2)) return fail(LBCH_E_INVALID, "s_j = %g outside (0, 2)", sj);
+    for (int k = 0; k < 9; ++k) p->s[k] = s[k];
+    return ok();
+}
+
 // ---------------------------------------------------------------- helpers
 namespace lbch {
 

@@ -26,6 +26,7 @@ FP64, FP32 = 0, 1
 BC_PERIODIC = 0
 REG_NONE, REG_LINEAR, REG_WILLMORE = 0, 1, 2
 Q_DERIVED, Q_LITERAL = 0, 1
+COLLISION_MRT, COLLISION_SRT, COLLISION_TRT = 0, 1, 2
 ABI_VERSION = 2
 
 
@@ -67,6 +68,7 @@ _SIGNATURES = {
     "lbch_params_from_sigma_width": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double]),
     "lbch_params_validate": (ctypes.c_int, [ctypes.POINTER(Params)]),
     "lbch_relaxation_rates": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_double)]),
+    "lbch_params_set_collision": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_double]),
     "lbch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "lbch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "lbch_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
@@ -162,6 +164,12 @@ def default_params(**overrides) -> Params:
 
 def validate(p: Params) -> int:
     return lib().lbch_params_validate(ctypes.byref(p))
+
+
+def set_collision(p: Params, model: int, magic: float = 0.25) -> Params:
+    """Sets the free rates of p for MRT, SRT or TRT (lbch_params_set_collision); returns p."""
+    _check(lib().lbch_params_set_collision(ctypes.byref(p), model, magic), "lbch_params_set_collision")
+    return p
 
 
 def relaxation_rates(p: Params) -> np.ndarray:

@@ -409,3 +409,16 @@ def test_autotune_keeps_state_and_results():
         assert s.nstep == 10 and np.array_equal(s.phi(), before)
         s.step(30)
         assert np.array_equal(s.phi(), want)
+
+
+@pytest.mark.parametrize("model,magic", [(1, 0.25), (2, 0.25), (2, 1.0 / 12.0)])
+def test_collision_variants_against_oracle(model, magic):
+    # SRT and TRT rate presets (host-side lbch_params_set_collision) on the eq 40 droplet at
+    # the eq 39 parameters with alpha = 0.3: the general-rate collision path, both depths
+    L = lb()
+    p = L.set_collision(L.default_params(nx=64, ny=48, precision=L.FP64, alpha=0.3), model, magic)
+    phi0 = inputs.droplet_width(16.0, 5.0, 64, 48)
+    want = common.oracle_phi(phi0, p, 301)
+    for depth in (1, 2):
+        got = run_gpu(p, phi0, 301, depth=depth)
+        assert np.abs(got - want).max() <= FP64_TOL, depth
