@@ -143,19 +143,23 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
 // Weight gradient of the 3x3 convolution on the matrix cores:
 //   P[s][co][tap][ci] = sum over the pixels of split s of dY[p][co] X[p + tap][ci]
 // GEMM per tap: M = co, N = ci, K = pixels.  The operands need 8 consecutive
-// pixels per lane, so dY (16x16 pixels x TCO channels) and the tap-shifted X
-// (16x16 pixels x 16 channels) are staged transposed ([channel][pixel]) in LDS.
-// Wave w owns output channels 16w..16w+15 and all 9 taps of a 16-channel ci
-// block.  Splits are reduced by wgrad_reduce_k (fixed order: deterministic).
+// pixels per lane, so both are staged transposed ([channel][pixel]) in LDS,
+// once per 16x16 pixel tile: dY (TCO channels) and the X halo of the tile's
+// 18 rows (16 channels) in three copies shifted by dx = -1, 0, +1 columns, so
+// that the B operand of every tap is an aligned 16-byte read.  Transposes go
+// through 8-byte writes of four pixels of one channel.  Wave w owns output
+// channels 16w..16w+15 and all 9 taps of a 16-channel ci block.  Splits are
+// reduced by wgrad_reduce_k (fixed order: deterministic).
 // ---------------------------------------------------------------------------
 template <int TCO>
 __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__ X, const __bf16* __restrict__ dY,
                                                       float* __restrict__ part, int N, int H, int Wd, int Ci, int Co,
                                                       int S) {
     constexpr int NT = TCO * 4;          // 64 threads (one wave) per 16 output channels
-    constexpr int KS = 256 + 8;          // row stride (bf16) of the transposed tiles
+    constexpr int KS = 256 + 8;          // channel stride (bf16) of the transposed dY tile
+    constexpr int HS = 18 * 16 + 8;      // channel stride of one shifted X copy: 18 rows x 16 pixels
     __shared__ __align__(16) __bf16 sdy[TCO * KS];
-    __shared__ __align__(16) __bf16 sxt[16 * KS];
+    __shared__ __align__(16) __bf16 sxh[3 * 16 * HS];
     const int s = blockIdx.x;
     const int co0 = blockIdx.y * TCO;
     const int ci0 = blockIdx.z * 16;
@@ -172,30 +176,46 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
         const int ty0 = (b % tiles_y) * 16;
         const int n = b / tiles_y;
         __syncthreads();
-        for (int q = threadIdx.x; q < 256 * (TCO / 8); q += NT) {
-            const int p = q / (TCO / 8), ch = q - p * (TCO / 8);
-            const int y = ty0 + (p >> 4), x = tx0 + (p & 15);
-            const bf16x8 v =
-                *reinterpret_cast<const bf16x8*>(dY + (((size_t)n * H + y) * Wd + x) * Co + co0 + ch * 8);
+        // dY^T: item = (channel group of 8, quad of 4 pixels in one tile row)
+        for (int q = threadIdx.x; q < 64 * (TCO / 8); q += NT) {
+            const int pq = q & 63, ch = q >> 6;
+            const int p0 = pq * 4;
+            const __bf16* src = dY + (((size_t)n * H + ty0 + (p0 >> 4)) * Wd + tx0 + (p0 & 15)) * Co + co0 + ch * 8;
+            bf16x8 v[4];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) sdy[(ch * 8 + e) * KS + p] = v[e];
+            for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const bf16x8*>(src + (size_t)u * Co);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<bf16x4*>(sdy + (ch * 8 + e) * KS + p0) = bf16x4{v[0][e], v[1][e], v[2][e], v[3][e]};
         }
+        // X halo: item = (shift dx, halo row 0..17, pixel quad, channel group); copy dx holds
+        // X[row ty0 - 1 + r][column tx0 + px + dx] at [ch][r * 16 + px]
+        for (int q = threadIdx.x; q < 3 * 18 * 4 * 2; q += NT) {
+            const int pq = q & 3, ch = (q >> 2) & 1, rr = q >> 3;
+            const int r = rr % 18, c = rr / 18;
+            const int y = wrap(ty0 - 1 + r, H);
+            bf16x8 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = wrap(tx0 + pq * 4 + u + c - 1, Wd);
+                v[u] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<bf16x4*>(sxh + (c * 16 + ch * 8 + e) * HS + r * 16 + pq * 4) =
+                    bf16x4{v[0][e], v[1][e], v[2][e], v[3][e]};
+        }
+        __syncthreads();
+#pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-            __syncthreads();
-            for (int q = threadIdx.x; q < 256 * 2; q += NT) {
-                const int p = q >> 1, ch = q & 1;
-                const int y = wrap(ty0 + (p >> 4) + dy, H), x = wrap(tx0 + (p & 15) + dx, Wd);
-                const bf16x8 v =
-                    *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) sxt[(ch * 8 + e) * KS + p] = v[e];
-            }
-            __syncthreads();
 #pragma unroll
             for (int k0 = 0; k0 < 256; k0 += 32) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(sdy + (wave * 16 + l16) * KS + k0 + kb * 8);
-                const bf16x8 bb = *reinterpret_cast<const bf16x8*>(sxt + l16 * KS + k0 + kb * 8);
+                // pixels k0 + 8 kb .. + 7: tile row py, columns px0 .. px0 + 7
+                const int k = k0 + kb * 8, py = k >> 4, px0 = k & 15;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(sdy + (wave * 16 + l16) * KS + k);
+                const bf16x8 bb =
+                    *reinterpret_cast<const bf16x8*>(sxh + ((dx + 1) * 16 + l16) * HS + (py + 1 + dy) * 16 + px0);
                 acc[tap] = mfma16(a, bb, acc[tap]);
             }
         }
