@@ -240,3 +240,66 @@ def test_unsupported_options():
             s.set_tiling(1024, 0)                  # 32 x 32 lanes exceed the LDS in FP64
         assert ei.value.status == L.E_INVALID
         assert s.tiling()[0] == 512
+
+
+@pytest.mark.parametrize("reg", [0, 1, 2])
+def test_free_energy_terms_each_regularisation(reg):
+    L = lb()
+    nx, ny, nz = 22, 17, 13
+    p = params3(nx, ny, nz, 0, alpha=0.2, regularization=reg, eps_reg=0.05)
+    op = common.oracle_params3(p)
+    phi0 = inputs.sphere(nx, ny, nz, 5.0, 1.5, centre=(10, 8, 6))
+    f_want = lbm3.run(phi0, op, 25)
+    want = lbm3.free_energy_terms(lbm3.phi_of(f_want), op)
+    with L.Sim(p) as s:
+        s.init(phi0)
+        s.step(25)
+        e, terms = s.free_energy()
+    for got, key in zip(terms, ("grad", "bulk", "reg", "total")):
+        assert abs(got - want[key]) <= 1e-10 * max(1.0, abs(want[key])), key
+    assert abs(e - want["total"]) <= 1e-10 * max(1.0, abs(want["total"]))
+
+
+def test_device_init_and_device_phi():
+    # lbch_init_device from FP32 and FP64 device arrays [nz][ny][nx] equals the host init of
+    # the same values; lbch_phi_device writes what lbch_moments returns
+    import torch
+    L = lb()
+    nx, ny, nz = 29, 12, 9
+    phi0 = inputs.spinodal3(nx, ny, nz, seed=4, amp=0.3)
+    for precision in (0, 1):
+        p = params3(nx, ny, nz, precision, alpha=0.3)
+        phi0_in = phi0.astype(np.float32).astype(np.float64) if precision == 1 else phi0
+        with L.Sim(p) as s:
+            s.init(phi0_in)
+            s.step(7)
+            ref = s.phi()
+            for dtype, tdt in ((L.FP64, torch.float64), (L.FP32, torch.float32)):
+                d = torch.tensor(phi0_in, dtype=tdt, device="cuda")
+                s.init_device(d.data_ptr(), dtype, d.numel())
+                s.step(7)
+                got = s.phi()
+                if dtype == L.FP64 or precision == 1:
+                    assert np.array_equal(got, ref), (precision, dtype)
+                out = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+                s.phi_device(out.data_ptr(), L.FP64)
+                torch.cuda.synchronize()
+                assert np.array_equal(out.cpu().numpy(), got)
+
+
+def test_checkpoints_do_not_cross_lattices():
+    L = lb()
+    p2 = L.default_params(nx=30, ny=12)
+    p3 = params3(30, 12, 8, 0)
+    p3b = params3(30, 12, 9, 0)
+    with L.Sim(p2) as s2, L.Sim(p3) as s3, L.Sim(p3b) as s3b:
+        s2.init(np.zeros((12, 30)))
+        s3.init(np.zeros((8, 12, 30)))
+        blob2, blob3 = s2.save_state(), s3.save_state()
+        for sim, blob in ((s3, blob2), (s2, blob3), (s3b, blob3)):
+            with pytest.raises(L.LbchError) as ei:
+                sim.load_state(blob)
+            assert ei.value.status == L.E_INVALID
+        with pytest.raises(L.LbchError) as ei:
+            s3.init(np.zeros((12, 30)))                     # nx * ny values for an nx * ny * nz box
+        assert ei.value.status == L.E_INVALID
