@@ -651,7 +651,9 @@ hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf1
                      int Co, bool relu, hipStream_t s) {
     if (H % 16 || Wd % 16 || Ci % 32 || Co % 32) return hipErrorInvalidValue;
     const int tiles = N * (H / 16) * (Wd / 16);
-    if (Co % 64 == 0) {
+    // 64 output channels per workgroup unless that leaves fewer than two
+    // workgroups per CU of a 256-CU part (the deep, small levels)
+    if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512) {
         dim3 grid(tiles, Co / 64);
         if (relu) conv3_fwd_k<64, true><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
         else conv3_fwd_k<64, false><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
