@@ -91,8 +91,8 @@ enum {
  * at s_j from the mobility.  Only the case where every other rate is 1 is
  * built (s[1], s[2], s[4], s[6], s[7], s[8] must be 1, else
  * LBCH_E_UNSUPPORTED), and aniso_m must be 4 with aniso_theta0 = 0.  One
- * launch per step (time-blocking depth 1); ensembles, the autotuner and the
- * hybrid schedule return LBCH_E_UNSUPPORTED for D3Q15.
+ * launch per step (time-blocking depth 1); ensembles and the hybrid schedule
+ * return LBCH_E_UNSUPPORTED for D3Q15.
  */
 typedef struct lbch_params {
     int32_t abi_version;      /* must equal LBCH_ABI_VERSION */
@@ -265,7 +265,8 @@ lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t
  * the current state and writing the idle buffer, so the state and the step
  * counter are unchanged), keeps the fastest per step (depth and tiling) and
  * returns its tiling and time per step.  Synchronises.  Before init ->
- * LBCH_E_STATE; D3Q15 -> LBCH_E_UNSUPPORTED. */
+ * LBCH_E_STATE.  D3Q15: every tile shape of lbch_set_tiling x z-sweep lengths
+ * {model default, 4, 8, ..., 128} (at most nz). */
 lbch_status lbch_autotune(lbch_sim* sim, int32_t steps_per_trial, int32_t* block_threads,
                           int32_t* rows_per_block, double* ms_per_step);
 

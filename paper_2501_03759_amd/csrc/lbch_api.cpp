@@ -755,12 +755,61 @@ extern "C" lbch_status lbch_diag_copy(const void* src, void* dst, int64_t bytes,
 }
 
 // ------------------------------------------------------------- autotuner
+namespace {
+
+// D3Q15: every built tile shape x sweep lengths {4, 8, 16, 32, 64, 128, model}
+// (capped at nz), timed like the D2Q9 trials (idle buffer written, state kept).
+lbch_status autotune3(lbch_sim* s, int steps_per_trial, int32_t* block_threads, int32_t* rows_per_block,
+                      double* ms_per_step) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    float best = -1.0f;
+    Tiling3 best_t = s->t3;
+    const int shapes[2] = {512, 1024};
+    const int hzs[7] = {0, 4, 8, 16, 32, 64, 128};
+    for (int bt : shapes) {
+        if (!tile3_supported(s->precision, 32, bt / 32)) continue;
+        for (int hz : hzs) {
+            if (hz > s->g3.nz) continue;
+            const Tiling3 t = sim_tiling3(s, bt, hz);
+            hipError_t e = launch_step3(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g3, t, coef_ptr(s),
+                                        s->stream);
+            if (e == hipSuccess) e = hipEventRecord(a, s->stream);
+            for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k)
+                e = launch_step3(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g3, t, coef_ptr(s), s->stream);
+            if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                return fail(LBCH_E_DEVICE, "autotune trial failed: %s", hipGetErrorString(e));
+            }
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    s->t3 = best_t;
+    if (block_threads) *block_threads = best_t.tx * best_t.ty;
+    if (rows_per_block) *rows_per_block = best_t.hz;
+    if (ms_per_step) *ms_per_step = best / steps_per_trial;
+    return LBCH_OK;
+}
+
+}  // namespace
+
 extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32_t* block_threads,
                                      int32_t* rows_per_block, double* ms_per_step) {
     lbch_status st = check_init(s);
     if (st != LBCH_OK) return st;
     if (steps_per_trial < 1) return fail(LBCH_E_INVALID, "steps_per_trial %d < 1", steps_per_trial);
-    if (s->d3) return fail(LBCH_E_UNSUPPORTED, "the autotuner covers the D2Q9 kernels only");
+    if (s->d3) return autotune3(s, steps_per_trial, block_threads, rows_per_block, ms_per_step);
     // Trials read the current state and write the idle buffer, so the state is untouched.
     const int nts[4] = {64, 128, 256, 512};
     const int hcs[7] = {8, 16, 32, 64, 128, 256, 512};

@@ -229,8 +229,12 @@ def test_unsupported_options():
         s.set_tiling(0, 3)
         assert s.tiling() == (1024, 3)
         s.init(inputs.spinodal3(30, 12, 8, seed=1))
+        ref = s.phi()
+        bt, hz, ms = s.autotune(2)                 # trials leave the state untouched
+        assert bt in (512, 1024) and 1 <= hz <= 8 and ms > 0 and s.tiling() == (bt, hz)
+        assert np.array_equal(s.phi(), ref) and s.nstep == 0
         with pytest.raises(L.LbchError) as ei:
-            s.autotune(1)
+            L.hybrid_advance(s, None, L.hybrid_opts(extrapolate=1), 100)
         assert ei.value.status == L.E_UNSUPPORTED
     with pytest.raises(L.LbchError) as ei:
         L.Batch([p])
