@@ -76,6 +76,82 @@ def cpu_baseline(seconds_target: float = 15.0):
             "sample": f"{steps} steps of a {n}x{n} window of the workload (FP64 NumPy oracle, 1 thread)"}
 
 
+def cpu_baseline_3d(seconds_target: float = 10.0):
+    """The D3Q15 oracle (NumPy, FP64, one thread) on a 32^3 periodic window of the 3D workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lbm, lbm3
+    from paper_2501_03759_amd import inputs
+    d = inputs.C5
+    n = 32
+    kappa, beta = lbm.kappa_beta_from_sigma_width(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"]))
+    p = lbm3.Params(nx=n, ny=n, nz=n, kappa=kappa, beta=beta, mobility=d["mobility"], alpha=d["alpha"],
+                    eps_reg=d["eps_reg"])
+    phi0 = inputs.spinodal3(n, n, n, seed=d["seed"], amp=d["amp"])
+    with threadpool_limits(limits=1):
+        f = lbm3.initial_populations(phi0, p)
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < seconds_target:
+            f = lbm3.step(f, p)
+            steps += 1
+        dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of a {n}^3 box of the workload's recipe (FP64 NumPy D3Q15 oracle, 1 thread)"}
+
+
+def cpu_baseline_ensemble(members, seconds_target: float = 10.0):
+    """The oracle stepping ensemble members one after another (FP64, one thread): the first
+    members of the list in order, as many whole steps over them as fit."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lbm
+    from paper_2501_03759_amd import inputs
+    kappa, beta = lbm.kappa_beta_from_sigma_width(inputs.SIGMA_PAPER, inputs.width_from_eps(1.5))
+    sims = []
+    for m in members[:8]:
+        p = lbm.Params(nx=m["side"], ny=m["side"], kappa=kappa, beta=beta, mobility=0.1, alpha=m["alpha"],
+                       aniso_m=m["m"], eps_reg=0.03)
+        sims.append((p, lbm.initial_populations(inputs.member_phi0(m), p)))
+    nodes = sum(p.nx * p.ny for p, _ in sims)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        sweeps = 0
+        while time.perf_counter() - t0 < seconds_target:
+            sims = [(p, lbm.step(f, p)) for p, f in sims]
+            sweeps += 1
+        dt = time.perf_counter() - t0
+    return {"value": nodes * sweeps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} steps of the first {len(sims)} members ({nodes} nodes; FP64 NumPy oracle, 1 thread)"}
+
+
+def cpu_baseline_unet(chans, c_in, seconds_target: float = 10.0):
+    """The float64 U-Net oracle's forward on one 64 x 64 patch, FLOPs counted as on the GPU."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import unet
+    hw = 64
+    params = unet.init_params(len(chans), chans, c_in, seed=0)
+    x = np.random.default_rng(0).standard_normal((1, hw, hw, c_in))
+    flops = 0.0
+    prev = c_in
+    for l, c in enumerate(chans):
+        flops += 18.0 * (prev * c + c * c) * (hw >> l) ** 2
+        prev = c
+    for l in range(len(chans) - 2, -1, -1):
+        flops += 18.0 * ((chans[l + 1] + chans[l]) * chans[l] + chans[l] * chans[l]) * (hw >> l) ** 2
+    flops += 2.0 * chans[0] * hw * hw
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < seconds_target:
+            unet.forward(params, x, len(chans), chans)
+            reps += 1
+        dt = time.perf_counter() - t0
+    return {"value": flops * reps / dt / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} forwards of one {hw}x{hw} patch (float64 NumPy U-Net oracle, 1 thread)"}
+
+
 def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=5):
     """Practical HBM copy bandwidth (read + write bytes / time) of the library's plain copy kernel."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
@@ -253,6 +329,8 @@ def ensemble_workload(args):
                      "launch_ms": round(launch_ms, 4), "bytes_per_update": 72,
                      "min_bytes_GBs": round(72 * nodes / (launch_ms * 1e-3) / 1e9, 1)},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_ensemble(mems)
     print(json.dumps(out), flush=True)
 
 
@@ -313,6 +391,8 @@ def step3d_workload(args):
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
         "hbm_copy": copy,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_3d()
     print(json.dumps(out), flush=True)
 
 
@@ -370,6 +450,8 @@ def surrogate_workload(args):
                      "frac": round(fwd_tf / 2500.0, 4), "traffic": None, "kernel": "conv3_fwd_k (all layers)"},
         "train_step": {"ms": round(res["train_step"][0], 3), "TFLOP/s": round(res["train_step"][1], 1)},
     }
+    if not args.no_cpu_baseline:
+        out_line["cpu_baseline"] = cpu_baseline_unet(chans, c_in)
     print(json.dumps(out_line), flush=True)
 
 
