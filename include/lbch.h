@@ -253,7 +253,9 @@ lbch_status lbch_get_time_blocking(const lbch_sim* sim, int32_t* depth);
  * workgroup owns a strip of block_threads - 8 * depth columns;
  * rows_per_block >= 1 rows of that strip are swept per workgroup.  The
  * result is bitwise independent of the choice.  0 for either argument
- * restores the built-in default for the grid.  D3Q15: block_threads is 512
+ * restores the built-in default for the grid (for grids with fewer tiles than
+ * CUs at the usual chunk, the shortest chunk of at least 4 rows that keeps at
+ * most 2.5 tiles per CU).  D3Q15: block_threads is 512
  * (32 x 16 lanes storing 26 x 10 nodes) or, in FP32, 1024 (32 x 32 lanes
  * storing 26 x 26; the FP32 default) and rows_per_block is the number of z
  * slabs swept per workgroup. */

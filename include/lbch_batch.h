@@ -64,9 +64,12 @@ lbch_status lbch_batch_get_time_blocking(const lbch_batch* batch, int32_t* depth
 
 /* Launch shape of the current depth: block_threads in {64, 128, 256, 512}
  * ({128, 256, 512} at depth 2, at most 256 in FP64) for every member,
- * rows_per_block >= 1 rows per tile (0 = default), persistent_blocks
+ * rows_per_block >= 1 rows per tile (0 = default: 64 at depth 2, 32 at
+ * depth 1, or for ensembles with fewer tiles than CUs the shortest chunk of
+ * at least 4 rows that keeps at most 2.5 tiles per CU), persistent_blocks
  * workgroups in the persistent grid (0 = fill every CU).  Bitwise
- * independent of the choice. */
+ * independent of the choice.  lbch_batch_get_tiling reports the chunk
+ * height in use. */
 lbch_status lbch_batch_set_tiling(lbch_batch* batch, int32_t block_threads, int32_t rows_per_block,
                                   int32_t persistent_blocks);
 lbch_status lbch_batch_get_tiling(const lbch_batch* batch, int32_t* block_threads, int32_t* rows_per_block,

@@ -259,13 +259,25 @@ static int default_nt(int nx, int depth, int esize) {
 }
 
 // slots: workgroups resident on the whole device at once (0 = unknown).
-Tiling make_tiling(int nx, int ny, int nt, int hc, int depth, int esize, int slots) {
+Tiling make_tiling(int nx, int ny, int nt, int hc, int depth, int esize, int slots, int cus) {
     if (nt == 0) nt = default_nt(nx, depth, esize);
     Tiling t{};
     t.nt = nt;
     t.depth = depth;
     t.W = nt - 8 * depth;  // multiple of 8: strips start on 32-byte boundaries
     t.strips = (nx + t.W - 1) / t.W;
+    const int hmin = depth == 1 ? 16 : 32;
+    if (hc == 0 && cus > 0 && (long long)t.strips * ((ny + hmin - 1) / hmin) < cus) {
+        // small grids: fewer tiles than CUs even at the usual shortest chunk, so a
+        // launch lasts one chunk's sweep; take the shortest chunk (>= 4 rows) that
+        // keeps at most 2.5 workgroups per CU (measured on 100^2 to 1024^2: beyond
+        // that the CUs' shared throughput outweighs the shorter sweep)
+        for (int h = 4; h <= hmin; ++h)
+            if ((long long)t.strips * ((ny + h - 1) / h) * 2 <= 5LL * cus) {
+                hc = h;
+                break;
+            }
+    }
     if (hc == 0) {
         if (depth == 1) {
             // short sweeps measured fastest on 8192^2 (more resident
@@ -308,7 +320,7 @@ static Tiling sim_tiling(const lbch_sim* s, int depth, int nt, int hc) {
     const bool staged = s->user_loader == 0 && s->precision == LBCH_FP32 && s->g.nx % 4 == 0;
     const bool unit = s->precision == LBCH_FP32 ? s->cf.unit != 0 : s->cd.unit != 0;
     const int slots = s->cus * step_blocks_per_cu(s->precision, depth, nt, unit, staged);
-    Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize, slots);
+    Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize, slots, s->cus);
     t.staged = s->user_loader == 0;
     return t;
 }

@@ -28,6 +28,7 @@ constexpr int kGraphLaunches = 16;   // launches per captured graph (even: buffe
 // tile -> member list and the persistent grid.
 struct BatchConfig {
     int nt = 128, hc_user = 0, blocks_user = 0;
+    int hc = 0;                      // chunk height in use (hc_user, or the default for the ensemble)
     int total_tiles = 0, nblocks = 0;
     void* d_members = nullptr;       // BatchMember<T>[count]
     int* d_tile_member = nullptr;    // int[total_tiles]
@@ -108,7 +109,25 @@ lbch_status configure(lbch_batch* b, int depth, int nt, int hc_user, int blocks_
     const int n = (int)b->m.size();
     BatchConfig& cf = b->cfg[depth - 1];
     const int hc_default = depth == 2 ? 64 : 32;   // a two-step sweep restarts 14 rows per chunk
-    const int hc = hc_user > 0 ? hc_user : hc_default;
+    int hc = hc_user > 0 ? hc_user : hc_default;
+    if (hc_user <= 0 && b->num_cus > 0) {
+        // small ensembles: fewer tiles than CUs at the default chunk, so a launch
+        // lasts one chunk's sweep; take the shortest chunk (>= 4 rows) that keeps
+        // at most 2.5 tiles per CU (the rule of the single-grid tiling)
+        const int W = nt - 8 * depth;
+        auto tiles_at = [&](int h) {
+            long long t = 0;
+            for (const Member& mm : b->m)
+                t += (long long)((mm.g.nx + W - 1) / W) * ((mm.g.ny + h - 1) / h);
+            return t;
+        };
+        if (tiles_at(hc_default) < b->num_cus)
+            for (int h = 4; h <= hc_default; ++h)
+                if (tiles_at(h) * 2 <= 5LL * b->num_cus) {
+                    hc = h;
+                    break;
+                }
+    }
     // order members by work, largest first, so the queue ends on small tiles
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
@@ -147,6 +166,7 @@ lbch_status configure(lbch_batch* b, int depth, int nt, int hc_user, int blocks_
     cf.nblocks = std::max(1, std::min(blocks, cf.total_tiles));
     cf.nt = nt;
     cf.hc_user = hc_user;
+    cf.hc = hc;
     cf.blocks_user = blocks_user;
     b->counter_dirty = true;
     return ok();
@@ -461,7 +481,7 @@ extern "C" lbch_status lbch_batch_get_tiling(const lbch_batch* b, int32_t* block
     if (!b) return fail(LBCH_E_INVALID, "batch handle is NULL");
     const BatchConfig& cf = b->cfg[b->depth - 1];
     if (block_threads) *block_threads = cf.nt;
-    if (rows_per_block) *rows_per_block = cf.hc_user > 0 ? cf.hc_user : (b->depth == 2 ? 64 : 32);
+    if (rows_per_block) *rows_per_block = cf.hc;
     if (persistent_blocks) *persistent_blocks = cf.nblocks;
     if (total_tiles) *total_tiles = cf.total_tiles;
     return ok();

@@ -94,7 +94,8 @@ lbch_status fail(lbch_status code, const char* fmt, ...) __attribute__((format(p
 template <typename T>
 void fill_coef(const lbch_params* p, StepCoef<T>& c);
 void fill_red(const lbch_params* p, RedCoef& r);
-Tiling make_tiling(int nx, int ny, int nt, int hc, int depth = 1, int esize = 4, int slots = 0);
+// slots: resident workgroups on the device; cus: its compute units (0 = unknown)
+Tiling make_tiling(int nx, int ny, int nt, int hc, int depth = 1, int esize = 4, int slots = 0, int cus = 0);
 
 constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
 constexpr int kRedThreads = 256;
