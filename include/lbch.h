@@ -242,7 +242,9 @@ lbch_status lbch_load_state(lbch_sim* sim, const void* src, int32_t src_is_devic
  * reads the populations once, keeps the first step's post-collision rows on
  * chip and writes the state two steps later; lbch_step with an odd count
  * finishes with one single-step launch).  Results are bitwise identical for
- * both depths.  Default 2.  Changing the depth restores the default tiling
+ * both depths.  Default 2, and 1 on grids of at most 512^2 nodes, where a
+ * launch is latency-bound and the single-step sweep's shorter start-up wins
+ * (measured).  Changing the depth restores the default tiling
  * of that depth.  depth not in {1, 2} -> LBCH_E_INVALID; D3Q15 runs depth 1
  * only (2 -> LBCH_E_UNSUPPORTED). */
 lbch_status lbch_set_time_blocking(lbch_sim* sim, int32_t depth);

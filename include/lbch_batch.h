@@ -56,7 +56,8 @@ lbch_status lbch_batch_moments(lbch_batch* batch, int32_t member, double* phi_ou
 lbch_status lbch_batch_free_energy(lbch_batch* batch, int32_t member, double* energy, double* terms4);
 lbch_status lbch_batch_phi_device(lbch_batch* batch, int32_t member, void* dst_dev, int32_t dtype);
 
-/* Time steps per launch, 1 or 2 (default 2; an odd remainder of
+/* Time steps per launch, 1 or 2 (default 2, and 1 for ensembles of at most
+ * 512^2 nodes in all, as for one simulation; an odd remainder of
  * lbch_batch_step runs one single-step launch).  Bitwise identical results.
  * depth not in {1, 2} -> LBCH_E_INVALID. */
 lbch_status lbch_batch_set_time_blocking(lbch_batch* batch, int32_t depth);

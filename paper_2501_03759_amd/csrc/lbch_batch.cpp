@@ -251,6 +251,13 @@ extern "C" lbch_status lbch_batch_create(const lbch_params* members, int32_t cou
         max_nodes = std::max(max_nodes, (long long)mm.p.nx * mm.p.ny);
     }
     b->total_elems = off;
+    {
+        // as for one simulation: ensembles of at most 512^2 nodes in all run one
+        // step per launch by default (latency-bound launches)
+        long long nodes = 0;
+        for (const Member& mm : b->m) nodes += (long long)mm.p.nx * mm.p.ny;
+        b->depth = nodes <= 512LL * 512 ? 1 : 2;
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, dev);

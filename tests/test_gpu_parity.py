@@ -130,8 +130,10 @@ def test_zero_steps_is_a_no_op():
 
 def test_time_blocking_errors():
     L = lb()
+    with L.Sim(common.make_params(1024, 257, 0, width=4.0)) as big:
+        assert big.time_blocking() == 2                 # more than 512^2 nodes
     with L.Sim(common.make_params(96, 64, 0, width=4.0)) as s:
-        assert s.time_blocking() == 2
+        assert s.time_blocking() == 1                   # small grids: one step per launch
         with pytest.raises(L.LbchError):
             s.set_time_blocking(3)
         s.set_time_blocking(1)
