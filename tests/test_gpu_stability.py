@@ -26,3 +26,25 @@ def test_collision_stability_map():
         assert srt < mrt, (m, srt, mrt)                     # strictly larger for MRT
     assert all(st[("trt", m, e)] for m in mobilities for e in eps_regs if st[("mrt", m, e)])
     assert not all(st.values())                             # the map has an edge
+
+
+def test_alpha_and_width_maps():
+    # Measured (same setting): at M = 0.1 the largest stable alpha grows with the Willmore
+    # regularisation (about 1.5 without it, 2 at the eq 39 value 0.03, 3 at 0.3), alike for
+    # the three models; across interface widths only SRT fails, at M = 5 with D <= 1.5.
+    from paper_2501_03759_amd import stability
+    am = stability.alpha_map(alphas=(0.0, 1.0, 2.0, 3.0, 5.0), eps_regs=(0.0, 0.03, 0.3))
+    print("case alpha map\n" + stability.table(am, "eps_reg", "alpha"), flush=True)
+    for model in ("mrt", "srt", "trt"):
+        largest = {}
+        for e in (0.0, 0.03, 0.3):
+            ok = [r["alpha"] for r in am if r["model"] == model and r["eps_reg"] == e and r["stable"]]
+            largest[e] = max(ok)
+            assert 1.0 in ok                                   # alpha = 1 at any regularisation
+        assert largest[0.0] <= largest[0.03] <= largest[0.3] and largest[0.3] > largest[0.0], (model, largest)
+        assert not all(r["stable"] for r in am if r["model"] == model)
+    wm = stability.width_map(widths=(1.0, 1.5, 5.0), mobilities=(0.1, 5.0))
+    print("case width map\n" + stability.table(wm, "mobility", "width"), flush=True)
+    st = {(r["model"], r["mobility"], r["width"]): r["stable"] for r in wm}
+    assert all(st[("mrt", m, w)] and st[("trt", m, w)] for m in (0.1, 5.0) for w in (1.0, 1.5, 5.0))
+    assert not st[("srt", 5.0, 1.0)] and st[("srt", 0.1, 1.0)] and st[("srt", 5.0, 5.0)]
