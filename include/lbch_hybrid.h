@@ -68,8 +68,11 @@ typedef struct lbch_hybrid_opts {
     int32_t inner_steps;      /* > 0: the correction phase runs in inner cycles of inner_steps plain
                                  steps followed by a projective step of the populations over
                                  inner_jump steps (f += inner_jump / d (f_n - f_(n-d)), d = 2 when
-                                 the plain steps ran two per launch, else 1), repeated while at least
-                                 inner_steps plain steps remain after it; the rest are plain steps */
+                                 inner_steps is even, else 1), repeated while at least inner_steps
+                                 plain steps remain after it; the rest are plain steps.  With inner
+                                 steps the simulation runs two steps per launch during the call
+                                 (its tiling is restored on return): only a two-step difference is
+                                 stable (the flux mode of a one-step difference grows). */
     int32_t inner_jump;       /* >= 0 */
 } lbch_hybrid_opts;
 

@@ -91,6 +91,15 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
     const int side = o->window_interior + 2 * o->window_margin;
     if (o->windows > 0 && (side > nx || side > ny)) return fail(LBCH_E_INVALID, "window larger than the grid");
     hipStream_t s = sim->stream;
+    // The projective difference of the correction phase spans the last launch, which must
+    // advance two steps (a one-step difference amplifies the flux mode, eigenvalue -0.25 of
+    // the linearised step): run at two steps per launch, and give the caller's tiling back.
+    struct TilingGuard {
+        lbch_sim* sim;
+        lbch::Tiling t;
+        ~TilingGuard() { sim->t = t; }
+    } tiling_guard{sim, sim->t};
+    if (o->inner_steps > 0 && o->inner_jump > 0 && sim->t.depth != 2) ST_TRY(lbch_set_time_blocking(sim, 2));
     lbch_hybrid_stats st{};
     Buffers B;
     void *snap = nullptr, *phi = nullptr, *phin = nullptr, *phi1 = nullptr, *dsum = nullptr, *part = nullptr,

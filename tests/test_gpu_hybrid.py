@@ -109,10 +109,12 @@ def test_extrapolated_jumps_track_plain_run(inner):
                       tol_energy=0.0, extrapolate=1, inner_steps=inner[0], inner_jump=inner[1])
     energies = [a.free_energy()[0]]
     accepted = 0
+    shape0 = (a.time_blocking(), a.tiling())        # 256^2 runs one step per launch by default
     for _ in range(10):
         st = L.hybrid_advance(a, None, o, 90)
         accepted += st.accepted
         assert st.cycles == 1 and st.max_window_err < 1e-2
+        assert (a.time_blocking(), a.tiling()) == shape0  # projective corrections ran at two steps
         energies.append(a.free_energy()[0])
     b.step(900)
     assert a.nstep == b.nstep == 4900
