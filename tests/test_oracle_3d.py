@@ -157,6 +157,66 @@ def test_collision_conserves_phi_and_equal_rates_is_bgk():
     assert np.abs(post - (f - 0.7 * (f - feq) + (1 - 0.35) * F)).max() < 1e-14
 
 
+EVEN_ROWS = (1, 2, 9, 10, 11, 12, 13)     # even in c: e, eps and the five second-order rows
+ODD_ROWS = (4, 6, 8, 14)                   # odd, not fluxes: |c|^2 c_a and c_x c_y c_z
+
+
+def _class_rates(s_e, s_q):
+    s = [1.0] * 15
+    for r in EVEN_ROWS:
+        s[r] = s_e
+    for r in ODD_ROWS:
+        s[r] = s_q
+    return tuple(s)
+
+
+def test_basis_rows_split_by_parity():
+    # the even rows span the vectors symmetric under c -> -c, the odd rows the antisymmetric
+    M = lbm3.M_MATRIX
+    opp = [int(np.flatnonzero((lbm3.E == -lbm3.E[:, [i]]).all(0))[0]) for i in range(15)]
+    for r in (0,) + EVEN_ROWS:
+        assert np.array_equal(M[r], M[r][opp])
+    for r in lbm3.J_ROWS + ODD_ROWS:
+        assert np.array_equal(M[r], -M[r][opp])
+
+
+def test_collision_trt_is_the_textbook_two_rate_update():
+    # even rows at s_+, odd rows at s_j: the symmetric / antisymmetric update with each part
+    # of the source scaled by its own (1 - s / 2)
+    p0 = _p(mobility=0.05)
+    s_j = lbm3.relaxation_rates(p0)[3]
+    s_p = 1.37
+    p = _p(mobility=0.05, s_free=_class_rates(s_p, s_j))
+    f, feq, F = _rand_state()
+    opp = [int(np.flatnonzero((lbm3.E == -lbm3.E[:, [i]]).all(0))[0]) for i in range(15)]
+    sym = lambda a: 0.5 * (a + a[opp])
+    asym = lambda a: 0.5 * (a - a[opp])
+    ref = (f - s_p * (sym(f) - sym(feq)) - s_j * (asym(f) - asym(feq))
+           + (1 - s_p / 2) * sym(F) + (1 - s_j / 2) * asym(F))
+    assert np.abs(lbm3.collide(f, feq, F, p) - ref).max() < 1e-14
+
+
+def test_collision_three_class_rates_closed_form():
+    # even rows at s_e, fluxes at s_j, other odd rows at s_q: with f_eq even and the source
+    # odd, f* = f_eq + (1 - s_e)(f+ - f_eq) + (1 - s_q) f- + (1 - s_q / 2) F
+    #           + (s_q - s_j) / 10 e_i.(j + F_m / 2)
+    p = _p(mobility=0.2, s_free=_class_rates(1.3, 0.8))
+    s_j = lbm3.relaxation_rates(p)[3]
+    f, feq, F = _rand_state()
+    opp = [int(np.flatnonzero((lbm3.E == -lbm3.E[:, [i]]).all(0))[0]) for i in range(15)]
+    assert np.abs(feq - feq[opp]).max() == 0 and np.abs(F + F[opp]).max() < 1e-18
+    c = lbm3.E.astype(float)
+    j, Fm = c @ f, c @ F
+    closed = (feq + (1 - 1.3) * (0.5 * (f + f[opp]) - feq) + (1 - 0.8) * 0.5 * (f - f[opp])
+              + (1 - 0.8 / 2) * F + (0.8 - s_j) / 10.0 * (c.T @ (j + 0.5 * Fm)))
+    assert np.abs(lbm3.collide(f, feq, F, p) - closed).max() < 1e-14
+    # and a change of any one odd non-flux rate alone changes the result
+    for r in ODD_ROWS:
+        s = list(_class_rates(1.3, 0.8))
+        s[r] = 0.9
+        assert np.abs(lbm3.collide(f, feq, F, _p(mobility=0.2, s_free=tuple(s))) - closed).max() > 1e-6
+
+
 @pytest.fixture(scope="module")
 def droplet_run():
     n = 14
