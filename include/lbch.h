@@ -88,9 +88,15 @@ enum {
  * 15-moment basis obtained by Gram-Schmidt orthogonalisation of 1, |c|^2,
  * |c|^4, c_x, |c|^2 c_x, c_y, |c|^2 c_y, c_z, |c|^2 c_z, 3c_x^2 - |c|^2,
  * c_y^2 - c_z^2, c_x c_y, c_y c_z, c_x c_z, c_x c_y c_z, whose flux rows relax
- * at s_j from the mobility.  Only the case where every other rate is 1 is
- * built (s[1], s[2], s[4], s[6], s[7], s[8] must be 1, else
- * LBCH_E_UNSUPPORTED), and aniso_m must be 4 with aniso_theta0 = 0.  One
+ * at s_j from the mobility.  The other rates come one per parity class under
+ * c -> -c from the D2Q9 slots of the same class: the eight even rows (|c|^2,
+ * |c|^4 and the five second-order rows) relax at s_e = s[1], which must equal
+ * s[2], s[7] and s[8]; the four odd non-flux rows (|c|^2 c_a, c_x c_y c_z) at
+ * s_q = s[4], which must equal s[6] (else LBCH_E_UNSUPPORTED).  The presets
+ * of lbch_params_set_collision satisfy this.  s_e = s_q = 1 (the default)
+ * runs a collision that reads only phi and the flux of each node; other
+ * rates re-read the pulled populations in the collision.  aniso_m must be 4
+ * with aniso_theta0 = 0.  One
  * launch per step (time-blocking depth 1); ensembles and the hybrid schedule
  * return LBCH_E_UNSUPPORTED for D3Q15.
  */
@@ -145,8 +151,9 @@ lbch_status lbch_relaxation_rates(const lbch_params* p, double s_out[9]);
  *                       Lambda = (1/s_+ - 1/2)(1/s_j - 1/2).
  * s_j comes from the mobility, dx and dt already in p (set them first).
  * magic is read for TRT only.  Unknown model, magic <= 0 or non-finite, or a
- * resulting rate outside (0, 2) -> LBCH_E_INVALID (p unchanged).  D3Q15
- * simulations accept MRT only (lbch_params_validate). */
+ * resulting rate outside (0, 2) -> LBCH_E_INVALID (p unchanged).  On D3Q15
+ * the same three presets apply class by class (see the D3Q15 paragraph of
+ * lbch_params). */
 enum { LBCH_COLLISION_MRT = 0, LBCH_COLLISION_SRT = 1, LBCH_COLLISION_TRT = 2 };
 lbch_status lbch_params_set_collision(lbch_params* p, int32_t model, double magic);
 

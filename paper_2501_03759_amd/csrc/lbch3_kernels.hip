@@ -1,10 +1,13 @@
 // HIP kernels of the scheme on the three-dimensional D3Q15 lattice (eq 21) for
 // gfx950: the same step as the D2Q9 kernels (eqs 17-19, 22, 26, 13, 16), with
-// the cubic anisotropy of eq 6 (d = 3).  Every free relaxation rate is 1, so
-// the collision needs only phi and the flux of each node:
-//   f*_i = f_eq,i - (dt c / 2) w_i e_i.g + (1 - s_j)/10 e_i.(j - (dt c / 6) g)
-// (g = grad mu_beta; 10 = |flux row|^2 of D3Q15), whatever the other moment
-// rows are.
+// the cubic anisotropy of eq 6 (d = 3).  The moment rows split by parity under
+// c -> -c: f_eq is even and the source odd, so with one rate s_e for the even
+// rows and one rate s_q for the odd rows other than the fluxes the collision
+// of eq 17 is, whatever the rows within each class are,
+//   f*_i = f_eq,i + (1 - s_e)(f+_i - f_eq,i) + (1 - s_q) f-_i
+//          - (1 - s_q / 2) dt c w_i e_i.g + (s_q - s_j)/10 e_i.(j - (dt c / 6) g)
+// (f+-: halves of f_i +- f_opp(i); g = grad mu_beta; 10 = |flux row|^2).  With
+// s_e = s_q = 1 (the default) only phi and the flux of each node are needed.
 //
 // Layout: population plane i holds nz slabs of ny rows of `pitch` elements;
 // element (i, z, y, x) is at i * plane + z * slab + y * pitch + x.  The buffer
@@ -97,7 +100,7 @@ struct Stencil3 {
 // padded planes; every lane computes every stage and only the tile interior
 // (TX - 6) x (TY - 6) is stored.
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool GEN>
 __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin, T* __restrict__ fout,
                                                        const Grid3 g, const Tiling3 tl, const StepCoef3<T> c) {
     constexpr int RW = TX + 2, RH = TY + 2, U = 4;
@@ -135,6 +138,7 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
     T red[U][4];      // phi, j_x, j_y, j_z of the pulled node (A -> D)
     T mua[U], tloc[U];
     T buf[2][15];     // pulled populations of the next plane in flight
+    T fr[GEN ? 15 : 1];  // s_e, s_q != 1: the populations of plane a-3, pulled again
 
     auto issue = [&](int za, T (&b)[15]) {
         const int zr = wrapi(za, g.nz);
@@ -173,6 +177,10 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                     s_phi[sN][ly][lx] = phi;
                 }
                 if (j + 1 < niter) issue(z0 - 3 + j + 1, buf[(j + 1) & 1]);
+                // the addresses stage A read three iterations ago
+                if constexpr (GEN) {
+                    if (j >= 6) issue(z0 - 6 + j, fr);
+                }
                 lds_barrier3();
                 // ---- B: plane a-1 ----
                 if (j >= 2) {
@@ -231,13 +239,29 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                     T o[15];
                     o[0] = r[0] + (c.w0 - T(1)) * mu_a;
                     const T ef = c.wf * mu_a, ed = c.wd * mu_a;
+                    if constexpr (!GEN) {
 #pragma unroll
-                    for (int i = 1; i < 15; ++i) {
-                        const T w_i = i < 7 ? c.wf : c.wd;
-                        const T eq = i < 7 ? ef : ed;
-                        const T ej = T(kEX[i]) * ax + T(kEY[i]) * ay + T(kEZ[i]) * az;
-                        const T eg = T(kEX[i]) * bx + T(kEY[i]) * by + T(kEZ[i]) * bz;
-                        o[i] = eq - w_i * eg + ej;
+                        for (int i = 1; i < 15; ++i) {
+                            const T w_i = i < 7 ? c.wf : c.wd;
+                            const T eq = i < 7 ? ef : ed;
+                            const T ej = T(kEX[i]) * ax + T(kEY[i]) * ay + T(kEZ[i]) * az;
+                            const T eg = T(kEX[i]) * bx + T(kEY[i]) * by + T(kEZ[i]) * bz;
+                            o[i] = eq - w_i * eg + ej;
+                        }
+                    } else {
+                        o[0] += c.se1 * (fr[0] - o[0]);
+                        // direction i + 1 is opposite to i for odd i
+#pragma unroll
+                        for (int i = 1; i < 15; i += 2) {
+                            const T w_i = i < 7 ? c.wf : c.wd;
+                            const T eq = i < 7 ? ef : ed;
+                            const T ej = T(kEX[i]) * ax + T(kEY[i]) * ay + T(kEZ[i]) * az;
+                            const T eg = T(kEX[i]) * bx + T(kEY[i]) * by + T(kEZ[i]) * bz;
+                            const T ev = eq + c.se1 * (T(0.5) * (fr[i] + fr[i + 1]) - eq);
+                            const T od = c.sq1 * (T(0.5) * (fr[i] - fr[i + 1])) - w_i * eg + ej;
+                            o[i] = ev + od;
+                            o[i + 1] = ev - od;
+                        }
                     }
                     if (store_lane) {
                         const int rd = z0 - 6 + j;
@@ -432,14 +456,19 @@ int blocks3(long long n) {
 }  // namespace
 
 namespace {
-template <typename T, int TX, int TY>
-int occ3() {
+template <typename T, int TX, int TY, bool GEN>
+int occ3_one() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step3_fused<T, TX, TY>, TX * TY, 0) != hipSuccess || n < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step3_fused<T, TX, TY, GEN>, TX * TY, 0) != hipSuccess ||
+        n < 1) {
         (void)hipGetLastError();
         n = 1;
     }
     return n;
+}
+template <typename T, int TX, int TY>
+int occ3(bool gen) {
+    return gen ? occ3_one<T, TX, TY, true>() : occ3_one<T, TX, TY, false>();
 }
 }  // namespace
 
@@ -447,9 +476,9 @@ bool tile3_supported(int precision, int tx, int ty) {
     return (tx == 32 && ty == 16) || (precision == 1 && tx == 32 && ty == 32);
 }
 
-int step3_blocks_per_cu(int precision, int tx, int ty) {
-    if (precision == 0) return occ3<double, 32, 16>();
-    return ty == 32 ? occ3<float, 32, 32>() : occ3<float, 32, 16>();
+int step3_blocks_per_cu(int precision, int tx, int ty, bool gen) {
+    if (precision == 0) return occ3<double, 32, 16>(gen);
+    return ty == 32 ? occ3<float, 32, 32>(gen) : occ3<float, 32, 16>(gen);
 }
 
 // hz = 0: the sweep length that minimises rounds * (hz + 6), where a round is
@@ -487,14 +516,24 @@ hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3&
                         const void* coef, hipStream_t s) {
     if (!tile3_supported(precision, t.tx, t.ty)) return hipErrorInvalidValue;
     if (precision == 0) {
-        step3_fused<double, 32, 16><<<t.nblocks, 512, 0, s>>>((const double*)fin, (double*)fout, g, t,
-                                                              *(const StepCoef3<double>*)coef);
-    } else if (t.ty == 32) {
-        step3_fused<float, 32, 32><<<t.nblocks, 1024, 0, s>>>((const float*)fin, (float*)fout, g, t,
-                                                              *(const StepCoef3<float>*)coef);
+        const auto& c = *(const StepCoef3<double>*)coef;
+        if (c.gen)
+            step3_fused<double, 32, 16, true><<<t.nblocks, 512, 0, s>>>((const double*)fin, (double*)fout, g, t, c);
+        else
+            step3_fused<double, 32, 16, false><<<t.nblocks, 512, 0, s>>>((const double*)fin, (double*)fout, g, t, c);
     } else {
-        step3_fused<float, 32, 16><<<t.nblocks, 512, 0, s>>>((const float*)fin, (float*)fout, g, t,
-                                                             *(const StepCoef3<float>*)coef);
+        const auto& c = *(const StepCoef3<float>*)coef;
+        if (t.ty == 32) {
+            if (c.gen)
+                step3_fused<float, 32, 32, true><<<t.nblocks, 1024, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
+            else
+                step3_fused<float, 32, 32, false><<<t.nblocks, 1024, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
+        } else {
+            if (c.gen)
+                step3_fused<float, 32, 16, true><<<t.nblocks, 512, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
+            else
+                step3_fused<float, 32, 16, false><<<t.nblocks, 512, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
+        }
     }
     return hipGetLastError();
 }

@@ -130,10 +130,14 @@ extern "C" lbch_status lbch_params_validate(const lbch_params* p) {
         return fail(LBCH_E_INVALID, "unknown q_form %d", p->q_form);
     if (!(p->grad_floor >= 0) || !isfin(p->grad_floor)) return fail(LBCH_E_INVALID, "grad_floor must be >= 0");
     if (d3) {
-        // the D3Q15 kernel implements the collision with every free rate 1
-        for (int k : {1, 2, 4, 6, 7, 8})
-            if (p->s[k] != 1.0)
-                return fail(LBCH_E_UNSUPPORTED, "D3Q15 needs every free relaxation rate = 1 (s[%d] = %g)", k, p->s[k]);
+        // D3Q15 takes one rate per parity class: the even D2Q9 slots (e, eps, p_xx, p_xy)
+        // give s_e, the odd non-flux slots (q_x, q_y) give s_q
+        for (int k : {2, 7, 8})
+            if (p->s[k] != p->s[1])
+                return fail(LBCH_E_UNSUPPORTED, "D3Q15 needs s[1] = s[2] = s[7] = s[8] (one even-row rate; s[%d] = %g)",
+                            k, p->s[k]);
+        if (p->s[6] != p->s[4])
+            return fail(LBCH_E_UNSUPPORTED, "D3Q15 needs s[4] = s[6] (one rate for the odd non-flux rows)");
         if (p->aniso_m != 4 || p->aniso_theta0 != 0.0)
             return fail(LBCH_E_UNSUPPORTED, "D3Q15 has the cubic anisotropy of eq 6 only (aniso_m 4, theta0 0)");
     }
@@ -342,14 +346,19 @@ void fill_coef3(const lbch_params* p, StepCoef3<T>& c) {
     c.alpha = (T)p->alpha;
     c.alpha16 = (T)(16.0 * p->alpha);
     c.floor2 = (T)(p->grad_floor * p->grad_floor);
-    c.u = (T)((1.0 - s_j_of(p)) / 10.0);
+    // D3Q15 rate classes: s_e from the even D2Q9 slots (s[1]), s_q from the odd non-flux ones (s[4])
+    const double se = p->s[1], sq = p->s[4];
+    c.u = (T)((sq - s_j_of(p)) / 10.0);
     c.v = (T)(dt * cc / 6.0);
-    c.hd = (T)(dt * cc / 2.0);
+    c.hd = (T)((1.0 - 0.5 * sq) * dt * cc);
     c.w0 = (T)(2.0 / 9.0);
     c.wf = (T)(1.0 / 9.0);
     c.wd = (T)(1.0 / 72.0);
+    c.se1 = (T)(1.0 - se);
+    c.sq1 = (T)(1.0 - sq);
     c.reg = p->regularization;
     c.qform = p->q_form;
+    c.gen = se != 1.0 || sq != 1.0;
 }
 
 // D3Q15 tiling: block_threads 512 = 32 x 16 lanes, 1024 = 32 x 32 (FP32
@@ -357,7 +366,8 @@ void fill_coef3(const lbch_params* p, StepCoef3<T>& c) {
 static Tiling3 sim_tiling3(const lbch_sim* s, int block_threads, int hz) {
     if (block_threads == 0) block_threads = s->precision == LBCH_FP32 ? 1024 : 512;
     const int tx = 32, ty = block_threads / 32;
-    return make_tiling3(s->g3.nx, s->g3.ny, s->g3.nz, hz, s->cus * step3_blocks_per_cu(s->precision, tx, ty), tx, ty);
+    return make_tiling3(s->g3.nx, s->g3.ny, s->g3.nz, hz,
+                        s->cus * step3_blocks_per_cu(s->precision, tx, ty, s->c3d.gen != 0), tx, ty);
 }
 
 template void fill_coef<double>(const lbch_params*, StepCoef<double>&);

@@ -135,18 +135,20 @@ struct StepCoef3 {
     T gf, gd;             // gradient eq 26a: face (1/3)/dx, body diagonal (1/24)/dx
     T lf, ld, lc;         // Laplacian eq 26b: (2/3)/dx^2, (1/12)/dx^2, (14/3)/dx^2
     T kappa, beta4, eps, alpha, alpha16, floor2;
-    T u;                  // (1 - s_j) / 10
+    T u;                  // (s_q - s_j) / 10
     T v;                  // dt c / 6
-    T hd;                 // dt c / 2
+    T hd;                 // (1 - s_q / 2) dt c
     T w0, wf, wd;         // eq 21b weights
+    T se1, sq1;           // 1 - s_e, 1 - s_q (even rows, odd non-flux rows)
     int reg, qform;
+    int gen;              // s_e != 1 or s_q != 1: the collision reads every population
 };
 
 template <typename T>
 void fill_coef3(const lbch_params* p, StepCoef3<T>& c);
 Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty);
 bool tile3_supported(int precision, int tx, int ty);
-int step3_blocks_per_cu(int precision, int tx, int ty);
+int step3_blocks_per_cu(int precision, int tx, int ty, bool gen);
 hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3& g, const Tiling3& t,
                         const void* coef, hipStream_t s);
 hipError_t launch_init3(int precision, const void* phi0, int phi_dtype, void* fout, const Grid3& g, const void* coef,

@@ -13,6 +13,10 @@ D = 5) and alpha = 0.3:
 * interface width D (kappa = 3 sigma D / 8) x mobility.
 
     python -m paper_2501_03759_amd.stability            # prints the three Markdown tables
+
+The D3Q15 map (``--lattice d3q15``): mobility x eps_reg for the same three rate choices,
+applied class by class (even rows, fluxes, other odd rows), each point one simulation of a
+ball (R = 10, D = 5) on a 40^3 periodic box for 20 000 steps.
 """
 from __future__ import annotations
 
@@ -63,6 +67,35 @@ def scan(points, n=64, steps=30000, magic=0.25, precision=lbch.FP32, bound=1.5):
     return full
 
 
+def scan3(points, n=40, radius=10.0, steps=20000, magic=0.25, precision=lbch.FP32, bound=1.5):
+    """As `scan` on D3Q15: each point is one simulation of a ball on an n^3 periodic box."""
+    full = [dict(BASE, **p) for p in points]
+    for q in full:
+        p = lbch.default_params(lattice=lbch.D3Q15, nx=n, ny=n, nz=n, precision=precision,
+                                sigma_width=(inputs.SIGMA_PAPER, q["width"]), mobility=q["mobility"],
+                                alpha=q["alpha"], eps_reg=q["eps_reg"],
+                                regularization=lbch.REG_WILLMORE if q["eps_reg"] > 0 else lbch.REG_NONE)
+        lbch.set_collision(p, MODELS[q["model"]], magic)
+        with lbch.Sim(p) as s:
+            s.init(inputs.sphere_width(n, radius, q["width"]))
+            s.step(steps)
+            try:
+                _, _, lo, hi = s.moments(want_phi=False)
+                amax = max(abs(lo), abs(hi))
+                q["stable"] = math.isfinite(amax) and amax <= bound
+            except lbch.LbchError:
+                amax, q["stable"] = float("nan"), False
+        q["max_abs_phi"] = amax
+        q["s_j"] = flux_rate(q["mobility"])
+    return full
+
+
+def stability_map3(models=("mrt", "srt", "trt"), mobilities=MOBILITIES, eps_regs=EPS_REGS, alpha=0.3, **kw):
+    """Mobility x eps_reg map on D3Q15 (alpha fixed)."""
+    return scan3([{"model": m, "mobility": mob, "eps_reg": e, "alpha": alpha}
+                  for m in models for mob in mobilities for e in eps_regs], **kw)
+
+
 def stability_map(models=("mrt", "srt", "trt"), mobilities=MOBILITIES, eps_regs=EPS_REGS, alpha=0.3, **kw):
     """Mobility x eps_reg map (alpha fixed)."""
     return scan([{"model": m, "mobility": mob, "eps_reg": e, "alpha": alpha}
@@ -101,9 +134,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--magic", type=float, default=0.25)
+    ap.add_argument("--lattice", choices=("d2q9", "d3q15"), default="d2q9")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
+    if args.lattice == "d3q15":
+        print("## D3Q15: mobility x eps_reg (alpha = 0.3, D = 5, ball R = 10 on 40^3)\n")
+        for m in MODELS:
+            print(table(stability_map3(models=(m,), steps=args.steps, magic=args.magic), "mobility", "eps_reg"),
+                  flush=True)
+        return
     kw = dict(steps=args.steps, magic=args.magic)
     print("## mobility x eps_reg (alpha = 0.3, D = 5)\n")
     print(table(stability_map(**kw), "mobility", "eps_reg"), flush=True)

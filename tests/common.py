@@ -60,11 +60,22 @@ def sampled_oracle_phi(phi0: np.ndarray, p, nsteps: int, points) -> np.ndarray:
     return np.array(out)
 
 
+D3Q15_EVEN_ROWS = (1, 2, 9, 10, 11, 12, 13)
+D3Q15_ODD_ROWS = (4, 6, 8, 14)
+
+
 def oracle_params3(p) -> lbm3.Params:
-    """The D3Q15 problem for the three-dimensional oracle (every free rate 1)."""
+    """The D3Q15 problem for the three-dimensional oracle.  The library takes one rate per
+    parity class from the D2Q9 slots: the even rows from s[1] (= s[2] = s[7] = s[8]), the
+    odd rows other than the fluxes from s[4] (= s[6])."""
+    s = [1.0] * 15
+    for r in D3Q15_EVEN_ROWS:
+        s[r] = p.s[1]
+    for r in D3Q15_ODD_ROWS:
+        s[r] = p.s[4]
     return lbm3.Params(nx=p.nx, ny=p.ny, nz=p.nz, kappa=p.kappa, beta=p.beta, mobility=p.mobility, alpha=p.alpha,
                        reg=REG_NAMES[p.regularization], eps_reg=p.eps_reg, q_form=QFORM_NAMES[p.q_form],
-                       grad_floor=p.grad_floor, dx=p.dx, dt=p.dt)
+                       grad_floor=p.grad_floor, dx=p.dx, dt=p.dt, s_free=tuple(s))
 
 
 def oracle_phi3(phi0, p, nsteps) -> np.ndarray:

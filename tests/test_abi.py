@@ -131,5 +131,13 @@ def test_validate_d3q15(field, value, status):
 def test_validate_d3q15_free_rates():
     p = lbch.default_params(lattice=lbch.D3Q15, nz=16, s=(0.0, 1.0, 1.0, 1.7, 1.0, 1.7, 1.0, 1.0, 1.0))
     assert lbch.validate(p) == lbch.OK                  # s0, s3, s5 ignored
+    # one rate per parity class: s[1] = s[2] = s[7] = s[8] (even rows), s[4] = s[6] (odd non-flux)
+    p = lbch.default_params(lattice=lbch.D3Q15, nz=16, s=(1.0, 1.2, 1.2, 1.0, 0.9, 1.0, 0.9, 1.2, 1.2))
+    assert lbch.validate(p) == lbch.OK
     p = lbch.default_params(lattice=lbch.D3Q15, nz=16, s=(1.0, 1.2, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0))
     assert lbch.validate(p) == lbch.E_UNSUPPORTED
+    p = lbch.default_params(lattice=lbch.D3Q15, nz=16, s=(1.0, 1.0, 1.0, 1.0, 0.9, 1.0, 1.0, 1.0, 1.0))
+    assert lbch.validate(p) == lbch.E_UNSUPPORTED
+    for model in (lbch.COLLISION_MRT, lbch.COLLISION_SRT, lbch.COLLISION_TRT):
+        p = lbch.set_collision(lbch.default_params(lattice=lbch.D3Q15, nz=16), model, 0.25)
+        assert lbch.validate(p) == lbch.OK

@@ -97,4 +97,6 @@ def test_library_preset_errors():
         assert ei.value.status == L.E_INVALID
         assert p.s[1] == 0.7                                     # unchanged on error
     q = L.set_collision(L.default_params(lattice=L.D3Q15, nz=8), L.COLLISION_SRT)
-    assert L.validate(q) == L.E_UNSUPPORTED                      # D3Q15 builds MRT only
+    assert L.validate(q) == L.OK                                 # one rate per parity class
+    q.s[7] = 0.9
+    assert L.validate(q) == L.E_UNSUPPORTED                      # even rows at two rates

@@ -62,6 +62,73 @@ def test_sphere_fp64(case):
         assert np.abs(got - want).max() <= FP64_TOL, hz
 
 
+def with_rates(p, model=None, magic=0.25, s=None):
+    L = lb()
+    if isinstance(model, str):
+        model = getattr(L, "COLLISION_" + model)
+    if model is not None:
+        L.set_collision(p, model, magic)
+    if s is not None:
+        for k, v in enumerate(s):
+            p.s[k] = v
+    return p
+
+
+# One rate per parity class: SRT (every rate s_j), TRT (even rows at s_+), and three distinct
+# rates (even rows 1.3, fluxes s_j, other odd rows 0.8).  Each is as well conditioned as the
+# cases above (a 1e-16 perturbation moves the oracle by < 2e-15).
+RATE_CASES = [
+    dict(model="SRT", alpha=0.3),
+    dict(model="TRT", alpha=0.3),                                         # magic 1/4
+    dict(s=(1, 1.3, 1.3, 1, 0.8, 1, 0.8, 1.3, 1.3), alpha=0.2, regularization=1),
+    dict(model="TRT", magic=3 / 16, alpha=0.25, dx=0.8, dt=0.5, mobility=0.05),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RATE_CASES)))
+def test_sphere_collision_rates_fp64(case):
+    kw = dict(RATE_CASES[case])
+    rates = {k: kw.pop(k) for k in ("model", "magic", "s") if k in kw}
+    nx, ny, nz = 30, 23, 14
+    p = with_rates(params3(nx, ny, nz, 0, **kw), **rates)
+    phi0 = inputs.sphere(nx, ny, nz, 6.0, 1.5, centre=(13, 11, 6))
+    want = common.oracle_phi3(phi0, p, 150)
+    for hz in (None, 5):
+        print(f"case sphere3 rates {case} hz={hz}", flush=True)
+        got = run3(p, phi0, 150, hz)
+        assert np.abs(got - want).max() <= FP64_TOL, hz
+
+
+def test_wavy_layer_trt_fp32_1000_steps():
+    # 6e-8 perturbation -> 2.4e-8 in the oracle after 1000 steps
+    L = lb()
+    nx, ny, nz = 28, 14, 24
+    p = with_rates(params3(nx, ny, nz, 1, alpha=0.3), L.COLLISION_TRT)
+    phi0 = inputs.wavy_slab(nx, ny, nz, 1.5, 6.0, 18.0)
+    want = common.oracle_phi3(phi0, p, 1000)
+    for threads in (512, 1024):
+        print(f"case wavy3 trt threads={threads}", flush=True)
+        got = run3(p, phi0, 1000, threads=threads)
+        assert np.abs(got - want).max() <= FP32_TOL, threads
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_z_sweep_length_is_bitwise_trt(precision):
+    L = lb()
+    nx, ny, nz = 57, 31, 19
+    p = with_rates(params3(nx, ny, nz, precision, alpha=0.3), s=(1, 1.3, 1.3, 1, 0.8, 1, 0.8, 1.3, 1.3))
+    phi0 = inputs.spinodal3(nx, ny, nz, seed=12, amp=0.2)
+    ref = run3(p, phi0, 40)
+    shapes = (512, 1024) if precision == 1 else (512,)
+    for threads in shapes:
+        for hz in (1, 4, 19):
+            print(f"case rates threads={threads} hz={hz} precision={precision}", flush=True)
+            assert np.array_equal(run3(p, phi0, 40, hz, threads), ref), (threads, hz)
+    # rates left at 1 by the presets reproduce the default MRT bit for bit
+    q = with_rates(params3(nx, ny, nz, precision, alpha=0.3), L.COLLISION_MRT)
+    assert np.array_equal(run3(q, phi0, 40), run3(params3(nx, ny, nz, precision, alpha=0.3), phi0, 40))
+
+
 def test_wavy_layer_fp32_1000_steps():
     # A relaxing wavy layer: a 6e-8 relative perturbation of its initial populations moves the
     # oracle's phi by 3e-8 after 1000 steps.  (A small ball at alpha = 0.3 is not a fair FP32
