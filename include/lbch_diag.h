@@ -32,6 +32,20 @@ lbch_status lbch_diag_copy(const void* src, void* dst, int64_t bytes, void* hip_
 lbch_status lbsg_diag_conv3(const float* x, const float* w, const float* bias, float* y, int32_t n, int32_t h,
                             int32_t wd, int32_t ci, int32_t co, int32_t relu);
 
+/* As lbsg_diag_conv3 on the channel concatenation [nearest 2x upsampling of
+ * u[N][H/2][W/2][Cu], sk[N][H][W][Cs]] (Ci = Cu + Cs), read by the kernel
+ * from its two sources (the decoder's first convolution).  Cu, Cs multiples
+ * of 32; w is [Co][Cu + Cs][3][3]. */
+lbch_status lbsg_diag_conv3_upcat(const float* u, const float* sk, const float* w, const float* bias, float* y,
+                                  int32_t n, int32_t h, int32_t wd, int32_t cu, int32_t cs, int32_t co, int32_t relu);
+
+/* The decoder's last convolution with the 1x1 head in its epilogue:
+ * out[p] = xin[p * cin] + scale (hb[0] + sum_c hw[c] y[p][c]), y the BF16
+ * ReLU activations of conv3(x, w) + bias (not stored); Co = 32 or 64. */
+lbch_status lbsg_diag_conv3_head(const float* x, const float* w, const float* bias, const float* hw, const float* hb,
+                                 const float* xin, int32_t cin, float scale, float* out, int32_t n, int32_t h,
+                                 int32_t wd, int32_t ci, int32_t co);
+
 /* dx[N][H][W][Ci] = data gradient of conv3 for dy[N][H][W][Co] (flipped,
  * transposed weights through the forward kernel). */
 lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, float* dx, int32_t n, int32_t h, int32_t wd,

@@ -8,6 +8,16 @@ namespace lbsg {
 
 hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd, int Ci,
                      int Co, bool relu, hipStream_t s);
+// conv3_fwd of the channel concatenation [nearest 2x upsampling of U (Cu
+// channels, H/2 x Wd/2), Sk (Cs channels, H x Wd)] without forming it.
+hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
+                           int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s);
+// ReLU conv3_fwd (Co = 32 or 64, one workgroup per 16 x 16 pixel tile) with
+// the 1x1 head in its epilogue: out[p] = xin[p * cin] + scale (hb[0] + sum_c
+// hw[c] y[p][c]) over the BF16 activations y, which go to Y unless it is NULL.
+hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd,
+                               int Ci, int Co, const float* hw, const float* hb, const float* xin, int cin, float* out,
+                               float scale, hipStream_t s);
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
                     hipStream_t s);
 hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s);

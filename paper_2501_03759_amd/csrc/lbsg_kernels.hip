@@ -3,6 +3,8 @@
 // (v_mfma_f32_16x16x32_bf16), NHWC layout with channels padded to 32.
 #include "lbsg_internal.h"
 
+#include <type_traits>
+
 namespace lbsg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -19,6 +21,22 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Scheduling pattern for NL LDS reads among MF matrix-core instructions: one
+// read, then two (or one, when reads outnumber half the MFMAs) MFMAs, repeated.
+template <int NL, int MF>
+__device__ __forceinline__ void interleave_ds_mfma() {
+    if constexpr (NL > 0 && MF > 0) {
+        constexpr int m = MF >= 2 * NL ? 2 : 1;
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+        __builtin_amdgcn_sched_group_barrier(0x008, m, 0);   // MFMA
+        interleave_ds_mfma<NL - 1, MF - m>();
+    } else if constexpr (NL > 0) {
+        __builtin_amdgcn_sched_group_barrier(0x100, NL, 0);
+    } else if constexpr (MF > 0) {
+        __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -33,11 +51,28 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const 
 // matrix-core work on the current one, so they overlap it.  Each wave owns 4
 // pixel rows x TC channels (4 x TC/16 MFMA tiles); the result fragment of a
 // lane is 4 consecutive output channels of one pixel (one 8-byte store).
+// UPCAT: the input is the channel concatenation of X (half resolution, Cu
+// channels, nearest-neighbour upsampled) and X2 (full resolution, Ci - Cu
+// channels), read from the two sources; both counts are multiples of 32, so
+// every chunk comes from one of them.
+// HEAD (Co = TC, one workgroup per pixel tile): the 1x1 output head is applied
+// in the epilogue, out[p] = xin[p][0] + scale (b + sum_c w_c y[p][c]) over the
+// BF16-rounded activations; Y (nullable) still receives them.
 // ---------------------------------------------------------------------------
-template <int TC, bool RELU>
-__global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ Wt,
-                                                   const float* __restrict__ bias, __bf16* __restrict__ Y, int H,
-                                                   int Wd, int Ci, int Co) {
+struct HeadArgs {
+    const float* w;      // [Co] head weights
+    const float* b;      // [1] head bias
+    const float* xin;    // [P][cin] FP32 input; channel 0 is the residual base
+    int cin;
+    float* out;          // [P]
+    float scale;
+};
+
+template <int TC, bool RELU, bool UPCAT, bool HEAD = false>
+__global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
+                                                   const __bf16* __restrict__ Wt, const float* __restrict__ bias,
+                                                   __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
+                                                   const HeadArgs hd = HeadArgs{}) {
     constexpr int NXQ = 18 * 18 * 4;              // 16-byte chunks of the pixel tile
     constexpr int NWQ = 9 * TC * 4;               // 16-byte chunks of the weights
     constexpr int RX = (NXQ + 255) / 256, RW = (NWQ + 255) / 256;
@@ -62,6 +97,7 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
     // per-thread source offsets (chunk-independent parts); indices past the
     // end are clamped to the last chunk (loaded, never stored)
     long long xoff[RX];
+    long long xoff2[UPCAT ? RX : 1];
     long long woff[RW];
 #pragma unroll
     for (int i = 0; i < RX; ++i) {
@@ -69,7 +105,12 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
         const int px = q >> 2, part = q & 3;
         const int py = px / 18, pxx = px - py * 18;
         const int y = wrap(ty0 - 1 + py, H), x = wrap(tx0 - 1 + pxx, Wd);
-        xoff[i] = (((long long)n * H + y) * Wd + x) * Ci + part * 8;
+        if constexpr (UPCAT) {
+            xoff[i] = (((long long)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + part * 8;
+            xoff2[i] = (((long long)n * H + y) * Wd + x) * (Ci - Cu) + part * 8;
+        } else {
+            xoff[i] = (((long long)n * H + y) * Wd + x) * Ci + part * 8;
+        }
     }
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
@@ -79,8 +120,19 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
         woff[i] = ((long long)(co0 + co) * 9 + tap) * Ci + part * 8;
     }
     bf16x8 rx[RX], rw[RW];
+    // pixel-tile chunk starting at input channel cc
+    auto load_x = [&](int cc) {
+        if constexpr (UPCAT) {
+            if (cc >= Cu) {
 #pragma unroll
-    for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X + xoff[i]);
+                for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X2 + xoff2[i] + (cc - Cu));
+                return;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X + xoff[i] + cc);
+    };
+    load_x(0);
 #pragma unroll
     for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + woff[i]);
 
@@ -98,43 +150,100 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
         }
         __syncthreads();
         if (cc + 32 < Ci) {                       // next chunk in flight during the MFMAs
-#pragma unroll
-            for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X + xoff[i] + cc + 32);
+            load_x(cc + 32);
 #pragma unroll
             for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + woff[i] + cc + 32);
         }
+        // Taps in kx-major order t = 3 kx + ky.  B rows wave * 4 + j (j = 0..5) at
+        // column l16 + kx live in bq[kx & 1][j] (tap (kx, ky) uses rows ky..ky+3);
+        // the A fragments of tap t in aq[t & 1].  The operands of tap t + 1 are
+        // read from LDS while the MFMAs of tap t run.
+        bf16x8 bq[2][6], aq[2][CB];
+        auto ld_b = [&](int kx, int j, bf16x8& v) {
+            v = *reinterpret_cast<const bf16x8*>(sx + ((wave * 4 + j) * 18 + l16 + kx) * kPadC + kb * 8);
+        };
+        auto ld_a = [&](int kx, int ky, bf16x8 (&a)[CB]) {
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
+            for (int c = 0; c < CB; ++c)
+                a[c] = *reinterpret_cast<const bf16x8*>(sw + ((ky * 3 + kx) * TC + c * 16 + l16) * kPadC + kb * 8);
+        };
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                bf16x8 bfr[4];
+        for (int j = 0; j < 4; ++j) ld_b(0, j, bq[0][j]);
+        ld_a(0, 0, aq[0]);
+        auto tap = [&](auto tc) {
+            constexpr int t = decltype(tc)::value, kx = t / 3, ky = t % 3;
+            constexpr int t1 = t + 1, kx1 = t1 / 3, ky1 = t1 % 3;
+            constexpr int nl = t1 < 9 ? (ky1 == 0 ? 4 : 1) + CB : 0;
+            if constexpr (t1 < 9) {
+                ld_a(kx1, ky1, aq[t1 & 1]);   // first: tap t1's first MFMAs need only these
+                if constexpr (ky1 == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    bfr[r] = *reinterpret_cast<const bf16x8*>(sx + ((wave * 4 + r + ky) * 18 + l16 + kx) * kPadC + kb * 8);
-#pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    const bf16x8 afr =
-                        *reinterpret_cast<const bf16x8*>(sw + ((ky * 3 + kx) * TC + c * 16 + l16) * kPadC + kb * 8);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(afr, bfr[r], acc[r][c]);
+                    for (int j = 0; j < 4; ++j) ld_b(kx1, j, bq[kx1 & 1][j]);
+                } else {
+                    ld_b(kx1, ky1 + 3, bq[kx1 & 1][ky1 + 3]);
                 }
             }
-        }
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq[t & 1][c], bq[kx & 1][ky + r], acc[r][c]);
+            interleave_ds_mfma<nl, 4 * CB>();
+        };
+        tap(std::integral_constant<int, 0>{});
+        tap(std::integral_constant<int, 1>{});
+        tap(std::integral_constant<int, 2>{});
+        tap(std::integral_constant<int, 3>{});
+        tap(std::integral_constant<int, 4>{});
+        tap(std::integral_constant<int, 5>{});
+        tap(std::integral_constant<int, 6>{});
+        tap(std::integral_constant<int, 7>{});
+        tap(std::integral_constant<int, 8>{});
+    }
+    // per-lane constants of the epilogue, loaded once: bias (and head weights) of the
+    // lane's 4 x CB channels, the head's residual base of its four pixels
+    float bv[CB][4], hv[HEAD ? CB : 1][4], xr[4], hb0 = 0.f;
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[c][j] = 0.f;
+    if (bias) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[c][j] = bias[co0 + c * 16 + kb * 4 + j];
+    }
+    if constexpr (HEAD) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) hv[c][j] = hd.w[co0 + c * 16 + kb * 4 + j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            xr[r] = hd.xin[(((size_t)n * H + ty0 + wave * 4 + r) * Wd + tx0 + l16) * hd.cin];
+        hb0 = hd.b[0];
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int y = ty0 + wave * 4 + r, x = tx0 + l16;
+        float part = 0.f;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int co = co0 + c * 16 + kb * 4;
             bf16x4 o;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float v = acc[r][c][j] + (bias ? bias[co + j] : 0.f);
+                float v = acc[r][c][j] + bv[c][j];
                 if (RELU) v = v > 0.f ? v : 0.f;
                 o[j] = (__bf16)v;
+                if constexpr (HEAD) part += hv[c][j] * (float)o[j];
             }
-            *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
+            if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
+        }
+        if constexpr (HEAD) {
+            // lanes l16, l16 + 16, l16 + 32, l16 + 48 hold the four channel groups of one pixel
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (kb == 0) hd.out[((size_t)n * H + y) * Wd + x] = xr[r] + hd.scale * (hb0 + part);
         }
     }
 }
@@ -647,21 +756,49 @@ int grid_for(long long n) {
 }
 }  // namespace
 
-hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd, int Ci,
-                     int Co, bool relu, hipStream_t s) {
-    if (H % 16 || Wd % 16 || Ci % 32 || Co % 32) return hipErrorInvalidValue;
+namespace {
+template <bool UPCAT>
+hipError_t conv3_fwd_any(const __bf16* X, const __bf16* X2, int Cu, const __bf16* Wt, const float* bias, __bf16* Y,
+                         int N, int H, int Wd, int Ci, int Co, bool relu, hipStream_t s) {
     const int tiles = N * (H / 16) * (Wd / 16);
     // 64 output channels per workgroup unless that leaves fewer than two
     // workgroups per CU of a 256-CU part (the deep, small levels)
     if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512) {
         dim3 grid(tiles, Co / 64);
-        if (relu) conv3_fwd_k<64, true><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
-        else conv3_fwd_k<64, false><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
+        if (relu) conv3_fwd_k<64, true, UPCAT><<<grid, 256, 0, s>>>(X, X2, Cu, Wt, bias, Y, H, Wd, Ci, Co);
+        else conv3_fwd_k<64, false, UPCAT><<<grid, 256, 0, s>>>(X, X2, Cu, Wt, bias, Y, H, Wd, Ci, Co);
     } else {
         dim3 grid(tiles, Co / 32);
-        if (relu) conv3_fwd_k<32, true><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
-        else conv3_fwd_k<32, false><<<grid, 256, 0, s>>>(X, Wt, bias, Y, H, Wd, Ci, Co);
+        if (relu) conv3_fwd_k<32, true, UPCAT><<<grid, 256, 0, s>>>(X, X2, Cu, Wt, bias, Y, H, Wd, Ci, Co);
+        else conv3_fwd_k<32, false, UPCAT><<<grid, 256, 0, s>>>(X, X2, Cu, Wt, bias, Y, H, Wd, Ci, Co);
     }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd, int Ci,
+                     int Co, bool relu, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || Co % 32) return hipErrorInvalidValue;
+    return conv3_fwd_any<false>(X, nullptr, 0, Wt, bias, Y, N, H, Wd, Ci, Co, relu, s);
+}
+
+hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
+                           int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || Co % 32) return hipErrorInvalidValue;
+    return conv3_fwd_any<true>(U, Sk, Cu, Wt, bias, Y, N, H, Wd, Cu + Cs, Co, relu, s);
+}
+
+hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd,
+                               int Ci, int Co, const float* hw, const float* hb, const float* xin, int cin, float* out,
+                               float scale, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || (Co != 32 && Co != 64) || !hw || !hb || !xin || !out || cin < 1)
+        return hipErrorInvalidValue;
+    const HeadArgs hd{hw, hb, xin, cin, out, scale};
+    const dim3 grid(N * (H / 16) * (Wd / 16), 1);
+    if (Co == 64)
+        conv3_fwd_k<64, true, false, true><<<grid, 256, 0, s>>>(X, nullptr, 0, Wt, bias, Y, H, Wd, Ci, Co, hd);
+    else
+        conv3_fwd_k<32, true, false, true><<<grid, 256, 0, s>>>(X, nullptr, 0, Wt, bias, Y, H, Wd, Ci, Co, hd);
     return hipGetLastError();
 }
 

@@ -154,14 +154,25 @@ lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, in
         Level& lv = n->lv[l];
         const Layer& La = n->layers[li++];
         const Layer& Lb = n->layers[li++];
-        HIP_TRY(lbsg::up2_concat(d, lv.e, lv.zc, B, h, w, C[l + 1], C[l], n->stream));
-        HIP_TRY(lbsg::conv3_fwd(lv.zc, La.wt, n->w + La.offB, lv.da, B, h, w, La.ci_pad, La.co, true, n->stream));
-        HIP_TRY(lbsg::conv3_fwd(lv.da, Lb.wt, n->w + Lb.offB, lv.d, B, h, w, Lb.ci_pad, Lb.co, true, n->stream));
-        d = lv.d;
+        // the upsampled-and-concatenated input is read from its two sources
+        HIP_TRY(lbsg::conv3_fwd_upcat(d, lv.e, La.wt, n->w + La.offB, lv.da, B, h, w, C[l + 1], C[l], La.co, true,
+                                      n->stream));
+        const Layer& Lh = n->layers[li];
+        if (l == 0 && (Lb.co == 32 || Lb.co == 64)) {
+            // the head in the last convolution's epilogue; the activations are kept only for training
+            HIP_TRY(lbsg::conv3_fwd_relu_head(lv.da, Lb.wt, n->w + Lb.offB, n->train ? lv.d : nullptr, B, h, w,
+                                              Lb.ci_pad, Lb.co, n->w + Lh.offW, n->w + Lh.offB, xres, cres, n->out,
+                                              n->scale, n->stream));
+            d = nullptr;
+        } else {
+            HIP_TRY(lbsg::conv3_fwd(lv.da, Lb.wt, n->w + Lb.offB, lv.d, B, h, w, Lb.ci_pad, Lb.co, true, n->stream));
+            d = lv.d;
+        }
     }
     const Layer& Lh = n->layers[li];
-    HIP_TRY(lbsg::head_fwd(d, n->w + Lh.offW, n->w + Lh.offB, xres, cres, n->out, (long long)B * H * W, C[0],
-                           n->scale, n->stream));
+    if (d)
+        HIP_TRY(lbsg::head_fwd(d, n->w + Lh.offW, n->w + Lh.offB, xres, cres, n->out, (long long)B * H * W, C[0],
+                               n->scale, n->stream));
     n->cur_b = B;
     n->cur_h = H;
     n->cur_w = W;
@@ -184,6 +195,9 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
         Level& lv = n->lv[l];
         lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w);
         if (st != LBCH_OK) return st;
+        // the weight gradient needs the concatenated input that the forward did not form
+        const __bf16* up = (l == Lv - 2) ? n->lv[Lv - 1].e : n->lv[l + 1].d;
+        HIP_TRY(lbsg::up2_concat(up, lv.e, lv.zc, B, h, w, C[l + 1], C[l], n->stream));
         st = conv_back(n, dec_layer(l, 0), lv.zc, lv.da, lv.gda, lv.gzc, B, h, w);
         if (st != LBCH_OK) return st;
         __bf16* du = (l + 1 < Lv - 1) ? n->lv[l + 1].gd : n->lv[Lv - 1].ge;
@@ -266,7 +280,7 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
         lv.a = A.get<__bf16>(P * C[l]);
         lv.e = A.get<__bf16>(P * C[l]);
         if (l < Lv - 1) {
-            lv.zc = A.get<__bf16>(P * (C[l + 1] + C[l]));
+            if (n->train) lv.zc = A.get<__bf16>(P * (C[l + 1] + C[l]));
             lv.da = A.get<__bf16>(P * C[l]);
             lv.d = A.get<__bf16>(P * C[l]);
         }
@@ -479,6 +493,50 @@ extern "C" lbch_status lbsg_diag_conv3(const float* x, const float* w, const flo
     HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
     HIP_TRY(lbsg::conv3_fwd(xb, wt, bias, yb, n, h, wd, ci, co, relu != 0, nullptr));
     HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_upcat(const float* u, const float* sk, const float* w, const float* bias,
+                                             float* y, int32_t n, int32_t h, int32_t wd, int32_t cu, int32_t cs,
+                                             int32_t co, int32_t relu) {
+    if (!u || !sk || !w || !y) return fail(LBCH_E_INVALID, "NULL argument");
+    if (cu < 32 || cu % 32) return fail(LBCH_E_INVALID, "cu = %d must be a positive multiple of 32", cu);
+    lbch_status st = diag_shape(n, h, wd, cs, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    const int ci = cu + cs;
+    __bf16* ub = S.get<__bf16>(P / 4 * cu);
+    __bf16* sb = S.get<__bf16>(P * cs);
+    __bf16* wt = S.get<__bf16>((size_t)co * 9 * ci);
+    __bf16* yb = S.get<__bf16>(P * co);
+    if (!ub || !sb || !wt || !yb) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(u, ub, P / 4, cu, cu, nullptr));
+    HIP_TRY(lbsg::pack_input(sk, sb, P, cs, cs, nullptr));
+    HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
+    HIP_TRY(lbsg::conv3_fwd_upcat(ub, sb, wt, bias, yb, n, h, wd, cu, cs, co, relu != 0, nullptr));
+    HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_head(const float* x, const float* w, const float* bias, const float* hw,
+                                            const float* hb, const float* xin, int32_t cin, float scale, float* out,
+                                            int32_t n, int32_t h, int32_t wd, int32_t ci, int32_t co) {
+    if (!x || !w || !hw || !hb || !xin || !out) return fail(LBCH_E_INVALID, "NULL argument");
+    if (co != 32 && co != 64) return fail(LBCH_E_INVALID, "co = %d: the fused head needs 32 or 64 channels", co);
+    if (cin < 1) return fail(LBCH_E_INVALID, "cin = %d must be >= 1", cin);
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    __bf16* xb = S.get<__bf16>(P * ci);
+    __bf16* wt = S.get<__bf16>((size_t)co * 9 * ci);
+    if (!xb || !wt) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
+    HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
+    HIP_TRY(lbsg::conv3_fwd_relu_head(xb, wt, bias, nullptr, n, h, wd, ci, co, hw, hb, xin, cin, out, scale, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }

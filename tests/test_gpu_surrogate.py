@@ -67,6 +67,8 @@ def run_both(levels, chans, hw, bias_shift, seed):
 
 
 OPS = [(2, 32, 48, 32, 64), (1, 16, 16, 96, 32), (3, 48, 32, 64, 128)]
+# at >= 512 (16 x 16 tile, 64-channel block) pairs the forward takes 64-channel workgroups
+OPS_FWD = OPS + [(2, 256, 256, 32, 64), (1, 256, 512, 64, 128)]
 
 
 def diag():
@@ -81,7 +83,7 @@ def diag():
     return L
 
 
-@pytest.mark.parametrize("n,h,w,ci,co", OPS)
+@pytest.mark.parametrize("n,h,w,ci,co", OPS_FWD)
 def test_mfma_conv_forward_exact_on_bf16_inputs(n, h, w, ci, co):
     import torch
     L = diag()
@@ -100,6 +102,72 @@ def test_mfma_conv_forward_exact_on_bf16_inputs(n, h, w, ci, co):
             ref = np.maximum(ref, 0)
         got = yt.cpu().numpy().astype(np.float64)
         assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+# (n, h, w, cu, cs, co): 32- and 64-channel workgroups, one and several chunks per source
+OPS_UPCAT = [(2, 32, 48, 64, 32, 32), (3, 16, 32, 32, 64, 64), (2, 256, 256, 64, 32, 64), (1, 256, 256, 32, 64, 128),
+             (1, 128, 256, 256, 128, 128)]
+
+
+@pytest.mark.parametrize("n,h,w,cu,cs,co", OPS_UPCAT)
+def test_mfma_conv_of_upsampled_concat_exact_on_bf16_inputs(n, h, w, cu, cs, co):
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_upcat
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int32] * 7
+    rng = np.random.default_rng(cu + cs + co)
+    u = bf16_round(rng.normal(size=(n, h // 2, w // 2, cu)))
+    sk = bf16_round(rng.normal(size=(n, h, w, cs)))
+    W = bf16_round(rng.normal(size=(co, cu + cs, 3, 3)) * 0.1)
+    b = rng.normal(size=co)
+    dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    ut, st, wt, bt = dev(u), dev(sk), dev(W), dev(b)
+    yt = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    z = np.concatenate([unet.up2(u), sk], axis=3)
+    ref0 = unet.conv3(z, W, b.astype(np.float32).astype(np.float64))
+    for relu in (0, 1):
+        print(f"case upcat {(n, h, w, cu, cs, co)} relu={relu}", flush=True)
+        assert fn(ut.data_ptr(), st.data_ptr(), wt.data_ptr(), bt.data_ptr(), yt.data_ptr(), n, h, w, cu, cs, co,
+                  relu) == 0
+        ref = np.maximum(ref0, 0) if relu else ref0
+        got = yt.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 32)])
+def test_mfma_conv_with_fused_head(n, h, w, ci, co):
+    # the BF16 activations are those of the plain kernel; only the FP32 order of the
+    # head's channel sum differs from a sequential dot product
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_head
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int32, ctypes.c_float, ctypes.c_void_p] + [ctypes.c_int32] * 5
+    rng = np.random.default_rng(ci * co)
+    cin = 3
+    x = bf16_round(rng.normal(size=(n, h, w, ci)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
+    b = rng.normal(size=co).astype(np.float32)
+    hw = rng.normal(size=co).astype(np.float32)
+    hb = np.float32(rng.normal())
+    xin = rng.normal(size=(n, h, w, cin)).astype(np.float32)
+    scale = 0.37
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    xt, wt, bt, hwt, hbt, xint = dev(x), dev(W), dev(b), dev(hw), dev(np.array([hb])), dev(xin)
+    out = torch.empty((n, h, w), dtype=torch.float32, device="cuda")
+    assert fn(xt.data_ptr(), wt.data_ptr(), bt.data_ptr(), hwt.data_ptr(), hbt.data_ptr(), xint.data_ptr(), cin,
+              scale, out.data_ptr(), n, h, w, ci, co) == 0
+    # activations from the plain kernel, then the head in float64
+    yt = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    assert L.lbsg_diag_conv3(xt.data_ptr(), wt.data_ptr(), bt.data_ptr(), yt.data_ptr(), n, h, w, ci, co, 1) == 0
+    y = yt.cpu().numpy().astype(np.float64)
+    ref = xin[..., 0].astype(np.float64) + scale * (float(hb) + y @ hw.astype(np.float64))
+    got = out.cpu().numpy().astype(np.float64)
+    bound = 5e-6 * (np.abs(xin[..., 0]) + scale * (abs(float(hb)) + np.abs(y) @ np.abs(hw.astype(np.float64))))
+    assert np.all(np.abs(got - ref) <= bound), np.abs(got - ref).max()
 
 
 @pytest.mark.parametrize("n,h,w,ci,co", OPS)
