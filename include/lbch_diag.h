@@ -39,6 +39,11 @@ lbch_status lbsg_diag_conv3(const float* x, const float* w, const float* bias, f
 lbch_status lbsg_diag_conv3_upcat(const float* u, const float* sk, const float* w, const float* bias, float* y,
                                   int32_t n, int32_t h, int32_t wd, int32_t cu, int32_t cs, int32_t co, int32_t relu);
 
+/* The encoder's second convolution: y as lbsg_diag_conv3 with ReLU, and
+ * yp[N][H/2][W/2][Co] its 2x2 average (BF16), formed in the same kernel. */
+lbch_status lbsg_diag_conv3_pool(const float* x, const float* w, const float* bias, float* y, float* yp, int32_t n,
+                                 int32_t h, int32_t wd, int32_t ci, int32_t co);
+
 /* The decoder's last convolution with the 1x1 head in its epilogue:
  * out[p] = xin[p * cin] + scale (hb[0] + sum_c hw[c] y[p][c]), y the BF16
  * ReLU activations of conv3(x, w) + bias (not stored); Co = 32 or 64. */

@@ -12,6 +12,10 @@ hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf1
 // channels, H/2 x Wd/2), Sk (Cs channels, H x Wd)] without forming it.
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s);
+// ReLU conv3_fwd writing Y and, to Yp (N x H/2 x Wd/2 x Co), its 2x2
+// average with the arithmetic of avgpool2 (the encoder's second convolution).
+hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, __bf16* Yp, int N, int H,
+                               int Wd, int Ci, int Co, hipStream_t s);
 // ReLU conv3_fwd (Co = 32 or 64, one workgroup per 16 x 16 pixel tile) with
 // the 1x1 head in its epilogue: out[p] = xin[p * cin] + scale (hb[0] + sum_c
 // hw[c] y[p][c]) over the BF16 activations y, which go to Y unless it is NULL.

@@ -21,6 +21,11 @@ __device__ __forceinline__ f32x4 mfma16(const bf16x8& a, const bf16x8& b, const 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// v from lane (lane ^ 1): DPP quad permutation [1, 0, 3, 2]
+__device__ __forceinline__ float lane_xor1(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
 // Scheduling pattern for NL LDS reads among MF matrix-core instructions: one
 // read, then two (or one, when reads outnumber half the MFMAs) MFMAs, repeated.
 template <int NL, int MF>
@@ -58,6 +63,9 @@ __device__ __forceinline__ void interleave_ds_mfma() {
 // HEAD (Co = TC, one workgroup per pixel tile): the 1x1 output head is applied
 // in the epilogue, out[p] = xin[p][0] + scale (b + sum_c w_c y[p][c]) over the
 // BF16-rounded activations; Y (nullable) still receives them.
+// POOL: Y as usual, and Yp (H/2 x Wd/2) receives its 2x2 average with the
+// arithmetic of avgpool2_k: the rows of a 2x2 block belong to one wave (rows
+// r, r + 1), the columns to lanes l16 and l16 ^ 1.
 // ---------------------------------------------------------------------------
 struct HeadArgs {
     const float* w;      // [Co] head weights
@@ -68,11 +76,11 @@ struct HeadArgs {
     float scale;
 };
 
-template <int TC, bool RELU, bool UPCAT, bool HEAD = false>
+template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false>
 __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
                                                    const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                    __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
-                                                   const HeadArgs hd = HeadArgs{}) {
+                                                   const HeadArgs hd = HeadArgs{}, __bf16* __restrict__ Yp = nullptr) {
     constexpr int NXQ = 18 * 18 * 4;              // 16-byte chunks of the pixel tile
     constexpr int NWQ = 9 * TC * 4;               // 16-byte chunks of the weights
     constexpr int RX = (NXQ + 255) / 256, RW = (NWQ + 255) / 256;
@@ -222,6 +230,7 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
             xr[r] = hd.xin[(((size_t)n * H + ty0 + wave * 4 + r) * Wd + tx0 + l16) * hd.cin];
         hb0 = hd.b[0];
     }
+    bf16x4 prev[POOL ? CB : 1];   // row r - 1 of the 2x2 block (POOL)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int y = ty0 + wave * 4 + r, x = tx0 + l16;
@@ -238,6 +247,21 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
                 if constexpr (HEAD) part += hv[c][j] * (float)o[j];
             }
             if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
+            if constexpr (POOL) {
+                if ((r & 1) == 0) {
+                    prev[c] = o;
+                } else {
+                    // even lanes: ((a + b) + (c + d)) with a, b the upper row, c, d this one
+                    bf16x4 q;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float up = (float)prev[c][j], lo = (float)o[j];
+                        q[j] = (__bf16)(0.25f * ((up + lane_xor1(up)) + (lo + lane_xor1(lo))));
+                    }
+                    if ((l16 & 1) == 0)
+                        *reinterpret_cast<bf16x4*>(Yp + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Co + co) = q;
+                }
+            }
         }
         if constexpr (HEAD) {
             // lanes l16, l16 + 16, l16 + 32, l16 + 48 hold the four channel groups of one pixel
@@ -786,6 +810,20 @@ hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, 
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s) {
     if (H % 16 || Wd % 16 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || Co % 32) return hipErrorInvalidValue;
     return conv3_fwd_any<true>(U, Sk, Cu, Wt, bias, Y, N, H, Wd, Cu + Cs, Co, relu, s);
+}
+
+hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, __bf16* Yp, int N, int H,
+                               int Wd, int Ci, int Co, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || Co % 32 || !Y || !Yp) return hipErrorInvalidValue;
+    const int tiles = N * (H / 16) * (Wd / 16);
+    if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512) {
+        conv3_fwd_k<64, true, false, false, true><<<dim3(tiles, Co / 64), 256, 0, s>>>(X, nullptr, 0, Wt, bias, Y, H,
+                                                                                      Wd, Ci, Co, HeadArgs{}, Yp);
+    } else {
+        conv3_fwd_k<32, true, false, false, true><<<dim3(tiles, Co / 32), 256, 0, s>>>(X, nullptr, 0, Wt, bias, Y, H,
+                                                                                      Wd, Ci, Co, HeadArgs{}, Yp);
+    }
+    return hipGetLastError();
 }
 
 hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd,

@@ -142,11 +142,14 @@ lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, in
     for (int l = 0; l < Lv; ++l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        if (l > 0) HIP_TRY(lbsg::avgpool2(n->lv[l - 1].e, lv.z, B, h * 2, w * 2, C[l - 1], n->stream));
         const Layer& La = n->layers[li++];
         const Layer& Lb = n->layers[li++];
         HIP_TRY(lbsg::conv3_fwd(lv.z, La.wt, n->w + La.offB, lv.a, B, h, w, La.ci_pad, La.co, true, n->stream));
-        HIP_TRY(lbsg::conv3_fwd(lv.a, Lb.wt, n->w + Lb.offB, lv.e, B, h, w, Lb.ci_pad, Lb.co, true, n->stream));
+        if (l + 1 < Lv)   // the next level's input, pooled in the epilogue
+            HIP_TRY(lbsg::conv3_fwd_relu_pool(lv.a, Lb.wt, n->w + Lb.offB, lv.e, n->lv[l + 1].z, B, h, w, Lb.ci_pad,
+                                              Lb.co, n->stream));
+        else
+            HIP_TRY(lbsg::conv3_fwd(lv.a, Lb.wt, n->w + Lb.offB, lv.e, B, h, w, Lb.ci_pad, Lb.co, true, n->stream));
     }
     const __bf16* d = n->lv[Lv - 1].e;
     for (int l = Lv - 2; l >= 0; --l) {
@@ -517,6 +520,27 @@ extern "C" lbch_status lbsg_diag_conv3_upcat(const float* u, const float* sk, co
     HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
     HIP_TRY(lbsg::conv3_fwd_upcat(ub, sb, wt, bias, yb, n, h, wd, cu, cs, co, relu != 0, nullptr));
     HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_pool(const float* x, const float* w, const float* bias, float* y, float* yp,
+                                            int32_t n, int32_t h, int32_t wd, int32_t ci, int32_t co) {
+    if (!x || !w || !y || !yp) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    __bf16* xb = S.get<__bf16>(P * ci);
+    __bf16* wt = S.get<__bf16>((size_t)co * 9 * ci);
+    __bf16* yb = S.get<__bf16>(P * co);
+    __bf16* pb = S.get<__bf16>(P / 4 * co);
+    if (!xb || !wt || !yb || !pb) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
+    HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
+    HIP_TRY(lbsg::conv3_fwd_relu_pool(xb, wt, bias, yb, pb, n, h, wd, ci, co, nullptr));
+    HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
+    HIP_TRY(lbsg::widen(pb, yp, P / 4 * co, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }

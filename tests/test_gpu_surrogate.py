@@ -136,6 +136,35 @@ def test_mfma_conv_of_upsampled_concat_exact_on_bf16_inputs(n, h, w, cu, cs, co)
         assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 64),
+                                         (1, 64, 64, 128, 256)])
+def test_mfma_conv_with_fused_pooling_is_bitwise(n, h, w, ci, co):
+    # y equals the plain ReLU kernel's output and yp the 2x2 average of it with the pooling
+    # kernel's arithmetic: bf16(0.25 ((a + b) + (c + d))) in FP32, bit for bit
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_pool
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int32] * 5
+    rng = np.random.default_rng(ci + 7 * co)
+    x = bf16_round(rng.normal(size=(n, h, w, ci)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
+    b = rng.normal(size=co)
+    dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    xt, wt, bt = dev(x), dev(W), dev(b)
+    y = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    yp = torch.empty((n, h // 2, w // 2, co), dtype=torch.float32, device="cuda")
+    y0 = torch.empty_like(y)
+    assert fn(xt.data_ptr(), wt.data_ptr(), bt.data_ptr(), y.data_ptr(), yp.data_ptr(), n, h, w, ci, co) == 0
+    assert L.lbsg_diag_conv3(xt.data_ptr(), wt.data_ptr(), bt.data_ptr(), y0.data_ptr(), n, h, w, ci, co, 1) == 0
+    yc = y.cpu()
+    assert torch.equal(yc, y0.cpu())
+    a, bb, c, d = yc[:, 0::2, 0::2], yc[:, 0::2, 1::2], yc[:, 1::2, 0::2], yc[:, 1::2, 1::2]
+    want = (0.25 * ((a + bb) + (c + d))).to(torch.bfloat16).to(torch.float32)
+    assert torch.equal(yp.cpu(), want)
+
+
 @pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 32)])
 def test_mfma_conv_with_fused_head(n, h, w, ci, co):
     # the BF16 activations are those of the plain kernel; only the FP32 order of the
