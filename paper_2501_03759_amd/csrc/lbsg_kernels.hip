@@ -13,7 +13,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kPadC = 40;   // LDS stride (bf16) of one pixel's 32-channel chunk: 80 bytes
+// LDS layout of the forward convolution's tiles: one 64-byte row per pixel
+// (or weight row) holding its 32-channel chunk as four 16-byte parts, part k
+// of row p stored in slot k ^ ((p >> 1) & 3).  Measured on gfx950 (rocprofv3
+// SQ_LDS_BANK_CONFLICT), this keeps both the 16-byte staging writes (four
+// lanes per row) and the MFMA fragment reads (16 consecutive rows, one part
+// per lane group) free of bank conflicts; an 80-byte padded row conflicts
+// two-way on both.
+__device__ __forceinline__ int lds_part(int p, int k) { return p * 32 + ((k ^ ((p >> 1) & 3)) << 3); }
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -77,15 +84,15 @@ struct HeadArgs {
 };
 
 template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false>
-__global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
+__global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
                                                    const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                    __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
                                                    const HeadArgs hd = HeadArgs{}, __bf16* __restrict__ Yp = nullptr) {
     constexpr int NXQ = 18 * 18 * 4;              // 16-byte chunks of the pixel tile
     constexpr int NWQ = 9 * TC * 4;               // 16-byte chunks of the weights
     constexpr int RX = (NXQ + 255) / 256, RW = (NWQ + 255) / 256;
-    __shared__ __align__(16) __bf16 sx[18 * 18 * kPadC];
-    __shared__ __align__(16) __bf16 sw[9 * TC * kPadC];
+    __shared__ __align__(16) __bf16 sx[18 * 18 * 32];
+    __shared__ __align__(16) __bf16 sw[9 * TC * 32];
     constexpr int CB = TC / 16;
     const int tiles_x = Wd / 16, tiles_y = H / 16;
     int b = blockIdx.x;
@@ -149,12 +156,12 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
 #pragma unroll
         for (int i = 0; i < RX; ++i) {
             const int q = (int)threadIdx.x + i * 256;
-            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + (q >> 2) * kPadC + (q & 3) * 8) = rx[i];
+            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + lds_part(q >> 2, q & 3)) = rx[i];
         }
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             const int q = (int)threadIdx.x + i * 256;
-            if (q < NWQ) *reinterpret_cast<bf16x8*>(sw + (q >> 2) * kPadC + (q & 3) * 8) = rw[i];
+            if (q < NWQ) *reinterpret_cast<bf16x8*>(sw + lds_part(q >> 2, q & 3)) = rw[i];
         }
         __syncthreads();
         if (cc + 32 < Ci) {                       // next chunk in flight during the MFMAs
@@ -168,12 +175,12 @@ __global__ __launch_bounds__(256) void conv3_fwd_k(const __bf16* __restrict__ X,
         // read from LDS while the MFMAs of tap t run.
         bf16x8 bq[2][6], aq[2][CB];
         auto ld_b = [&](int kx, int j, bf16x8& v) {
-            v = *reinterpret_cast<const bf16x8*>(sx + ((wave * 4 + j) * 18 + l16 + kx) * kPadC + kb * 8);
+            v = *reinterpret_cast<const bf16x8*>(sx + lds_part((wave * 4 + j) * 18 + l16 + kx, kb));
         };
         auto ld_a = [&](int kx, int ky, bf16x8 (&a)[CB]) {
 #pragma unroll
             for (int c = 0; c < CB; ++c)
-                a[c] = *reinterpret_cast<const bf16x8*>(sw + ((ky * 3 + kx) * TC + c * 16 + l16) * kPadC + kb * 8);
+                a[c] = *reinterpret_cast<const bf16x8*>(sw + lds_part((ky * 3 + kx) * TC + c * 16 + l16, kb));
         };
 #pragma unroll
         for (int j = 0; j < 4; ++j) ld_b(0, j, bq[0][j]);
