@@ -309,43 +309,74 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
     f32x4 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tile = s; tile < ntiles; tile += S) {
+    // Staging items of one tile: dY^T items (channel group of 8, quad of 4 pixels
+    // in one tile row), exactly two per thread; X halo items (shift dx, halo row
+    // 0..17, pixel quad, channel group; copy dx holds X[row ty0 - 1 + r][column
+    // tx0 + px + dx] at [ch][r * 16 + px]), NXI per thread, the last one guarded.
+    // The next tile's items are loaded into registers while the matrix cores
+    // work on the current one.
+    constexpr int NXQ = 3 * 18 * 4 * 2, NXI = (NXQ + NT - 1) / NT;
+    bf16x8 ry[2][4], rx[NXI][4];
+    auto load_tile = [&](int tile) {
         int b = tile;
         const int tx0 = (b % tiles_x) * 16;
         b /= tiles_x;
         const int ty0 = (b % tiles_y) * 16;
         const int n = b / tiles_y;
-        __syncthreads();
-        // dY^T: item = (channel group of 8, quad of 4 pixels in one tile row)
-        for (int q = threadIdx.x; q < 64 * (TCO / 8); q += NT) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = (int)threadIdx.x + i * NT;
             const int pq = q & 63, ch = q >> 6;
             const int p0 = pq * 4;
             const __bf16* src = dY + (((size_t)n * H + ty0 + (p0 >> 4)) * Wd + tx0 + (p0 & 15)) * Co + co0 + ch * 8;
-            bf16x8 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const bf16x8*>(src + (size_t)u * Co);
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                *reinterpret_cast<bf16x4*>(sdy + (ch * 8 + e) * KS + p0) = bf16x4{v[0][e], v[1][e], v[2][e], v[3][e]};
+            for (int u = 0; u < 4; ++u) ry[i][u] = *reinterpret_cast<const bf16x8*>(src + (size_t)u * Co);
         }
-        // X halo: item = (shift dx, halo row 0..17, pixel quad, channel group); copy dx holds
-        // X[row ty0 - 1 + r][column tx0 + px + dx] at [ch][r * 16 + px]
-        for (int q = threadIdx.x; q < 3 * 18 * 4 * 2; q += NT) {
-            const int pq = q & 3, ch = (q >> 2) & 1, rr = q >> 3;
-            const int r = rr % 18, c = rr / 18;
-            const int y = wrap(ty0 - 1 + r, H);
-            bf16x8 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int x = wrap(tx0 + pq * 4 + u + c - 1, Wd);
-                v[u] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
+        for (int i = 0; i < NXI; ++i) {
+            const int q = (int)threadIdx.x + i * NT;
+            if (q < NXQ) {
+                const int pq = q & 3, ch = (q >> 2) & 1, rr = q >> 3;
+                const int r = rr % 18, c = rr / 18;
+                const int y = wrap(ty0 - 1 + r, H);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int x = wrap(tx0 + pq * 4 + u + c - 1, Wd);
+                    rx[i][u] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
+                }
             }
+        }
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = (int)threadIdx.x + i * NT;
+            const int pq = q & 63, ch = q >> 6;
+            const int p0 = pq * 4;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                *reinterpret_cast<bf16x4*>(sxh + (c * 16 + ch * 8 + e) * HS + r * 16 + pq * 4) =
-                    bf16x4{v[0][e], v[1][e], v[2][e], v[3][e]};
+                *reinterpret_cast<bf16x4*>(sdy + (ch * 8 + e) * KS + p0) =
+                    bf16x4{ry[i][0][e], ry[i][1][e], ry[i][2][e], ry[i][3][e]};
         }
+#pragma unroll
+        for (int i = 0; i < NXI; ++i) {
+            const int q = (int)threadIdx.x + i * NT;
+            if (q < NXQ) {
+                const int pq = q & 3, ch = (q >> 2) & 1, rr = q >> 3;
+                const int r = rr % 18, c = rr / 18;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    *reinterpret_cast<bf16x4*>(sxh + (c * 16 + ch * 8 + e) * HS + r * 16 + pq * 4) =
+                        bf16x4{rx[i][0][e], rx[i][1][e], rx[i][2][e], rx[i][3][e]};
+            }
+        }
+    };
+    if (s < ntiles) load_tile(s);
+    for (int tile = s; tile < ntiles; tile += S) {
+        __syncthreads();                          // every wave is done with the previous tile
+        store_tile();
         __syncthreads();
+        if (tile + S < ntiles) load_tile(tile + S);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3 - 1, dx = tap % 3 - 1;
