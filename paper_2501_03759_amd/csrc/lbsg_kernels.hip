@@ -282,24 +282,44 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 // ---------------------------------------------------------------------------
 // Weight gradient of the 3x3 convolution on the matrix cores:
 //   P[s][co][tap][ci] = sum over the pixels of split s of dY[p][co] X[p + tap][ci]
-// GEMM per tap: M = co, N = ci, K = pixels.  The operands need 8 consecutive
-// pixels per lane, so both are staged transposed ([channel][pixel]) in LDS,
-// once per 16x16 pixel tile: dY (TCO channels) and the X halo of the tile's
-// 18 rows (16 channels) in three copies shifted by dx = -1, 0, +1 columns, so
-// that the B operand of every tap is an aligned 16-byte read.  Transposes go
-// through 8-byte writes of four pixels of one channel.  Wave w owns output
+// GEMM per tap: M = co, N = ci, K = pixels.  Per 16x16 pixel tile the
+// workgroup copies, channels-last as in HBM, the tile's dY (TCO channels) and
+// the X halo (18 x 18 pixels, 16 channels of the ci block) into LDS with
+// 16-byte stores.  The operands need 8 consecutive pixels of one channel per
+// lane; gfx950's transposing LDS read (ds_read_b64_tr_b16) delivers them: in a
+// group of 16 lanes, lane m reads 4 channels (4 (m & 3) ..) of pixel pb + m/4,
+// and lane i receives channel i of pixels pb .. pb + 3.  Two such reads give
+// one operand.  The A operand (dY) of a K step serves all nine taps.  The next
+// tile's global loads are in flight during the MFMAs.  Wave w owns output
 // channels 16w..16w+15 and all 9 taps of a 16-channel ci block.  Splits are
 // reduced by wgrad_reduce_k (fixed order: deterministic).
 // ---------------------------------------------------------------------------
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x4 lds_read_tr(const __bf16* p) {
+    const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4*)p);
+    return __builtin_bit_cast(bf16x4, v);
+}
+
+__device__ __forceinline__ bf16x8 cat8(const bf16x4& a, const bf16x4& b) {
+    return bf16x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+
 template <int TCO>
 __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__ X, const __bf16* __restrict__ dY,
                                                       float* __restrict__ part, int N, int H, int Wd, int Ci, int Co,
                                                       int S) {
     constexpr int NT = TCO * 4;          // 64 threads (one wave) per 16 output channels
-    constexpr int KS = 256 + 8;          // channel stride (bf16) of the transposed dY tile
-    constexpr int HS = 18 * 16 + 8;      // channel stride of one shifted X copy: 18 rows x 16 pixels
-    __shared__ __align__(16) __bf16 sdy[TCO * KS];
-    __shared__ __align__(16) __bf16 sxh[3 * 16 * HS];
+    // LDS strides (bf16) of one dY pixel and one X halo pixel, chosen by
+    // measurement (SQ_LDS_BANK_CONFLICT): the 16-byte stores are conflict-free
+    // at 72 / 32 / 16, and the transposing reads cost their minimum there (a
+    // 64-element dY stride doubles their cost)
+    constexpr int SP = TCO == 64 ? 72 : 32;
+    constexpr int SXP = 16;
+    constexpr int NYQ = 256 * TCO / 8, NYI = NYQ / NT;           // dY 16-byte chunks (NYI = 8 per thread)
+    constexpr int NXQ = 18 * 18 * 2, NXI = (NXQ + NT - 1) / NT;  // X halo chunks, the last item guarded
+    __shared__ __align__(16) __bf16 sdy[256 * SP];
+    __shared__ __align__(16) __bf16 sx[18 * 18 * SXP];
     const int s = blockIdx.x;
     const int co0 = blockIdx.y * TCO;
     const int ci0 = blockIdx.z * 16;
@@ -309,14 +329,7 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
     f32x4 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // Staging items of one tile: dY^T items (channel group of 8, quad of 4 pixels
-    // in one tile row), exactly two per thread; X halo items (shift dx, halo row
-    // 0..17, pixel quad, channel group; copy dx holds X[row ty0 - 1 + r][column
-    // tx0 + px + dx] at [ch][r * 16 + px]), NXI per thread, the last one guarded.
-    // The next tile's items are loaded into registers while the matrix cores
-    // work on the current one.
-    constexpr int NXQ = 3 * 18 * 4 * 2, NXI = (NXQ + NT - 1) / NT;
-    bf16x8 ry[2][4], rx[NXI][4];
+    bf16x8 ry[NYI], rx[NXI];
     auto load_tile = [&](int tile) {
         int b = tile;
         const int tx0 = (b % tiles_x) * 16;
@@ -324,53 +337,36 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
         const int ty0 = (b % tiles_y) * 16;
         const int n = b / tiles_y;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < NYI; ++i) {
             const int q = (int)threadIdx.x + i * NT;
-            const int pq = q & 63, ch = q >> 6;
-            const int p0 = pq * 4;
-            const __bf16* src = dY + (((size_t)n * H + ty0 + (p0 >> 4)) * Wd + tx0 + (p0 & 15)) * Co + co0 + ch * 8;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) ry[i][u] = *reinterpret_cast<const bf16x8*>(src + (size_t)u * Co);
+            const int px = q / (TCO / 8), ch = q % (TCO / 8);
+            ry[i] = *reinterpret_cast<const bf16x8*>(
+                dY + (((size_t)n * H + ty0 + (px >> 4)) * Wd + tx0 + (px & 15)) * Co + co0 + ch * 8);
         }
 #pragma unroll
         for (int i = 0; i < NXI; ++i) {
             const int q = (int)threadIdx.x + i * NT;
             if (q < NXQ) {
-                const int pq = q & 3, ch = (q >> 2) & 1, rr = q >> 3;
-                const int r = rr % 18, c = rr / 18;
-                const int y = wrap(ty0 - 1 + r, H);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int x = wrap(tx0 + pq * 4 + u + c - 1, Wd);
-                    rx[i][u] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
-                }
+                const int hp = q >> 1, ch = q & 1;
+                const int y = wrap(ty0 - 1 + hp / 18, H), x = wrap(tx0 - 1 + hp % 18, Wd);
+                rx[i] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
             }
         }
     };
     auto store_tile = [&]() {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < NYI; ++i) {
             const int q = (int)threadIdx.x + i * NT;
-            const int pq = q & 63, ch = q >> 6;
-            const int p0 = pq * 4;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                *reinterpret_cast<bf16x4*>(sdy + (ch * 8 + e) * KS + p0) =
-                    bf16x4{ry[i][0][e], ry[i][1][e], ry[i][2][e], ry[i][3][e]};
+            *reinterpret_cast<bf16x8*>(sdy + (q / (TCO / 8)) * SP + (q % (TCO / 8)) * 8) = ry[i];
         }
 #pragma unroll
         for (int i = 0; i < NXI; ++i) {
             const int q = (int)threadIdx.x + i * NT;
-            if (q < NXQ) {
-                const int pq = q & 3, ch = (q >> 2) & 1, rr = q >> 3;
-                const int r = rr % 18, c = rr / 18;
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    *reinterpret_cast<bf16x4*>(sxh + (c * 16 + ch * 8 + e) * HS + r * 16 + pq * 4) =
-                        bf16x4{rx[i][0][e], rx[i][1][e], rx[i][2][e], rx[i][3][e]};
-            }
+            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + (q >> 1) * SXP + (q & 1) * 8) = rx[i];
         }
     };
+    // lane m = l16 of its group reads channels 4 (m & 3) .. of pixel (group base) + m / 4
+    const int mp = l16 >> 2, mc = (l16 & 3) * 4;
     if (s < ntiles) load_tile(s);
     for (int tile = s; tile < ntiles; tile += S) {
         __syncthreads();                          // every wave is done with the previous tile
@@ -378,15 +374,16 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
         __syncthreads();
         if (tile + S < ntiles) load_tile(tile + S);
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        for (int k0 = 0; k0 < 256; k0 += 32) {
+            // this lane group's 8 pixels k0 + 8 kb .. + 7: tile row py, columns px0 .. px0 + 7
+            const int k = k0 + kb * 8, py = k >> 4, px0 = k & 15;
+            const __bf16* pa = sdy + (k + mp) * SP + wave * 16 + mc;
+            const bf16x8 a = cat8(lds_read_tr(pa), lds_read_tr(pa + 4 * SP));
 #pragma unroll
-            for (int k0 = 0; k0 < 256; k0 += 32) {
-                // pixels k0 + 8 kb .. + 7: tile row py, columns px0 .. px0 + 7
-                const int k = k0 + kb * 8, py = k >> 4, px0 = k & 15;
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(sdy + (wave * 16 + l16) * KS + k);
-                const bf16x8 bb =
-                    *reinterpret_cast<const bf16x8*>(sxh + ((dx + 1) * 16 + l16) * HS + (py + 1 + dy) * 16 + px0);
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const __bf16* pb = sx + ((py + 1 + dy) * 18 + px0 + 1 + dx + mp) * SXP + mc;
+                const bf16x8 bb = cat8(lds_read_tr(pb), lds_read_tr(pb + 4 * SXP));
                 acc[tap] = mfma16(a, bb, acc[tap]);
             }
         }
