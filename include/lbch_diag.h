@@ -60,6 +60,11 @@ lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, float* dx, in
 lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, float* dw, int32_t n, int32_t h, int32_t wd,
                                   int32_t ci, int32_t co);
 
+/* db[Co] = sum over pixels of dy[p][co] (FP32), as the weight-gradient kernel
+ * forms it beside dw (split partials, fixed-order reduction). */
+lbch_status lbsg_diag_conv3_bgrad(const float* x, const float* dy, float* db, int32_t n, int32_t h, int32_t wd,
+                                  int32_t ci, int32_t co);
+
 #ifdef __cplusplus
 }
 #endif

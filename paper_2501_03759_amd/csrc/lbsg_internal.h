@@ -12,6 +12,10 @@ hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf1
 // channels, H/2 x Wd/2), Sk (Cs channels, H x Wd)] without forming it.
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s);
+// conv3_fwd without bias or activation whose BF16 result is masked:
+// Y = Mask > 0 ? y : 0 (Mask laid out as Y), as relu_bwd would.
+hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mask, __bf16* Y, int N, int H, int Wd,
+                            int Ci, int Co, hipStream_t s);
 // ReLU conv3_fwd writing Y and, to Yp (N x H/2 x Wd/2 x Co), its 2x2
 // average with the arithmetic of avgpool2 (the encoder's second convolution).
 hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, __bf16* Yp, int N, int H,
@@ -22,8 +26,11 @@ hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* b
 hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd,
                                int Ci, int Co, const float* hw, const float* hb, const float* xin, int cin, float* out,
                                float scale, hipStream_t s);
+// Weight-gradient split partials; bpart (nullable, S x Co floats) receives the
+// bias gradient's split partials, reduced by colsum_reduce.
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
-                    hipStream_t s);
+                    hipStream_t s, float* bpart = nullptr);
+hipError_t colsum_reduce(const float* part, int S, int C, float* out, hipStream_t s);
 hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s);
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s);
 hipError_t gather(const float* field, int H, int W, const int* yx, int k, int crop, const float* cond, int ncond,

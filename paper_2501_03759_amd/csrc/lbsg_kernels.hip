@@ -73,6 +73,9 @@ __device__ __forceinline__ void interleave_ds_mfma() {
 // POOL: Y as usual, and Yp (H/2 x Wd/2) receives its 2x2 average with the
 // arithmetic of avgpool2_k: the rows of a 2x2 block belong to one wave (rows
 // r, r + 1), the columns to lanes l16 and l16 ^ 1.
+// Mask (nullable, same layout as Y): Y = Mask > 0 ? y : 0 elementwise, the
+// ReLU backward of relu_bwd_k applied to the BF16 result (for data gradients
+// whose next consumer masks them by the previous layer's activation).
 // ---------------------------------------------------------------------------
 struct HeadArgs {
     const float* w;      // [Co] head weights
@@ -87,7 +90,8 @@ template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false>
 __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
                                                    const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                    __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
-                                                   const HeadArgs hd = HeadArgs{}, __bf16* __restrict__ Yp = nullptr) {
+                                                   const HeadArgs hd = HeadArgs{}, __bf16* __restrict__ Yp = nullptr,
+                                                   const __bf16* __restrict__ Mask = nullptr) {
     constexpr int NXQ = 18 * 18 * 4;              // 16-byte chunks of the pixel tile
     constexpr int NWQ = 9 * TC * 4;               // 16-byte chunks of the weights
     constexpr int RX = (NXQ + 255) / 256, RW = (NWQ + 255) / 256;
@@ -253,6 +257,11 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
                 o[j] = (__bf16)v;
                 if constexpr (HEAD) part += hv[c][j] * (float)o[j];
             }
+            if (!RELU && !HEAD && !POOL && Mask) {
+                const bf16x4 m = *reinterpret_cast<const bf16x4*>(Mask + (((size_t)n * H + y) * Wd + x) * Co + co);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = (float)m[j] > 0.f ? o[j] : (__bf16)0.f;
+            }
             if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
             if constexpr (POOL) {
                 if ((r & 1) == 0) {
@@ -292,7 +301,11 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 // one operand.  The A operand (dY) of a K step serves all nine taps.  The next
 // tile's global loads are in flight during the MFMAs.  Wave w owns output
 // channels 16w..16w+15 and all 9 taps of a 16-channel ci block.  Splits are
-// reduced by wgrad_reduce_k (fixed order: deterministic).
+// reduced by wgrad_reduce_k (fixed order: deterministic).  With bpart, the
+// workgroups of the first ci block also form the bias gradient's split
+// partials bpart[s][co] = sum over the split's pixels of dY[p][co]: each thread
+// always stages the same 8 channels and sums them in tile order, then a fixed
+// order over the threads of a channel (reduced over splits by colsum_reduce_k).
 // ---------------------------------------------------------------------------
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
@@ -308,7 +321,7 @@ __device__ __forceinline__ bf16x8 cat8(const bf16x4& a, const bf16x4& b) {
 template <int TCO>
 __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__ X, const __bf16* __restrict__ dY,
                                                       float* __restrict__ part, int N, int H, int Wd, int Ci, int Co,
-                                                      int S) {
+                                                      int S, float* __restrict__ bpart) {
     constexpr int NT = TCO * 4;          // 64 threads (one wave) per 16 output channels
     // LDS strides (bf16) of one dY pixel and one X halo pixel, chosen by
     // measurement (SQ_LDS_BANK_CONFLICT): the 16-byte stores are conflict-free
@@ -330,6 +343,8 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     bf16x8 ry[NYI], rx[NXI];
+    const bool bsum = bpart != nullptr && blockIdx.z == 0;
+    float csum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // channels co0 + 8 (tid % (TCO / 8)) + e
     auto load_tile = [&](int tile) {
         int b = tile;
         const int tx0 = (b % tiles_x) * 16;
@@ -358,6 +373,12 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
         for (int i = 0; i < NYI; ++i) {
             const int q = (int)threadIdx.x + i * NT;
             *reinterpret_cast<bf16x8*>(sdy + (q / (TCO / 8)) * SP + (q % (TCO / 8)) * 8) = ry[i];
+        }
+        if (bsum) {
+#pragma unroll
+            for (int i = 0; i < NYI; ++i)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) csum[e] += (float)ry[i][e];
         }
 #pragma unroll
         for (int i = 0; i < NXI; ++i) {
@@ -396,6 +417,20 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
             const int co = co0 + wave * 16 + kb * 4 + j;
             part[(((size_t)s * Co + co) * 9 + tap) * Ci + ci0 + l16] = acc[tap][j];
         }
+    if (bsum) {
+        // the 32 threads tid = g + k TCO / 8 (k = 0..31) hold channels 8 g .. 8 g + 7
+        __syncthreads();                          // every wave is done reading sdy
+        float* red = reinterpret_cast<float*>(sdy);   // NT x 8 floats <= the dY tile's bytes
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[threadIdx.x * 8 + e] = csum[e];
+        __syncthreads();
+        if ((int)threadIdx.x < TCO) {
+            const int g = threadIdx.x >> 3, e = threadIdx.x & 7;
+            float v = 0.f;
+            for (int k = 0; k < NT / (TCO / 8); ++k) v += red[(g + k * (TCO / 8)) * 8 + e];
+            bpart[(size_t)s * Co + co0 + threadIdx.x] = v;
+        }
+    }
 }
 
 // dW[co][ci][ky][kx] (FP32 parameter layout, only the first ci_real input
@@ -841,6 +876,19 @@ hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf1
     return conv3_fwd_any<false>(X, nullptr, 0, Wt, bias, Y, N, H, Wd, Ci, Co, relu, s);
 }
 
+hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mask, __bf16* Y, int N, int H, int Wd,
+                            int Ci, int Co, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || Co % 32 || !Mask) return hipErrorInvalidValue;
+    const int tiles = N * (H / 16) * (Wd / 16);
+    if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512)
+        conv3_fwd_k<64, false, false><<<dim3(tiles, Co / 64), 256, 0, s>>>(X, nullptr, 0, Wt, nullptr, Y, H, Wd, Ci, Co,
+                                                                           HeadArgs{}, nullptr, Mask);
+    else
+        conv3_fwd_k<32, false, false><<<dim3(tiles, Co / 32), 256, 0, s>>>(X, nullptr, 0, Wt, nullptr, Y, H, Wd, Ci, Co,
+                                                                           HeadArgs{}, nullptr, Mask);
+    return hipGetLastError();
+}
+
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s) {
     if (H % 16 || Wd % 16 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || Co % 32) return hipErrorInvalidValue;
@@ -876,15 +924,20 @@ hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* b
 }
 
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
-                    hipStream_t s) {
-    if (H % 16 || Wd % 16 || Ci % 16 || Co % 32) return hipErrorInvalidValue;
+                    hipStream_t s, float* bpart) {
+    if (H % 16 || Wd % 16 || Ci % 16 || Co % 32 || S < 1 || S > N * (H / 16) * (Wd / 16)) return hipErrorInvalidValue;
     if (Co % 64 == 0) {
         dim3 grid(S, Co / 64, Ci / 16);
-        conv3_dw_k<64><<<grid, 256, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S);
+        conv3_dw_k<64><<<grid, 256, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart);
     } else {
         dim3 grid(S, Co / 32, Ci / 16);
-        conv3_dw_k<32><<<grid, 128, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S);
+        conv3_dw_k<32><<<grid, 128, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart);
     }
+    return hipGetLastError();
+}
+
+hipError_t colsum_reduce(const float* part, int S, int C, float* out, hipStream_t s) {
+    colsum_reduce_k<<<(C + 3) / 4, 256, 0, s>>>(part, S, C, out);
     return hipGetLastError();
 }
 

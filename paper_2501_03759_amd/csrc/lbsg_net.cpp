@@ -57,6 +57,7 @@ struct lbsg_net {
     float* wpart = nullptr;          // weight-gradient split partials
     long long wpart_elems = 0;
     float* cpart = nullptr;          // column-sum partials
+    long long cpart_elems = 0;
     float* out = nullptr;            // fp32 prediction [B][H][W]
     float* gout = nullptr;           // fp32 dLoss/dprediction
     float* xin1 = nullptr;           // fp32 phi (one channel) for lbsg_predict
@@ -109,20 +110,37 @@ lbch_status repack(lbsg_net* n) {
 }
 
 // gradient of one conv layer: gout = dLoss/d(post-ReLU output y), input z.
+// gout_masked: gout already carries the ReLU mask of y.  dz_mask (nullable):
+// the data gradient dz is written masked by dz_mask > 0 (the layer whose
+// post-ReLU output is z consumes it as its gout_masked).
 lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16* y, const __bf16* gout, __bf16* dz,
-                      int B, int H, int W) {
+                      int B, int H, int W, bool gout_masked = false, const __bf16* dz_mask = nullptr) {
     const long long P = (long long)B * H * W;
-    HIP_TRY(lbsg::relu_bwd(gout, y, n->gtmp, P * L.co, n->stream));
+    const __bf16* g = gout;
+    if (!gout_masked) {
+        HIP_TRY(lbsg::relu_bwd(gout, y, n->gtmp, P * L.co, n->stream));
+        g = n->gtmp;
+    }
     const int ntiles = B * (H / 16) * (W / 16);
     const int other = (L.co % 64 == 0 ? L.co / 64 : L.co / 32) * (L.ci_pad / 16);
     int S = 1024 / (other > 0 ? other : 1);
     if (S < 1) S = 1;
     if (S > ntiles) S = ntiles;
     while ((long long)S * L.co * 9 * L.ci_pad > n->wpart_elems && S > 1) S /= 2;
-    HIP_TRY(lbsg::conv3_dw(z, n->gtmp, n->wpart, S, B, H, W, L.ci_pad, L.co, n->stream));
+    // the bias gradient's split partials come from the weight-gradient kernel when they fit
+    const bool fused_bias = (long long)S * L.co <= n->cpart_elems;
+    HIP_TRY(lbsg::conv3_dw(z, g, n->wpart, S, B, H, W, L.ci_pad, L.co, n->stream, fused_bias ? n->cpart : nullptr));
     HIP_TRY(lbsg::wgrad_reduce(n->wpart, n->g + L.offW, S, L.co, L.ci_pad, L.ci_real, n->stream));
-    HIP_TRY(lbsg::colsum_bf16(n->gtmp, P, L.co, 256, n->cpart, n->g + L.offB, n->stream));
-    if (dz) HIP_TRY(lbsg::conv3_fwd(n->gtmp, L.wf, nullptr, dz, B, H, W, L.co, L.ci_pad, false, n->stream));
+    if (fused_bias)
+        HIP_TRY(lbsg::colsum_reduce(n->cpart, S, L.co, n->g + L.offB, n->stream));
+    else
+        HIP_TRY(lbsg::colsum_bf16(g, P, L.co, 256, n->cpart, n->g + L.offB, n->stream));
+    if (dz) {
+        if (dz_mask)
+            HIP_TRY(lbsg::conv3_fwd_masked(g, L.wf, dz_mask, dz, B, H, W, L.co, L.ci_pad, n->stream));
+        else
+            HIP_TRY(lbsg::conv3_fwd(g, L.wf, nullptr, dz, B, H, W, L.co, L.ci_pad, false, n->stream));
+    }
     return ok();
 }
 
@@ -196,12 +214,12 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
     for (int l = 0; l <= Lv - 2; ++l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w);
+        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w, false, lv.da);
         if (st != LBCH_OK) return st;
         // the weight gradient needs the concatenated input that the forward did not form
         const __bf16* up = (l == Lv - 2) ? n->lv[Lv - 1].e : n->lv[l + 1].d;
         HIP_TRY(lbsg::up2_concat(up, lv.e, lv.zc, B, h, w, C[l + 1], C[l], n->stream));
-        st = conv_back(n, dec_layer(l, 0), lv.zc, lv.da, lv.gda, lv.gzc, B, h, w);
+        st = conv_back(n, dec_layer(l, 0), lv.zc, lv.da, lv.gda, lv.gzc, B, h, w, true);
         if (st != LBCH_OK) return st;
         __bf16* du = (l + 1 < Lv - 1) ? n->lv[l + 1].gd : n->lv[Lv - 1].ge;
         HIP_TRY(lbsg::up2_concat_bwd(lv.gzc, du, lv.ge, B, h, w, C[l + 1], C[l], false, n->stream));
@@ -210,9 +228,9 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
     for (int l = Lv - 1; l >= 0; --l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.e, lv.ge, lv.ga, B, h, w);
+        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.e, lv.ge, lv.ga, B, h, w, false, lv.a);
         if (st != LBCH_OK) return st;
-        st = conv_back(n, n->layers[2 * l], lv.z, lv.a, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w);
+        st = conv_back(n, n->layers[2 * l], lv.z, lv.a, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w, true);
         if (st != LBCH_OK) return st;
         if (l > 0) HIP_TRY(lbsg::avgpool2_bwd(lv.gz, n->lv[l - 1].ge, B, h * 2, w * 2, C[l - 1], true, n->stream));
     }
@@ -307,7 +325,8 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
     n->out = A.get<float>(P0);
     n->xin1 = A.get<float>(P0);
     n->cond = A.get<float>(32);
-    n->cpart = A.get<float>(256 * 513);
+    n->cpart_elems = 256 * 513;
+    n->cpart = A.get<float>(n->cpart_elems);
     if (n->train) {
         n->g = A.get<float>(n->nparam);
         n->m = A.get<float>(n->nparam);
@@ -580,6 +599,28 @@ extern "C" lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, fl
     HIP_TRY(lbsg::pack_wflip(w, wf, co, ci, nullptr));
     HIP_TRY(lbsg::conv3_fwd(gb, wf, nullptr, xb, n, h, wd, co, ci, false, nullptr));
     HIP_TRY(lbsg::widen(xb, dx, P * ci, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_bgrad(const float* x, const float* dy, float* db, int32_t n, int32_t h,
+                                             int32_t wd, int32_t ci, int32_t co) {
+    if (!x || !dy || !db) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    const int ntiles = n * (h / 16) * (wd / 16);
+    const int splits = ntiles < 7 ? ntiles : 7;      // several splits, uneven tile counts per split
+    __bf16* xb = S.get<__bf16>(P * ci);
+    __bf16* gb = S.get<__bf16>(P * co);
+    float* part = S.get<float>((size_t)splits * co * 9 * ci);
+    float* bpart = S.get<float>((size_t)splits * co);
+    if (!xb || !gb || !part || !bpart) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
+    HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
+    HIP_TRY(lbsg::conv3_dw(xb, gb, part, splits, n, h, wd, ci, co, nullptr, bpart));
+    HIP_TRY(lbsg::colsum_reduce(bpart, splits, co, db, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }

@@ -75,7 +75,8 @@ def diag():
     from paper_2501_03759_amd import lbch
     L = lbch.lib()
     import ctypes
-    for name, nargs in (("lbsg_diag_conv3", 10), ("lbsg_diag_conv3_dgrad", 8), ("lbsg_diag_conv3_wgrad", 8)):
+    for name, nargs in (("lbsg_diag_conv3", 10), ("lbsg_diag_conv3_dgrad", 8), ("lbsg_diag_conv3_wgrad", 8),
+                        ("lbsg_diag_conv3_bgrad", 8)):
         fn = getattr(L, name)
         fn.restype = ctypes.c_int
         fn.argtypes = [ctypes.c_void_p] * (4 if name == "lbsg_diag_conv3" else 3) + [ctypes.c_int32] * (
@@ -207,18 +208,24 @@ def test_mfma_conv_gradients_exact_on_bf16_inputs(n, h, w, ci, co):
     x = bf16_round(rng.normal(size=(n, h, w, ci)))
     W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
     dy = bf16_round(rng.normal(size=(n, h, w, co)))
-    dx_ref, dw_ref, _ = unet.conv3_backward(x, W, dy)
+    dx_ref, dw_ref, db_ref = unet.conv3_backward(x, W, dy)
     xt = torch.tensor(x, dtype=torch.float32, device="cuda")
     wt = torch.tensor(W, dtype=torch.float32, device="cuda")
     gt = torch.tensor(dy, dtype=torch.float32, device="cuda")
     dxt = torch.empty((n, h, w, ci), dtype=torch.float32, device="cuda")
     dwt = torch.empty((co, ci, 3, 3), dtype=torch.float32, device="cuda")
+    dbt = torch.empty(co, dtype=torch.float32, device="cuda")
     assert L.lbsg_diag_conv3_dgrad(gt.data_ptr(), wt.data_ptr(), dxt.data_ptr(), n, h, w, ci, co) == 0
     assert L.lbsg_diag_conv3_wgrad(xt.data_ptr(), gt.data_ptr(), dwt.data_ptr(), n, h, w, ci, co) == 0
+    assert L.lbsg_diag_conv3_bgrad(xt.data_ptr(), gt.data_ptr(), dbt.data_ptr(), n, h, w, ci, co) == 0
     dx = dxt.cpu().numpy().astype(np.float64)
     dw = dwt.cpu().numpy().astype(np.float64)
+    db = dbt.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(dx - dx_ref) <= 2.0 ** -8 * np.abs(dx_ref) + 1e-5 * np.abs(dx_ref).max())
     assert np.abs(dw - dw_ref).max() <= 1e-5 * np.abs(dw_ref).max()
+    # FP32 sums of BF16 values: within n_terms * 2^-24 of the sum of magnitudes
+    bound = (n * h * w) * 2.0 ** -24 * np.abs(dy).sum(axis=(0, 1, 2))
+    assert np.all(np.abs(db - db_ref) <= bound)
 
 
 def test_forward_and_gradients_default_init():
