@@ -242,6 +242,19 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
         hb0 = hd.b[0];
     }
     bf16x4 prev[POOL ? CB : 1];   // row r - 1 of the 2x2 block (POOL)
+    // the mask of the lane's outputs, loaded at once (data-gradient use)
+    constexpr bool MASKABLE = !RELU && !HEAD && !POOL;
+    bf16x4 mk[MASKABLE ? 4 : 1][MASKABLE ? CB : 1];
+    if constexpr (MASKABLE) {
+        if (Mask) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    mk[r][c] = *reinterpret_cast<const bf16x4*>(
+                        Mask + (((size_t)n * H + ty0 + wave * 4 + r) * Wd + tx0 + l16) * Co + co0 + c * 16 + kb * 4);
+        }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int y = ty0 + wave * 4 + r, x = tx0 + l16;
@@ -257,10 +270,11 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
                 o[j] = (__bf16)v;
                 if constexpr (HEAD) part += hv[c][j] * (float)o[j];
             }
-            if (!RELU && !HEAD && !POOL && Mask) {
-                const bf16x4 m = *reinterpret_cast<const bf16x4*>(Mask + (((size_t)n * H + y) * Wd + x) * Co + co);
+            if constexpr (MASKABLE) {
+                if (Mask) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) o[j] = (float)m[j] > 0.f ? o[j] : (__bf16)0.f;
+                    for (int j = 0; j < 4; ++j) o[j] = (float)mk[r][c][j] > 0.f ? o[j] : (__bf16)0.f;
+                }
             }
             if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
             if constexpr (POOL) {
