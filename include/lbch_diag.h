@@ -60,6 +60,12 @@ lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, float* dx, in
 lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, float* dw, int32_t n, int32_t h, int32_t wd,
                                   int32_t ci, int32_t co);
 
+/* dw as lbsg_diag_conv3_wgrad for the input [nearest 2x upsampling of
+ * u[N][H/2][W/2][Cu], sk[N][H][W][Cs]] (the decoder's first convolution),
+ * read by the kernel from its two sources; dw is [Co][Cu + Cs][3][3]. */
+lbch_status lbsg_diag_conv3_wgrad_upcat(const float* u, const float* sk, const float* dy, float* dw, int32_t n,
+                                        int32_t h, int32_t wd, int32_t cu, int32_t cs, int32_t co);
+
 /* db[Co] = sum over pixels of dy[p][co] (FP32), as the weight-gradient kernel
  * forms it beside dw (split partials, fixed-order reduction). */
 lbch_status lbsg_diag_conv3_bgrad(const float* x, const float* dy, float* db, int32_t n, int32_t h, int32_t wd,

@@ -30,6 +30,10 @@ hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* b
 // bias gradient's split partials, reduced by colsum_reduce.
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
                     hipStream_t s, float* bpart = nullptr);
+// conv3_dw of the channel concatenation [nearest 2x upsampling of U (Cu
+// channels, H/2 x Wd/2), Sk (Cs channels, H x Wd)] without forming it.
+hipError_t conv3_dw_upcat(const __bf16* U, const __bf16* Sk, const __bf16* dY, float* part, int S, int N, int H, int Wd,
+                          int Cu, int Cs, int Co, hipStream_t s, float* bpart = nullptr);
 hipError_t colsum_reduce(const float* part, int S, int C, float* out, hipStream_t s);
 hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s);
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s);

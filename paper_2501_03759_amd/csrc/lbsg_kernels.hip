@@ -320,6 +320,9 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 // partials bpart[s][co] = sum over the split's pixels of dY[p][co]: each thread
 // always stages the same 8 channels and sums them in tile order, then a fixed
 // order over the threads of a channel (reduced over splits by colsum_reduce_k).
+// UPCAT: X is the channel concatenation [nearest 2x upsampling of X (Cu
+// channels, H/2 x Wd/2), X2 (Ci - Cu channels)], read from its two sources;
+// a 16-channel ci block lies in one of them (Cu is a multiple of 32).
 // ---------------------------------------------------------------------------
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
@@ -332,10 +335,11 @@ __device__ __forceinline__ bf16x8 cat8(const bf16x4& a, const bf16x4& b) {
     return bf16x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
 }
 
-template <int TCO>
+template <int TCO, bool UPCAT>
 __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__ X, const __bf16* __restrict__ dY,
                                                       float* __restrict__ part, int N, int H, int Wd, int Ci, int Co,
-                                                      int S, float* __restrict__ bpart) {
+                                                      int S, float* __restrict__ bpart,
+                                                      const __bf16* __restrict__ X2, int Cu) {
     constexpr int NT = TCO * 4;          // 64 threads (one wave) per 16 output channels
     // LDS strides (bf16) of one dY pixel and one X halo pixel, chosen by
     // measurement (SQ_LDS_BANK_CONFLICT): the 16-byte stores are conflict-free
@@ -378,7 +382,14 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
             if (q < NXQ) {
                 const int hp = q >> 1, ch = q & 1;
                 const int y = wrap(ty0 - 1 + hp / 18, H), x = wrap(tx0 - 1 + hp % 18, Wd);
-                rx[i] = *reinterpret_cast<const bf16x8*>(X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8);
+                const __bf16* src;
+                if constexpr (UPCAT) {
+                    src = ci0 < Cu ? X + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + ci0 + ch * 8
+                                   : X2 + (((size_t)n * H + y) * Wd + x) * (Ci - Cu) + (ci0 - Cu) + ch * 8;
+                } else {
+                    src = X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8;
+                }
+                rx[i] = *reinterpret_cast<const bf16x8*>(src);
             }
         }
     };
@@ -937,17 +948,31 @@ hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* b
     return hipGetLastError();
 }
 
-hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
-                    hipStream_t s, float* bpart) {
+namespace {
+template <bool UPCAT>
+hipError_t conv3_dw_any(const __bf16* X, const __bf16* X2, int Cu, const __bf16* dY, float* part, int S, int N, int H,
+                        int Wd, int Ci, int Co, hipStream_t s, float* bpart) {
     if (H % 16 || Wd % 16 || Ci % 16 || Co % 32 || S < 1 || S > N * (H / 16) * (Wd / 16)) return hipErrorInvalidValue;
     if (Co % 64 == 0) {
         dim3 grid(S, Co / 64, Ci / 16);
-        conv3_dw_k<64><<<grid, 256, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart);
+        conv3_dw_k<64, UPCAT><<<grid, 256, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart, X2, Cu);
     } else {
         dim3 grid(S, Co / 32, Ci / 16);
-        conv3_dw_k<32><<<grid, 128, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart);
+        conv3_dw_k<32, UPCAT><<<grid, 128, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart, X2, Cu);
     }
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
+                    hipStream_t s, float* bpart) {
+    return conv3_dw_any<false>(X, nullptr, 0, dY, part, S, N, H, Wd, Ci, Co, s, bpart);
+}
+
+hipError_t conv3_dw_upcat(const __bf16* U, const __bf16* Sk, const __bf16* dY, float* part, int S, int N, int H, int Wd,
+                          int Cu, int Cs, int Co, hipStream_t s, float* bpart) {
+    if (Cu < 32 || Cu % 32 || Cs < 16 || Cs % 16) return hipErrorInvalidValue;
+    return conv3_dw_any<true>(U, Sk, Cu, dY, part, S, N, H, Wd, Cu + Cs, Co, s, bpart);
 }
 
 hipError_t colsum_reduce(const float* part, int S, int C, float* out, hipStream_t s) {

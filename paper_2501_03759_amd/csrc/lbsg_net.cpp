@@ -35,7 +35,7 @@ struct Layer {
 struct Level {
     // forward activations (bf16, channels-last)
     __bf16 *z = nullptr, *a = nullptr, *e = nullptr;      // encoder block input, mid, output
-    __bf16 *zc = nullptr, *da = nullptr, *d = nullptr;    // decoder block input (concat), mid, output
+    __bf16 *da = nullptr, *d = nullptr;                   // decoder block mid, output
     // gradients
     __bf16 *gz = nullptr, *ga = nullptr, *ge = nullptr, *gzc = nullptr, *gda = nullptr, *gd = nullptr;
 };
@@ -112,9 +112,11 @@ lbch_status repack(lbsg_net* n) {
 // gradient of one conv layer: gout = dLoss/d(post-ReLU output y), input z.
 // gout_masked: gout already carries the ReLU mask of y.  dz_mask (nullable):
 // the data gradient dz is written masked by dz_mask > 0 (the layer whose
-// post-ReLU output is z consumes it as its gout_masked).
+// post-ReLU output is z consumes it as its gout_masked).  z_up (nullable):
+// the layer's input is [nearest 2x upsampling of z_up (cu channels), z].
 lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16* y, const __bf16* gout, __bf16* dz,
-                      int B, int H, int W, bool gout_masked = false, const __bf16* dz_mask = nullptr) {
+                      int B, int H, int W, bool gout_masked = false, const __bf16* dz_mask = nullptr,
+                      const __bf16* z_up = nullptr, int cu = 0) {
     const long long P = (long long)B * H * W;
     const __bf16* g = gout;
     if (!gout_masked) {
@@ -129,7 +131,11 @@ lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16
     while ((long long)S * L.co * 9 * L.ci_pad > n->wpart_elems && S > 1) S /= 2;
     // the bias gradient's split partials come from the weight-gradient kernel when they fit
     const bool fused_bias = (long long)S * L.co <= n->cpart_elems;
-    HIP_TRY(lbsg::conv3_dw(z, g, n->wpart, S, B, H, W, L.ci_pad, L.co, n->stream, fused_bias ? n->cpart : nullptr));
+    float* bpart = fused_bias ? n->cpart : nullptr;
+    if (z_up)
+        HIP_TRY(lbsg::conv3_dw_upcat(z_up, z, g, n->wpart, S, B, H, W, cu, L.ci_pad - cu, L.co, n->stream, bpart));
+    else
+        HIP_TRY(lbsg::conv3_dw(z, g, n->wpart, S, B, H, W, L.ci_pad, L.co, n->stream, bpart));
     HIP_TRY(lbsg::wgrad_reduce(n->wpart, n->g + L.offW, S, L.co, L.ci_pad, L.ci_real, n->stream));
     if (fused_bias)
         HIP_TRY(lbsg::colsum_reduce(n->cpart, S, L.co, n->g + L.offB, n->stream));
@@ -216,10 +222,9 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
         Level& lv = n->lv[l];
         lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w, false, lv.da);
         if (st != LBCH_OK) return st;
-        // the weight gradient needs the concatenated input that the forward did not form
+        // the weight gradient reads the concatenated input from its two sources
         const __bf16* up = (l == Lv - 2) ? n->lv[Lv - 1].e : n->lv[l + 1].d;
-        HIP_TRY(lbsg::up2_concat(up, lv.e, lv.zc, B, h, w, C[l + 1], C[l], n->stream));
-        st = conv_back(n, dec_layer(l, 0), lv.zc, lv.da, lv.gda, lv.gzc, B, h, w, true);
+        st = conv_back(n, dec_layer(l, 0), lv.e, lv.da, lv.gda, lv.gzc, B, h, w, true, nullptr, up, C[l + 1]);
         if (st != LBCH_OK) return st;
         __bf16* du = (l + 1 < Lv - 1) ? n->lv[l + 1].gd : n->lv[Lv - 1].ge;
         HIP_TRY(lbsg::up2_concat_bwd(lv.gzc, du, lv.ge, B, h, w, C[l + 1], C[l], false, n->stream));
@@ -301,7 +306,6 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
         lv.a = A.get<__bf16>(P * C[l]);
         lv.e = A.get<__bf16>(P * C[l]);
         if (l < Lv - 1) {
-            if (n->train) lv.zc = A.get<__bf16>(P * (C[l + 1] + C[l]));
             lv.da = A.get<__bf16>(P * C[l]);
             lv.d = A.get<__bf16>(P * C[l]);
         }
@@ -599,6 +603,32 @@ extern "C" lbch_status lbsg_diag_conv3_dgrad(const float* dy, const float* w, fl
     HIP_TRY(lbsg::pack_wflip(w, wf, co, ci, nullptr));
     HIP_TRY(lbsg::conv3_fwd(gb, wf, nullptr, xb, n, h, wd, co, ci, false, nullptr));
     HIP_TRY(lbsg::widen(xb, dx, P * ci, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_wgrad_upcat(const float* u, const float* sk, const float* dy, float* dw,
+                                                   int32_t n, int32_t h, int32_t wd, int32_t cu, int32_t cs,
+                                                   int32_t co) {
+    if (!u || !sk || !dy || !dw) return fail(LBCH_E_INVALID, "NULL argument");
+    if (cu < 32 || cu % 32) return fail(LBCH_E_INVALID, "cu = %d must be a positive multiple of 32", cu);
+    lbch_status st = diag_shape(n, h, wd, cs, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    const int ci = cu + cs;
+    const int ntiles = n * (h / 16) * (wd / 16);
+    const int splits = ntiles < 7 ? ntiles : 7;
+    __bf16* ub = S.get<__bf16>(P / 4 * cu);
+    __bf16* sb = S.get<__bf16>(P * cs);
+    __bf16* gb = S.get<__bf16>(P * co);
+    float* part = S.get<float>((size_t)splits * co * 9 * ci);
+    if (!ub || !sb || !gb || !part) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(u, ub, P / 4, cu, cu, nullptr));
+    HIP_TRY(lbsg::pack_input(sk, sb, P, cs, cs, nullptr));
+    HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
+    HIP_TRY(lbsg::conv3_dw_upcat(ub, sb, gb, part, splits, n, h, wd, cu, cs, co, nullptr));
+    HIP_TRY(lbsg::wgrad_reduce(part, dw, splits, co, ci, ci, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }

@@ -228,6 +228,29 @@ def test_mfma_conv_gradients_exact_on_bf16_inputs(n, h, w, ci, co):
     assert np.all(np.abs(db - db_ref) <= bound)
 
 
+@pytest.mark.parametrize("n,h,w,cu,cs,co", [(2, 32, 48, 64, 32, 32), (3, 48, 32, 32, 64, 64), (1, 64, 64, 128, 64, 128)])
+def test_mfma_weight_gradient_of_upsampled_concat(n, h, w, cu, cs, co):
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_wgrad_upcat
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 6
+    rng = np.random.default_rng(5 * cu + cs + co)
+    u = bf16_round(rng.normal(size=(n, h // 2, w // 2, cu)))
+    sk = bf16_round(rng.normal(size=(n, h, w, cs)))
+    dy = bf16_round(rng.normal(size=(n, h, w, co)))
+    W = np.zeros((co, cu + cs, 3, 3))
+    _, dw_ref, _ = unet.conv3_backward(np.concatenate([unet.up2(u), sk], axis=3), W, dy)
+    dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    ut, st, gt = dev(u), dev(sk), dev(dy)
+    dwt = torch.empty((co, cu + cs, 3, 3), dtype=torch.float32, device="cuda")
+    print(f"case wgrad upcat {(n, h, w, cu, cs, co)}", flush=True)
+    assert fn(ut.data_ptr(), st.data_ptr(), gt.data_ptr(), dwt.data_ptr(), n, h, w, cu, cs, co) == 0
+    dw = dwt.cpu().numpy().astype(np.float64)
+    assert np.abs(dw - dw_ref).max() <= 1e-5 * np.abs(dw_ref).max()
+
+
 def test_forward_and_gradients_default_init():
     # Whole-network composition (pool / upsample / concat adjoints, layer order) against the
     # float64 reference.  Each operator is exact on BF16 inputs (tests above); here BF16
