@@ -6,6 +6,19 @@
 
 namespace lbsg {
 
+// Segments of the one-launch weight packing (pack_all): per segment the
+// FP32 master W[co][ci][3][3], its BF16 output, and the layout: flip 0 ->
+// out[co][tap][cip] (zero padded ci), flip 1 -> out[ci][8 - tap][co].
+constexpr int kPackMaxSeg = 64;
+struct PackAll {
+    int nseg;
+    long long end[kPackMaxSeg];   // cumulative element counts
+    const float* W[kPackMaxSeg];
+    __bf16* out[kPackMaxSeg];
+    int co[kPackMaxSeg], ci[kPackMaxSeg], cip[kPackMaxSeg], flip[kPackMaxSeg];
+};
+hipError_t pack_all(const PackAll& t, hipStream_t s);
+
 hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd, int Ci,
                      int Co, bool relu, hipStream_t s);
 // conv3_fwd of the channel concatenation [nearest 2x upsampling of U (Cu

@@ -3,6 +3,7 @@
 // (v_mfma_f32_16x16x32_bf16), NHWC layout with channels padded to 32.
 #include "lbsg_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace lbsg {
@@ -575,6 +576,26 @@ __global__ void pack_wflip_k(const float* __restrict__ W, __bf16* __restrict__ W
     }
 }
 
+// Every layer's packing in one launch: grid row s (blockIdx.y) writes out[s]
+// either as pack_w_k (flip 0) or as pack_wflip_k (flip 1) from W[s]; end[]
+// holds the cumulative element counts.
+__global__ void pack_all_k(const PackAll t) {
+    const int sg = blockIdx.y;
+    const long long n = t.end[sg] - (sg ? t.end[sg - 1] : 0);
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
+         j += (long long)gridDim.x * blockDim.x) {
+        const int Co = t.co[sg], Ci = t.ci[sg];
+        if (!t.flip[sg]) {
+            const int Cip = t.cip[sg];
+            const int ci = (int)(j % Cip), tap = (int)((j / Cip) % 9), co = (int)(j / (9LL * Cip));
+            t.out[sg][j] = (__bf16)(ci < Ci ? t.W[sg][((size_t)co * Ci + ci) * 9 + tap] : 0.f);
+        } else {
+            const int co = (int)(j % Co), tp = (int)((j / Co) % 9), ci = (int)(j / (9LL * Co));
+            t.out[sg][j] = (__bf16)t.W[sg][((size_t)co * Ci + ci) * 9 + (8 - tp)];
+        }
+    }
+}
+
 // ------------------------------------------------------------- elementwise
 // Every activation tensor is [pixels][C] BF16 with C a multiple of 8: these
 // kernels move 8 channels (16 bytes) per thread and index by chunk.
@@ -1005,6 +1026,14 @@ hipError_t widen(const __bf16* a, float* b, long long n, hipStream_t s) {
 
 hipError_t pack_w(const float* W, __bf16* Wt, int Co, int Ci, int Cip, hipStream_t s) {
     pack_w_k<<<grid_for((long long)Co * 9 * Cip), 256, 0, s>>>(W, Wt, Co, Ci, Cip);
+    return hipGetLastError();
+}
+
+hipError_t pack_all(const PackAll& t, hipStream_t s) {
+    if (t.nseg < 1 || t.nseg > kPackMaxSeg) return hipErrorInvalidValue;
+    long long largest = 0;
+    for (int i = 0; i < t.nseg; ++i) largest = std::max(largest, t.end[i] - (i ? t.end[i - 1] : 0));
+    pack_all_k<<<dim3(std::min(grid_for(largest), 1024), t.nseg), 256, 0, s>>>(t);
     return hipGetLastError();
 }
 

@@ -99,13 +99,29 @@ void release(lbsg_net* n) {
     n->allocs.clear();
 }
 
+// BF16 copies of every 3x3 layer's weights (and the flipped copies used by the
+// data gradient) from the FP32 masters, in one launch
 lbch_status repack(lbsg_net* n) {
-    for (size_t k = 0; k < n->layers.size(); ++k) {
-        Layer& L = n->layers[k];
+    lbsg::PackAll t{};
+    long long end = 0;
+    auto add = [&](const Layer& L, __bf16* out, int flip) {
+        const int sg = t.nseg++;
+        end += flip ? (long long)L.ci_real * 9 * L.co : (long long)L.co * 9 * L.ci_pad;
+        t.end[sg] = end;
+        t.W[sg] = n->w + L.offW;
+        t.out[sg] = out;
+        t.co[sg] = L.co;
+        t.ci[sg] = L.ci_real;
+        t.cip[sg] = L.ci_pad;
+        t.flip[sg] = flip;
+    };
+    for (const Layer& L : n->layers) {
         if (L.k != 3) continue;
-        HIP_TRY(lbsg::pack_w(n->w + L.offW, L.wt, L.co, L.ci_real, L.ci_pad, n->stream));
-        if (L.wf) HIP_TRY(lbsg::pack_wflip(n->w + L.offW, L.wf, L.co, L.ci_real, n->stream));
+        if (t.nseg + 2 > lbsg::kPackMaxSeg) return fail(LBCH_E_INVALID, "too many layers to pack");
+        add(L, L.wt, 0);
+        if (L.wf) add(L, L.wf, 1);
     }
+    HIP_TRY(lbsg::pack_all(t, n->stream));
     return ok();
 }
 
