@@ -30,7 +30,7 @@ hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, 
 hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mask, __bf16* Y, int N, int H, int Wd,
                             int Ci, int Co, hipStream_t s);
 // ReLU conv3_fwd writing Y and, to Yp (N x H/2 x Wd/2 x Co), its 2x2
-// average with the arithmetic of avgpool2 (the encoder's second convolution).
+// average (the encoder's second convolution and the pooling after it).
 hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, __bf16* Yp, int N, int H,
                                int Wd, int Ci, int Co, hipStream_t s);
 // ReLU conv3_fwd (Co = 32 or 64, one workgroup per 16 x 16 pixel tile) with
@@ -58,10 +58,7 @@ hipError_t pack_wflip(const float* W, __bf16* Wf, int Co, int Ci, hipStream_t s)
 hipError_t pack_input(const float* x, __bf16* out, long long P, int cin, int cpad, hipStream_t s);
 hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16* out, float* xin, long long P, int cpad,
                          hipStream_t s);
-hipError_t avgpool2(const __bf16* x, __bf16* y, int N, int H, int Wd, int C, hipStream_t s);
 hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s);
-hipError_t up2_concat(const __bf16* u, const __bf16* sk, __bf16* z, int N, int H, int Wd, int Cu, int Cs,
-                      hipStream_t s);
 hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
                           bool accumulate, hipStream_t s);
 hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s);

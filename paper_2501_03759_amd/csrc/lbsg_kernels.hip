@@ -71,9 +71,10 @@ __device__ __forceinline__ void interleave_ds_mfma() {
 // HEAD (Co = TC, one workgroup per pixel tile): the 1x1 output head is applied
 // in the epilogue, out[p] = xin[p][0] + scale (b + sum_c w_c y[p][c]) over the
 // BF16-rounded activations; Y (nullable) still receives them.
-// POOL: Y as usual, and Yp (H/2 x Wd/2) receives its 2x2 average with the
-// arithmetic of avgpool2_k: the rows of a 2x2 block belong to one wave (rows
-// r, r + 1), the columns to lanes l16 and l16 ^ 1.
+// POOL: Y as usual, and Yp (H/2 x Wd/2) receives its 2x2 average of the BF16
+// outputs, bf16(0.25 ((a + b) + (c + d))) in FP32 with a, b the upper and c, d
+// the lower row of the block: the rows belong to one wave (rows r, r + 1),
+// the columns to lanes l16 and l16 ^ 1.
 // Mask (nullable, same layout as Y): Y = Mask > 0 ? y : 0 elementwise, the
 // ReLU backward of relu_bwd_k applied to the BF16 result (for data gradients
 // whose next consumer masks them by the previous layer's activation).
@@ -641,30 +642,6 @@ __global__ void pack_phi_cond_k(const float* __restrict__ phi, const float* __re
     }
 }
 
-__global__ void avgpool2_k(const __bf16* __restrict__ x, __bf16* __restrict__ y, int N, int H, int Wd, int C) {
-    const int Ho = H / 2, Wo = Wd / 2, Q = C / 8;
-    const long long total = (long long)N * Ho * Wo * Q;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long po = i / Q;
-        const int c0 = (int)(i - po * Q) * 8;
-        const int xo = (int)(po % Wo);
-        const long long r = po / Wo;
-        const int yo = (int)(r % Ho);
-        const long long nn = r / Ho;
-        const __bf16* b0 = x + ((nn * H + 2 * yo) * Wd + 2 * xo) * C + c0;
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(b0);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(b0 + C);
-        const bf16x8 c = *reinterpret_cast<const bf16x8*>(b0 + (long long)Wd * C);
-        const bf16x8 d = *reinterpret_cast<const bf16x8*>(b0 + (long long)Wd * C + C);
-        bf16x8 o;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            o[k] = (__bf16)(0.25f * (((float)a[k] + (float)b[k]) + ((float)c[k] + (float)d[k])));
-        *reinterpret_cast<bf16x8*>(y + po * C + c0) = o;
-    }
-}
-
 // dx (N,H,W,C) (+)= avgpool2 adjoint of dy (N,H/2,W/2,C)
 __global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict__ dx, int N, int H, int Wd, int C,
                                int accumulate) {
@@ -689,29 +666,6 @@ __global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict
             for (int k = 0; k < 8; ++k) o[k] = (__bf16)(0.25f * (float)g[k]);
         }
         *reinterpret_cast<bf16x8*>(dx + p * C + c0) = o;
-    }
-}
-
-// z[..., 0:Cu] = up2(u), z[..., Cu:Cu+Cs] = s     (u: N,H/2,W/2,Cu; s, z: N,H,W)
-__global__ void up2_concat_k(const __bf16* __restrict__ u, const __bf16* __restrict__ sk, __bf16* __restrict__ z,
-                             int N, int H, int Wd, int Cu, int Cs) {
-    const int C = Cu + Cs, Q = C / 8, Qu = Cu / 8;
-    const long long total = (long long)N * H * Wd * Q;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long p = i / Q;
-        const int q = (int)(i - p * Q);
-        bf16x8 v;
-        if (q < Qu) {
-            const int x = (int)(p % Wd);
-            const long long r = p / Wd;
-            const int y = (int)(r % H);
-            const long long nn = r / H;
-            v = *reinterpret_cast<const bf16x8*>(u + ((nn * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + q * 8);
-        } else {
-            v = *reinterpret_cast<const bf16x8*>(sk + p * Cs + (q - Qu) * 8);
-        }
-        *reinterpret_cast<bf16x8*>(z + p * C + q * 8) = v;
     }
 }
 
@@ -1055,22 +1009,9 @@ hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16*
     return hipGetLastError();
 }
 
-hipError_t avgpool2(const __bf16* x, __bf16* y, int N, int H, int Wd, int C, hipStream_t s) {
-    if (C % 8 != 0) return hipErrorInvalidValue;
-    avgpool2_k<<<grid_for((long long)N * H * Wd * C / 32), 256, 0, s>>>(x, y, N, H, Wd, C);
-    return hipGetLastError();
-}
-
 hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s) {
     if (C % 8 != 0) return hipErrorInvalidValue;
     avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C / 8), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t up2_concat(const __bf16* u, const __bf16* sk, __bf16* z, int N, int H, int Wd, int Cu, int Cs,
-                      hipStream_t s) {
-    if (Cu % 8 != 0 || Cs % 8 != 0) return hipErrorInvalidValue;
-    up2_concat_k<<<grid_for((long long)N * H * Wd * (Cu + Cs) / 8), 256, 0, s>>>(u, sk, z, N, H, Wd, Cu, Cs);
     return hipGetLastError();
 }
 
