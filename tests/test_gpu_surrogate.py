@@ -269,6 +269,14 @@ def test_forward_and_gradients_default_init():
         assert np.median(per_co) < 0.1 and rel(a, b) < 0.25, (name, np.median(per_co), rel(a, b))
 
 
+def test_forward_with_wide_first_level():
+    # 128 channels at the first level: the output head runs as its own kernel (the fused
+    # epilogue covers 32 or 64), and the pooled / upsampled paths carry 128 channels
+    y_gpu, y_ref, g_gpu, g_ref = run_both(2, (128, 64), 32, bias_shift=0.0, seed=4)
+    assert rel(y_gpu, y_ref) < 3e-2
+    assert rel(g_gpu["head.W"], g_ref["head.W"]) < 2e-2
+
+
 def test_untrained_net_is_identity_and_training_lowers_loss():
     import torch
     from paper_2501_03759_amd import lbsg
