@@ -198,6 +198,15 @@ lbch_status lbch_init_device(lbch_sim* sim, const void* phi0_dev, int32_t dtype,
  * waiting.  Before init -> LBCH_E_STATE. */
 lbch_status lbch_step(lbch_sim* sim, int64_t nsteps);
 
+/* Two time steps in one two-step launch, storing the populations
+ * f_{n+2} + ext (f_{n+2} - f_n) elementwise instead of f_{n+2}: a projective
+ * step of the populations (the correction phase of lbch_hybrid_advance uses
+ * it with ext = inner_jump / 2) folded into the launch that reads f_n.  The
+ * step count advances by 2.  Needs two steps per launch
+ * (lbch_set_time_blocking 2) and D2Q9, else LBCH_E_UNSUPPORTED; non-finite
+ * ext -> LBCH_E_INVALID; before init -> LBCH_E_STATE.  Stream-ordered. */
+lbch_status lbch_step_extrapolated(lbch_sim* sim, double ext);
+
 /* Steps taken since the last init / load. */
 lbch_status lbch_get_step(const lbch_sim* sim, int64_t* step);
 

@@ -555,6 +555,20 @@ extern "C" lbch_status lbch_step(lbch_sim* s, int64_t nsteps) {
     return ok();
 }
 
+extern "C" lbch_status lbch_step_extrapolated(lbch_sim* s, double ext) {
+    lbch_status st = check_init(s);
+    if (st != LBCH_OK) return st;
+    if (!std::isfinite(ext)) return fail(LBCH_E_INVALID, "ext = %g is not finite", ext);
+    if (s->d3) return fail(LBCH_E_UNSUPPORTED, "the extrapolating step is built for D2Q9");
+    if (s->t.depth != 2) return fail(LBCH_E_UNSUPPORTED, "the extrapolating step needs two steps per launch");
+    hipError_t e = launch_step2_extrap(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, s->t, coef_ptr(s), ext,
+                                       s->stream);
+    if (e != hipSuccess) return fail(LBCH_E_DEVICE, "step launch failed: %s", hipGetErrorString(e));
+    s->cur ^= 1;
+    s->step += 2;
+    return ok();
+}
+
 extern "C" lbch_status lbch_get_step(const lbch_sim* s, int64_t* step) {
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;

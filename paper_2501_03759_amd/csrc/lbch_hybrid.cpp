@@ -135,11 +135,20 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
         if (o->inner_steps > 0 && o->inner_jump > 0) {
             // the difference spans the last launch: two steps when the plain steps run two per launch
             const int span = (sim->t.depth == 2 && o->inner_steps % 2 == 0) ? 2 : 1;
+            // with two steps per launch the extrapolation is stored by the last launch itself
+            const bool fused = span == 2 && !sim->d3;
             while (done + 2LL * o->inner_steps + o->inner_jump <= n) {
-                lbch_status ls = lbch_step(sim, o->inner_steps);
-                if (ls != LBCH_OK) return ls;
-                HIP_TRY(launch_extrap_pop(sim->precision, sim->f[sim->cur], sim->f[sim->cur ^ 1],
-                                          (double)o->inner_jump / span, (long long)pop_elems, s));
+                if (fused) {
+                    lbch_status ls = lbch_step(sim, o->inner_steps - 2);
+                    if (ls != LBCH_OK) return ls;
+                    ls = lbch_step_extrapolated(sim, (double)o->inner_jump / span);
+                    if (ls != LBCH_OK) return ls;
+                } else {
+                    lbch_status ls = lbch_step(sim, o->inner_steps);
+                    if (ls != LBCH_OK) return ls;
+                    HIP_TRY(launch_extrap_pop(sim->precision, sim->f[sim->cur], sim->f[sim->cur ^ 1],
+                                              (double)o->inner_jump / span, (long long)pop_elems, s));
+                }
                 sim->step += o->inner_jump;
                 done += o->inner_steps + o->inner_jump;
             }

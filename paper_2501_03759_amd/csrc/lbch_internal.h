@@ -54,6 +54,10 @@ enum { REG_NONE = 0, REG_LINEAR = 1, REG_WILLMORE = 2 };
 // launch status.
 hipError_t launch_step(int precision, const void* fin, void* fout, const Grid& g, const Tiling& t,
                        const void* coef, hipStream_t s);
+// One two-step launch storing f_{n+2} + ext (f_{n+2} - f_n) (fin holds f_n);
+// t must be a two-step tiling.
+hipError_t launch_step2_extrap(int precision, const void* fin, void* fout, const Grid& g, const Tiling& t,
+                               const void* coef, double ext, hipStream_t s);
 hipError_t launch_init(int precision, const void* phi0, int phi_dtype, void* fout, const Grid& g,
                        const void* coef, unsigned* bad_count, hipStream_t s);
 // phi of the current state (float64 math) -> optional dense output + partial sums

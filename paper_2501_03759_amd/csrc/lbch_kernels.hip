@@ -489,11 +489,15 @@ struct Pass2Lds {
     T phi[3][NT], qx[3][NT], qy[3][NT], w[3][NT], mb[3][NT];
 };
 
-template <typename T, int NT, bool UNIT, bool STAGED>
+// EXTRAP: the stored state is f_{n+2} + ext (f_{n+2} - f_n) elementwise, f_n
+// being this launch's input at the same element (a projective step of the
+// populations fused into the store).
+template <typename T, int NT, bool UNIT, bool STAGED, bool EXTRAP = false>
 __device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __restrict__ fout, const Grid& g,
                                              const int x0, const int wlen, const int y0, const int hlen,
                                              const StepCoef<T>& c, Pass2Lds<T, NT>& L1, Pass2Lds<T, NT>& L2,
-                                             T (*s_13)[2][NT], T (*s_56)[2][NT], T (*s_78)[NT], T* s_f) {
+                                             T (*s_13)[2][NT], T (*s_56)[2][NT], T (*s_78)[NT], T* s_f,
+                                             const T ext = T(0)) {
     constexpr int U = 4;
     using Loader = RowLoader<T, NT, STAGED>;
     const int nx = g.nx, ny = g.ny, pitch = g.pitch;
@@ -591,8 +595,17 @@ __device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __res
                                          mua2[(k + U - 2) % U], o);
                     const int rd = y0 - 14 + j;
                     T* __restrict__ q = fout + ((long long)rd * pitch + xc);
+                    if constexpr (EXTRAP) {
+                        const T* __restrict__ pv = fin + ((long long)rd * pitch + xc);
+                        T prev[9];
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i];
+                        for (int i = 0; i < 9; ++i) prev[i] = pv[i * g.plane];
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i] + ext * (o[i] - prev[i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i];
+                    }
                 }
             }
         }
@@ -638,6 +651,28 @@ __global__ __launch_bounds__(NT) void step2_fused(const T* __restrict__ fin, T* 
     const int y0 = chunk * tl.hc;
     sweep_strip2<T, NT, UNIT, STAGED>(fin, fout, g, x0, min(tl.W, g.nx - x0), y0, min(tl.hc, g.ny - y0), c, L1, L2,
                                       s_13, s_56, s_78, s_f);
+}
+
+// Two steps per launch with the projective extrapolation of the populations
+// in the store: fout = f_{n+2} + ext (f_{n+2} - f_n), fin holding f_n.
+template <typename T, int NT, bool UNIT, bool STAGED>
+__global__ __launch_bounds__(NT) void step2_extrap(const T* __restrict__ fin, T* __restrict__ fout,
+                                                   const Grid g, const Tiling tl, const StepCoef<T> c, const T ext) {
+    __shared__ Pass2Lds<T, NT> L1;
+    __shared__ Pass2Lds<T, NT> L2;
+    __shared__ T s_13[2][2][NT];
+    __shared__ T s_56[3][2][NT];
+    __shared__ T s_78[2][NT];
+    __shared__ __align__(16) T s_f[StageLds<T, NT, STAGED>::kF];
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * tl.per_xcd + (bid >> 3);
+    if (tile >= tl.ntiles) return;
+    const int strip = tile % tl.strips;
+    const int chunk = tile / tl.strips;
+    const int x0 = strip * tl.W;
+    const int y0 = chunk * tl.hc;
+    sweep_strip2<T, NT, UNIT, STAGED, true>(fin, fout, g, x0, min(tl.W, g.nx - x0), y0, min(tl.hc, g.ny - y0), c,
+                                            L1, L2, s_13, s_56, s_78, s_f, ext);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,6 +998,47 @@ static hipError_t launch_step_t(const T* fin, T* fout, const Grid& g, const Tili
     }
     return c.unit ? launch_step_v<T, true, false>(fin, fout, g, t, c, s)
                   : launch_step_v<T, false, false>(fin, fout, g, t, c, s);
+}
+
+template <typename T, bool UNIT, bool STAGED>
+static hipError_t launch_step2_extrap_v(const T* fin, T* fout, const Grid& g, const Tiling& t, const StepCoef<T>& c,
+                                        T ext, hipStream_t s) {
+    if (t.depth != 2) return hipErrorInvalidValue;
+    dim3 grid(t.nblocks);
+    switch (t.nt) {
+        case 128: step2_extrap<T, 128, UNIT, STAGED><<<grid, 128, 0, s>>>(fin, fout, g, t, c, ext); break;
+        case 256: step2_extrap<T, 256, UNIT, STAGED><<<grid, 256, 0, s>>>(fin, fout, g, t, c, ext); break;
+        case 512:
+            if constexpr (sizeof(T) == 4) {
+                step2_extrap<T, 512, UNIT, STAGED><<<grid, 512, 0, s>>>(fin, fout, g, t, c, ext);
+                break;
+            } else {
+                return hipErrorInvalidValue;
+            }
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_step2_extrap_t(const T* fin, T* fout, const Grid& g, const Tiling& t, const StepCoef<T>& c,
+                                        T ext, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (g.nx % 4 == 0 && t.staged)
+            return c.unit ? launch_step2_extrap_v<T, true, true>(fin, fout, g, t, c, ext, s)
+                          : launch_step2_extrap_v<T, false, true>(fin, fout, g, t, c, ext, s);
+    }
+    return c.unit ? launch_step2_extrap_v<T, true, false>(fin, fout, g, t, c, ext, s)
+                  : launch_step2_extrap_v<T, false, false>(fin, fout, g, t, c, ext, s);
+}
+
+hipError_t launch_step2_extrap(int precision, const void* fin, void* fout, const Grid& g, const Tiling& t,
+                               const void* coef, double ext, hipStream_t s) {
+    if (precision == 0)
+        return launch_step2_extrap_t<double>((const double*)fin, (double*)fout, g, t, *(const StepCoef<double>*)coef,
+                                             ext, s);
+    return launch_step2_extrap_t<float>((const float*)fin, (float*)fout, g, t, *(const StepCoef<float>*)coef,
+                                        (float)ext, s);
 }
 
 hipError_t launch_step(int precision, const void* fin, void* fout, const Grid& g, const Tiling& t, const void* coef,

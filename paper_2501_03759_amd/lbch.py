@@ -74,6 +74,7 @@ _SIGNATURES = {
     "lbch_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]),
     "lbch_init_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
     "lbch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "lbch_step_extrapolated": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "lbch_get_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "lbch_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "lbch_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -226,6 +227,10 @@ class Sim:
 
     def step(self, n: int = 1):
         _check(lib().lbch_step(self._h, int(n)), "lbch_step")
+
+    def step_extrapolated(self, ext: float):
+        """Two steps storing f_{n+2} + ext (f_{n+2} - f_n) (lbch_step_extrapolated)."""
+        _check(lib().lbch_step_extrapolated(self._h, float(ext)), "lbch_step_extrapolated")
 
     @property
     def nstep(self) -> int:

@@ -143,3 +143,56 @@ def test_zero_residual_network_leaves_extrapolation_unchanged():
     sb = L.hybrid_advance(b, net, o, 3 * 60)
     assert sa.accepted == sb.accepted == 3
     assert np.array_equal(a.phi(), b.phi())
+
+
+@pytest.mark.parametrize("precision,nx,ny,tiling", [(0, 96, 70, (128, 16)), (1, 128, 90, (256, 24)),
+                                                    (1, 130, 64, (128, 8)), (1, 256, 96, (512, 20))])
+def test_extrapolating_step_stores_the_projective_state(precision, nx, ny, tiling):
+    # lbch_step_extrapolated = two steps, then f <- f_{n+2} + k (f_{n+2} - f_n) on the populations
+    # (the saved state is a permutation of the stored populations, so the identity holds on it)
+    L = lb()
+    p = common.make_params(nx, ny, precision, alpha=0.3)
+    dt = np.float64 if precision == 0 else np.float32
+    k = dt(8.0)
+    phi0 = inputs.spinodal(nx, ny, seed=3, amp=0.3)
+    with L.Sim(p) as a, L.Sim(p) as b:
+        for s in (a, b):
+            s.set_time_blocking(2)
+            s.set_tiling(*tiling)
+            s.init(phi0)
+            s.step(6)
+        fn = np.frombuffer(a.save_state()[-9 * nx * ny * dt().itemsize:], dtype=dt)
+        a.step(2)
+        fn2 = np.frombuffer(a.save_state()[-9 * nx * ny * dt().itemsize:], dtype=dt)
+        b.step_extrapolated(float(k))
+        got = np.frombuffer(b.save_state()[-9 * nx * ny * dt().itemsize:], dtype=dt)
+        assert b.nstep == 8
+    want = fn2 + k * (fn2 - fn)
+    eps = np.finfo(dt).eps
+    bound = 2 * eps * (np.abs(fn2) + k * np.abs(fn2 - fn))
+    print(f"case extrap precision={precision} {nx}x{ny} tiling={tiling}", flush=True)
+    assert np.all(np.abs(got.astype(np.float64) - want.astype(np.float64)) <= bound)
+
+
+def test_extrapolating_step_errors():
+    L = lb()
+    p = common.make_params(64, 64, 1)
+    with L.Sim(p) as s:
+        with pytest.raises(L.LbchError) as ei:
+            s.step_extrapolated(8.0)
+        assert ei.value.status == L.E_STATE
+        s.init(inputs.spinodal(64, 64, seed=1))
+        s.set_time_blocking(1)
+        with pytest.raises(L.LbchError) as ei:
+            s.step_extrapolated(8.0)
+        assert ei.value.status == L.E_UNSUPPORTED
+        s.set_time_blocking(2)
+        with pytest.raises(L.LbchError) as ei:
+            s.step_extrapolated(float("nan"))
+        assert ei.value.status == L.E_INVALID
+    p3 = common.make_params(30, 12, 1, lattice=L.D3Q15, nz=8)
+    with L.Sim(p3) as s:
+        s.init(inputs.spinodal3(30, 12, 8, seed=1))
+        with pytest.raises(L.LbchError) as ei:
+            s.step_extrapolated(8.0)
+        assert ei.value.status == L.E_UNSUPPORTED
