@@ -124,6 +124,34 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
             if (b) lbch_batch_destroy(b);
         }
     } guard{win};
+    // Three population buffers rotate: the simulation's pair f[cur], f[cur ^ 1] and one
+    // outside it, which holds the snapshot of the cycle's start state while a cycle runs
+    // (no copy): the first write of a cycle goes to a pair buffer that is not the snapshot,
+    // and the snapshot is then taken out of the pair.  On exit the simulation gets its own
+    // two buffers back (one copy when its state sits in the third).
+    void* const own[2] = {sim->f[0], sim->f[1]};
+    struct PairGuard {
+        lbch_sim* sim;
+        const void* own0;
+        const void* own1;
+        void* third;
+        size_t bytes;
+        hipStream_t s;
+        ~PairGuard() {
+            void*& cur = sim->f[sim->cur];
+            void*& oth = sim->f[sim->cur ^ 1];
+            void* o0 = const_cast<void*>(own0);
+            void* o1 = const_cast<void*>(own1);
+            if (cur == third) {
+                void* dst = (oth == o0) ? o1 : o0;
+                (void)hipMemcpyAsync(dst, third, bytes, hipMemcpyDeviceToDevice, s);
+                (void)hipStreamSynchronize(s);
+                cur = dst;
+            }
+            oth = (cur == o0) ? o1 : o0;
+        }
+    } pair_guard{sim, own[0], own[1], snap, fbytes, s};
+    void* spare = snap;     // the buffer outside the pair
     std::mt19937_64 rng(o->seed);
     Timer tm(s);
     const int64_t cyc = (int64_t)o->jump + o->correct_steps;
@@ -164,14 +192,22 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
             if (est != LBCH_OK) return est;
         }
         const int64_t step0 = sim->step;
-        // snapshot, jump, mass projection, re-initialisation
+        // snapshot (the start state's buffer leaves the pair), jump, mass projection,
+        // re-initialisation
         tm.start();
-        HIP_TRY(hipMemcpyAsync(snap, sim->f[sim->cur], fbytes, hipMemcpyDeviceToDevice, s));
-        if (!o->dry_run) {
+        void* const saved = sim->f[sim->cur];
+        if (o->dry_run) {
+            HIP_TRY(hipMemcpyAsync(spare, saved, fbytes, hipMemcpyDeviceToDevice, s));
+            sim->f[sim->cur] = spare;
+            spare = saved;
+        } else {
             ST_TRY(lbch_phi_device(sim, phi, LBCH_FP32));
             if (o->extrapolate) {
-                // rate from one plain step (the state is re-initialised below)
+                // rate from one plain step (the state is re-initialised below); it reads the
+                // saved buffer and writes the other one, then the saved buffer leaves the pair
                 ST_TRY(lbch_step(sim, 1));
+                sim->f[sim->cur ^ 1] = spare;
+                spare = saved;
                 ST_TRY(lbch_phi_device(sim, phi1, LBCH_FP32));
                 const float* base = (const float*)phi;
                 if (net) {
@@ -182,6 +218,8 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
                                           (float*)phin, s));
             } else {
                 ST_TRY(lbsg_predict(net, (const float*)phi, o->cond, o->ncond, ny, nx, (float*)phin));
+                sim->f[sim->cur] = spare;     // the re-initialisation writes outside the snapshot
+                spare = saved;
             }
             HIP_TRY(launch_sum_f32((const float*)phi, N, (double*)part, (double*)dsum, s));
             HIP_TRY(launch_sum_f32((const float*)phin, N, (double*)part, (double*)dsum + 1, s));
@@ -210,7 +248,7 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
             // shadow windows from the snapshot (swap it in temporarily as the state to read)
             std::vector<std::pair<int, int>> pos(o->windows);
             void* live = sim->f[sim->cur];
-            sim->f[sim->cur] = snap;
+            sim->f[sim->cur] = saved;
             for (int w = 0; w < o->windows; ++w) {
                 pos[w] = {(int)(rng() % (uint64_t)ny), (int)(rng() % (uint64_t)nx)};
                 lbch_status ls = lbch_batch_load_window(win, w, sim, pos[w].first, pos[w].second);
@@ -245,11 +283,13 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
             st.accepted += 1;
             st.last_energy = E1;
             E0 = E1;
-            have_e0 = true;
+            have_e0 = true;       // the snapshot's buffer (spare) is free again
         } else {
             have_e0 = false;
             tm.start();
-            HIP_TRY(hipMemcpyAsync(sim->f[sim->cur], snap, fbytes, hipMemcpyDeviceToDevice, s));
+            // back to the start state: its buffer returns to the pair
+            spare = sim->f[sim->cur];
+            sim->f[sim->cur] = saved;
             sim->step = step0;
             ST_TRY(lbch_step(sim, cyc));
             st.plain_steps += cyc;
