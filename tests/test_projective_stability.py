@@ -49,6 +49,12 @@ def test_short_plain_phase_is_unstable(spectra):
     assert worst_gain(spectra, 2, 8) > 1.5
 
 
+def test_longest_stable_jump_after_four_plain_steps(spectra):
+    # 4 + 20 is the last stable inner cycle after four plain steps; 4 + 24 amplifies
+    assert worst_gain(spectra, 4, 20) < 1.0
+    assert worst_gain(spectra, 4, 24) > 1.1
+
+
 def test_slow_mode_first_order(spectra):
     # slow modes (|1 - lam| < 1e-3): the projective step reproduces lam^(n+J) to O(((n+J)(1-lam))^2)
     for lam in spectra:
