@@ -76,10 +76,12 @@ lbch_status lbch_batch_set_tiling(lbch_batch* batch, int32_t block_threads, int3
 lbch_status lbch_batch_get_tiling(const lbch_batch* batch, int32_t* block_threads, int32_t* rows_per_block,
                                   int32_t* persistent_blocks, int32_t* total_tiles);
 
-/* Times launch shapes (depth x block_threads x rows_per_block) for this
- * batch with steps_per_trial launches each (writing the idle buffer: the
- * state and step counter are unchanged), keeps the fastest per step (and the
- * fastest single-step shape for odd remainders).  Synchronises. */
+/* Times launch shapes (depth x block_threads x rows_per_block, the heights
+ * being the default rule's own and 16 .. 128) for this batch with
+ * steps_per_trial launches each (writing the idle buffer: the state and step
+ * counter are unchanged), keeps the fastest per step (and the fastest
+ * single-step shape for odd remainders); rows_per_block returns the height in
+ * use.  Synchronises. */
 lbch_status lbch_batch_autotune(lbch_batch* batch, int32_t steps_per_trial, int32_t* block_threads,
                                 int32_t* rows_per_block, double* ms_per_step);
 

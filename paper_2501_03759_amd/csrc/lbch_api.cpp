@@ -854,8 +854,10 @@ extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32
     if (steps_per_trial < 1) return fail(LBCH_E_INVALID, "steps_per_trial %d < 1", steps_per_trial);
     if (s->d3) return autotune3(s, steps_per_trial, block_threads, rows_per_block, ms_per_step);
     // Trials read the current state and write the idle buffer, so the state is untouched.
+    // chunk heights: 0 = the launch model's own choice (the default tiling, small-grid rule
+    // included), then fixed heights
     const int nts[4] = {64, 128, 256, 512};
-    const int hcs[7] = {8, 16, 32, 64, 128, 256, 512};
+    const int hcs[8] = {0, 8, 16, 32, 64, 128, 256, 512};
     hipEvent_t a = nullptr, b = nullptr;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
@@ -867,9 +869,10 @@ extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32
             if (nt > 128 && s->g.nx < nt / 2) continue;          // mostly idle lanes
             if (depth == 2 && (nt == 64 || (s->esize == 8 && nt == 512))) continue;
             for (int hc : hcs) {
-                if (hc > s->g.ny && hc != hcs[0]) continue;
-                if (depth == 2 && hc < 32) continue;             // 14 start-up rows per chunk
-                Tiling t = make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize);
+                if (hc > 8 && hc > s->g.ny) continue;
+                if (depth == 2 && hc > 0 && hc < 32) continue;   // 14 start-up rows per chunk
+                Tiling t = hc == 0 ? sim_tiling(s, depth, nt, 0)
+                                   : make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize);
                 t.staged = staged;
                 hipError_t e =
                     launch_step(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g, t, coef_ptr(s), s->stream);

@@ -516,8 +516,8 @@ extern "C" lbch_status lbch_batch_autotune(lbch_batch* b, int32_t steps_per_tria
     for (int depth = 1; depth <= 2 && st == LBCH_OK; ++depth) {
         for (int nt : {64, 128, 256}) {
             if (depth == 2 && nt == 64) continue;
-            for (int hc : {16, 32, 64, 128}) {
-                if (depth == 2 && hc < 32) continue;
+            for (int hc : {0, 16, 32, 64, 128}) {        // 0: the default rule's height
+                if (depth == 2 && hc > 0 && hc < 32) continue;
                 st = configure(b, depth, nt, hc, b->cfg[depth - 1].blocks_user);
                 if (st == LBCH_OK) st = reset_counter(b);
                 if (st != LBCH_OK) break;
@@ -554,7 +554,7 @@ extern "C" lbch_status lbch_batch_autotune(lbch_batch* b, int32_t steps_per_tria
     if (d != b->depth) drop_graphs(b);
     b->depth = d;
     if (block_threads) *block_threads = best_nt[d - 1];
-    if (rows_per_block) *rows_per_block = best_hc[d - 1];
+    if (rows_per_block) *rows_per_block = b->cfg[d - 1].hc;   // the height in use
     if (ms_per_step) *ms_per_step = best[d - 1] / steps_per_trial;
     return ok();
 }
