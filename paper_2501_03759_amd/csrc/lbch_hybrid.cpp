@@ -129,28 +129,25 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
     // (no copy): the first write of a cycle goes to a pair buffer that is not the snapshot,
     // and the snapshot is then taken out of the pair.  On exit the simulation gets its own
     // two buffers back (one copy when its state sits in the third).
-    void* const own[2] = {sim->f[0], sim->f[1]};
     struct PairGuard {
         lbch_sim* sim;
-        const void* own0;
-        const void* own1;
+        void* own0;       // the simulation's own buffers
+        void* own1;
         void* third;
         size_t bytes;
         hipStream_t s;
         ~PairGuard() {
             void*& cur = sim->f[sim->cur];
             void*& oth = sim->f[sim->cur ^ 1];
-            void* o0 = const_cast<void*>(own0);
-            void* o1 = const_cast<void*>(own1);
             if (cur == third) {
-                void* dst = (oth == o0) ? o1 : o0;
+                void* dst = (oth == own0) ? own1 : own0;
                 (void)hipMemcpyAsync(dst, third, bytes, hipMemcpyDeviceToDevice, s);
                 (void)hipStreamSynchronize(s);
                 cur = dst;
             }
-            oth = (cur == o0) ? o1 : o0;
+            oth = (cur == own0) ? own1 : own0;
         }
-    } pair_guard{sim, own[0], own[1], snap, fbytes, s};
+    } pair_guard{sim, sim->f[0], sim->f[1], snap, fbytes, s};
     void* spare = snap;     // the buffer outside the pair
     std::mt19937_64 rng(o->seed);
     Timer tm(s);
