@@ -30,14 +30,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(n_nodes: int, precision: str, depth: int, lattice: str = "d2q9"):
+def measured_traffic(n_nodes: int, precision: str, depth: int, lattice: str = "d2q9", path: str = "",
+                     tiling=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source at this size and depth; else None."""
+    the current kernel source at this size, depth (and launch shape, when given); else None."""
     from paper_2501_03759_amd.profiling import STEP_KERNEL_3D, STEP_KERNELS, kernel_hash
-    if lattice == "d3q15":
+    if not path and lattice == "d3q15":
         side = int(round(n_nodes ** (1.0 / 3.0)))
         path = os.path.join(ROOT, "profiles", f"{STEP_KERNEL_3D}_spinodal{side}_{precision}.json")
-    else:
+    elif not path:
         side = int(round(n_nodes ** 0.5))
         path = os.path.join(ROOT, "profiles", f"{STEP_KERNELS[depth]}_spinodal{side}_{precision}.json")
     try:
@@ -45,7 +46,8 @@ def measured_traffic(n_nodes: int, precision: str, depth: int, lattice: str = "d
     except Exception:
         return None
     if (rec.get("kernel_sha256_16") != kernel_hash(lattice) or rec.get("nodes") != n_nodes
-            or rec.get("precision") != precision or rec.get("depth", 1) != depth):
+            or rec.get("precision") != precision or rec.get("depth", 1) != depth
+            or (tiling is not None and rec.get("tiling") != list(tiling))):
         return None
     return rec.get("bytes_per_launch")
 
@@ -301,7 +303,13 @@ def ensemble_workload(args):
     b = lbch.Batch(params, stream)
     for k, m in enumerate(mems):
         b.init(k, inputs.member_phi0(m))
-    nt, hc, _ = b.autotune(3)
+    if args.tiling:                                  # block_threads,rows_per_block[,depth]: a fixed shape
+        v = [int(x) for x in args.tiling.split(",")]
+        b.set_time_blocking(v[2] if len(v) > 2 else 2)
+        b.set_tiling(v[0], v[1])
+        nt, hc = v[0], v[1]
+    else:
+        nt, hc, _ = b.autotune(3)
     depth = b.time_blocking()
     nodes = b.nodes
     b.step(args.warmup)
@@ -314,8 +322,12 @@ def ensemble_workload(args):
     end.synchronize()
     ms_step = start.elapsed_time(end) / args.steps
     b.close()
+    copy = copy_ceiling(torch, lbch, stream)
     launch_ms = ms_step * depth
     alg = 72 * nodes * depth
+    traffic = measured_traffic(nodes, "fp32", depth,
+                               path=os.path.join(ROOT, "profiles", "batch_step_ensemble512_fp32.json"),
+                               tiling=(nt, hc))
     achieved = alg / (launch_ms * 1e-3) / 1e9
     out = {
         "metric": "MLUPS, 512-member ragged ensemble (1 GPU)", "value": round(nodes / (ms_step * 1e-3) / 1e6, 1),
@@ -325,9 +337,10 @@ def ensemble_workload(args):
         "config": {"workload": "ensemble-512-ragged-fp32", "members": len(mems), "nodes": nodes,
                    "time_steps_per_launch": depth, "tiling": [nt, hc]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "batch_step",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "batch_step",
                      "launch_ms": round(launch_ms, 4), "bytes_per_update": 72,
                      "min_bytes_GBs": round(72 * nodes / (launch_ms * 1e-3) / 1e9, 1)},
+        "hbm_copy": copy,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_ensemble(mems)
@@ -463,7 +476,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192, help="grid side (default: the 8192^2 workload)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per kernel launch")
-    ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block")
+    ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block (ensemble: [,depth], a fixed shape instead of the autotuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n3", type=int, default=256, help="box side of the D3Q15 workload")
     ap.add_argument("--workload", choices=["step", "step3d", "hybrid", "ensemble", "surrogate"], default="step",

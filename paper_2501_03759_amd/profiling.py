@@ -44,8 +44,21 @@ def counter_values(d, counter, kernel_substr):
     vals = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter and kernel_substr in r["Kernel_Name"]:
-            vals.append(float(r["Counter_Value"]))
+            vals.append((int(r.get("Dispatch_Id") or 0), float(r["Counter_Value"])))
+    vals = [v for _, v in sorted(vals, key=lambda dv: dv[0])]       # dispatch order
     return vals
+
+
+def last_dispatches(d, kernel_substr, last):
+    """Name and durations (ns) of the last `last` dispatches of a kernel, from the run's kernel trace."""
+    path = _one(os.path.join(d, "**", "*kernel_trace.csv"))
+    rows = [r for r in csv.DictReader(open(path)) if kernel_substr in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    rows = rows[-last:]
+    names = {r["Kernel_Name"] for r in rows}
+    if len(names) != 1:
+        raise ValueError(f"the last {last} dispatches of {kernel_substr} are not one kernel: {sorted(names)}")
+    return names.pop()[:120], [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
 
 
 def kernel_stats(d):
@@ -83,11 +96,15 @@ def main():
     ap.add_argument("--command", required=True, help="the profiled command lines (for the summary header)")
     ap.add_argument("--out", required=True, help="output prefix, e.g. profiles/step2_fused_spinodal8192_fp32")
     ap.add_argument("--title", default="", help="summary title (stats-only mode)")
+    ap.add_argument("--kernel", default="", help="kernel name substring (default: the lattice's step kernel)")
+    ap.add_argument("--tiling", default="", help="launch shape of the profiled runs (block_threads,rows), recorded")
+    ap.add_argument("--last", type=int, default=0,
+                    help="use only the last N dispatches of the kernel (runs that also launch it in other shapes)")
     args = ap.parse_args()
     d3 = args.lattice == "d3q15"
     if d3:
         args.depth = 1
-    STEP_KERNEL = STEP_KERNEL_3D if d3 else STEP_KERNELS[args.depth]
+    STEP_KERNEL = args.kernel or (STEP_KERNEL_3D if d3 else STEP_KERNELS[args.depth])
     q = 15 if d3 else 9
     if not args.fetch:
         stats_only(args)
@@ -99,10 +116,17 @@ def main():
     w_copy = statistics.median(counter_values(args.write, "WRITE_SIZE", COPY_KERNEL)) * kib
     fetch_scale = COPY_BYTES / f_copy
     write_scale = COPY_BYTES / w_copy
-    f_step = statistics.median(counter_values(args.fetch, "FETCH_SIZE", STEP_KERNEL)) * kib * fetch_scale
-    w_step = statistics.median(counter_values(args.write, "WRITE_SIZE", STEP_KERNEL)) * kib * write_scale
+    fv = counter_values(args.fetch, "FETCH_SIZE", STEP_KERNEL)
+    wv = counter_values(args.write, "WRITE_SIZE", STEP_KERNEL)
+    if args.last:
+        fv, wv = fv[-args.last:], wv[-args.last:]
+    f_step = statistics.median(fv) * kib * fetch_scale
+    w_step = statistics.median(wv) * kib * write_scale
     stats = kernel_stats(args.trace)
-    step = [s for s in stats if STEP_KERNEL in s["name"]][0]
+    step = dict([s for s in stats if STEP_KERNEL in s["name"]][0])
+    if args.last:
+        name, durs = last_dispatches(args.trace, STEP_KERNEL, args.last)
+        step = {"name": name, "avg_ns": statistics.mean(durs)}
     # algorithmic bytes: q populations read + q written per lattice update
     # (the one-step figure), times the updates of one launch; the launch's
     # own minimum traffic is one read and one write of the state
@@ -117,6 +141,8 @@ def main():
         "depth": args.depth,
         "min_bytes_per_launch": min_traffic,
         "avg_duration_ms": step["avg_ns"] / 1e6,
+        "dispatches_used": args.last or "all",
+        "tiling": [int(v) for v in args.tiling.split(",")] if args.tiling else None,
         "fetch_scale_from_copy": fetch_scale,
         "write_scale_from_copy": write_scale,
         "fetch_bytes_per_launch": f_step,
@@ -142,7 +168,8 @@ def main():
               f"time step(s); algorithmic {alg / 1e9:.3f} GB ({2 * q * esize} B per lattice update x "
               f"{args.depth} updates per node); ratio {rec['traffic_over_algorithmic']:.3f}; one read + one write "
               f"of the state = {min_traffic / 1e9:.3f} GB (measured / that = {(f_step + w_step) / min_traffic:.3f})",
-              f"- average duration {rec['avg_duration_ms']:.4f} ms -> {rec['achieved_alg_GBs']:.0f} GB/s algorithmic, "
+              f"- average duration {rec['avg_duration_ms']:.4f} ms"
+              f"{f' (last {args.last} dispatches)' if args.last else ''} -> {rec['achieved_alg_GBs']:.0f} GB/s algorithmic, "
               f"{rec['achieved_traffic_GBs']:.0f} GB/s measured traffic (8000 GB/s peak)",
               f"- kernel source sha256[:16] = {rec['kernel_sha256_16']}"]
     with open(args.out + ".md", "w") as fh:
