@@ -1,0 +1,62 @@
+"""Host-side checks of the rocprofv3 summary tool and of bench.py's lookup of the measured
+traffic (synthetic CSV files in the layout rocprofv3 writes; no GPU)."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_counter_values_in_dispatch_order(tmp_path):
+    from paper_2501_03759_amd import profiling
+    rows = [[7, "FETCH_SIZE", "void lbch::batch_step<float, 128, true, 2>", 30.0],
+            [2, "FETCH_SIZE", "void lbch::batch_step<float, 64, true, 1>", 10.0],
+            [5, "WRITE_SIZE", "void lbch::batch_step<float, 128, true, 2>", 99.0],
+            [4, "FETCH_SIZE", "lbch::copy16_k", 5.0],
+            [3, "FETCH_SIZE", "void lbch::batch_step<float, 128, true, 2>", 20.0]]
+    _write_csv(str(tmp_path / "r" / "run_counter_collection.csv"),
+               ["Dispatch_Id", "Counter_Name", "Kernel_Name", "Counter_Value"], rows)
+    assert profiling.counter_values(str(tmp_path / "r"), "FETCH_SIZE", "batch_step") == [10.0, 20.0, 30.0]
+    assert profiling.counter_values(str(tmp_path / "r"), "FETCH_SIZE", "copy16_k") == [5.0]
+
+
+def test_last_dispatches_are_one_kernel(tmp_path):
+    from paper_2501_03759_amd import profiling
+    a, b = "void lbch::batch_step<float, 256, true, 2>(x)", "void lbch::batch_step<float, 128, true, 2>(x)"
+    rows = [[a, 100, 150], [b, 300, 310], [b, 200, 230], [b, 400, 440], ["lbch::copy16_k", 500, 900]]
+    _write_csv(str(tmp_path / "t" / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+               rows)
+    name, durs = profiling.last_dispatches(str(tmp_path / "t"), "batch_step", 3)
+    assert name == b and durs == [30, 10, 40]                       # in start order
+    with pytest.raises(ValueError):
+        profiling.last_dispatches(str(tmp_path / "t"), "batch_step", 4)
+
+
+def test_measured_traffic_requires_matching_source_size_depth_and_shape(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2501_03759_amd.profiling import kernel_hash
+    rec = {"kernel_sha256_16": kernel_hash("d2q9"), "nodes": 1000, "precision": "fp32", "depth": 2,
+           "tiling": [128, 32], "bytes_per_launch": 123.0}
+    p = str(tmp_path / "prof.json")
+    json.dump(rec, open(p, "w"))
+    assert bench.measured_traffic(1000, "fp32", 2, path=p, tiling=(128, 32)) == 123.0
+    assert bench.measured_traffic(1000, "fp32", 2, path=p) == 123.0
+    assert bench.measured_traffic(1000, "fp32", 2, path=p, tiling=(128, 64)) is None
+    assert bench.measured_traffic(999, "fp32", 2, path=p, tiling=(128, 32)) is None
+    assert bench.measured_traffic(1000, "fp32", 1, path=p, tiling=(128, 32)) is None
+    assert bench.measured_traffic(1000, "fp64", 2, path=p, tiling=(128, 32)) is None
+    json.dump(dict(rec, kernel_sha256_16="0" * 16), open(p, "w"))
+    assert bench.measured_traffic(1000, "fp32", 2, path=p, tiling=(128, 32)) is None
+    assert bench.measured_traffic(1000, "fp32", 2, path=str(tmp_path / "missing.json")) is None
