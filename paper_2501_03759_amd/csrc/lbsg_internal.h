@@ -58,14 +58,20 @@ hipError_t pack_wflip(const float* W, __bf16* Wf, int Co, int Ci, hipStream_t s)
 hipError_t pack_input(const float* x, __bf16* out, long long P, int cin, int cpad, hipStream_t s);
 hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16* out, float* xin, long long P, int cpad,
                          hipStream_t s);
-hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s);
+// the gradient producers below can fold in the ReLU backward of the layer
+// that consumes their result: mask (nullable) is that layer's stored
+// post-activation, laid out as the result, which is zeroed where mask <= 0
+hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s,
+                        const __bf16* mask = nullptr);
 hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
-                          bool accumulate, hipStream_t s);
+                          bool accumulate, hipStream_t s, const __bf16* mask_u = nullptr,
+                          const __bf16* mask_s = nullptr);
 hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s);
 hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
                     long long P, int C, float scale, hipStream_t s);
+// mask_dd: dd is ReLU-masked by d (the head's input is a post-ReLU activation)
 hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float scale,
-                    float* part, float* grad_wb, hipStream_t s);
+                    float* part, float* grad_wb, hipStream_t s, bool mask_dd = false);
 hipError_t mse(const float* pred, const float* target, float* g, int N, int H, int Wd, int margin, double* part,
                double* out, hipStream_t s);
 hipError_t adam(float* w, const float* g, float* m, float* v, long long n, float lr, float b1, float b2, float eps,

@@ -642,9 +642,21 @@ __global__ void pack_phi_cond_k(const float* __restrict__ phi, const float* __re
     }
 }
 
-// dx (N,H,W,C) (+)= avgpool2 adjoint of dy (N,H/2,W/2,C)
+// ReLU backward folded into a gradient's producer: v where the stored
+// post-activation m is positive, else 0 (no-op for a null mask)
+__device__ __forceinline__ bf16x8 relu_mask8(const bf16x8 v, const __bf16* __restrict__ mask, long long off) {
+    if (!mask) return v;
+    const bf16x8 m = *reinterpret_cast<const bf16x8*>(mask + off);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (float)m[k] > 0.f ? v[k] : (__bf16)0.f;
+    return o;
+}
+
+// dx (N,H,W,C) (+)= avgpool2 adjoint of dy (N,H/2,W/2,C); mask (nullable, laid
+// out as dx): the result is ReLU-masked by it
 __global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict__ dx, int N, int H, int Wd, int C,
-                               int accumulate) {
+                               int accumulate, const __bf16* __restrict__ mask) {
     const int Q = C / 8;
     const long long total = (long long)N * H * Wd * Q;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -665,13 +677,15 @@ __global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict
 #pragma unroll
             for (int k = 0; k < 8; ++k) o[k] = (__bf16)(0.25f * (float)g[k]);
         }
-        *reinterpret_cast<bf16x8*>(dx + p * C + c0) = o;
+        *reinterpret_cast<bf16x8*>(dx + p * C + c0) = relu_mask8(o, mask, p * C + c0);
     }
 }
 
-// adjoint of up2_concat: du = sum of the 2x2 block of dz[..., :Cu]; dsk (+)= dz[..., Cu:]
+// adjoint of up2_concat: du = sum of the 2x2 block of dz[..., :Cu]; dsk (+)= dz[..., Cu:];
+// mask_u / mask_s (nullable, laid out as du / dsk) ReLU-mask the results
 __global__ void up2_concat_bwd_k(const __bf16* __restrict__ dz, __bf16* __restrict__ du, __bf16* __restrict__ dsk,
-                                 int N, int H, int Wd, int Cu, int Cs, int accumulate) {
+                                 int N, int H, int Wd, int Cu, int Cs, int accumulate,
+                                 const __bf16* __restrict__ mask_u, const __bf16* __restrict__ mask_s) {
     const int C = Cu + Cs, Qu = Cu / 8, Qs = Cs / 8;
     const int Ho = H / 2, Wo = Wd / 2;
     const long long tu = (long long)N * Ho * Wo * Qu;
@@ -698,7 +712,7 @@ __global__ void up2_concat_bwd_k(const __bf16* __restrict__ dz, __bf16* __restri
             bf16x8 o;
 #pragma unroll
             for (int k = 0; k < 8; ++k) o[k] = (__bf16)acc[k];
-            *reinterpret_cast<bf16x8*>(du + po * Cu + c0) = o;
+            *reinterpret_cast<bf16x8*>(du + po * Cu + c0) = relu_mask8(o, mask_u, po * Cu + c0);
         } else {
             const long long j = i - tu;
             const long long p = j / Qs;
@@ -712,7 +726,7 @@ __global__ void up2_concat_bwd_k(const __bf16* __restrict__ dz, __bf16* __restri
             } else {
                 o = g;
             }
-            *reinterpret_cast<bf16x8*>(dsk + p * Cs + c0) = o;
+            *reinterpret_cast<bf16x8*>(dsk + p * Cs + c0) = relu_mask8(o, mask_s, p * Cs + c0);
         }
     }
 }
@@ -748,7 +762,7 @@ __global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict
 
 // data gradient of the 1x1 head: dd[p][c] = scale g[p] w[c] (8 channels per thread)
 __global__ void head_dd_k(const float* __restrict__ g, const float* __restrict__ w, __bf16* __restrict__ dd,
-                          long long P, int C, float scale) {
+                          long long P, int C, float scale, const __bf16* __restrict__ mask) {
     const int Q = C / 8;
     const long long n = P * Q;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
@@ -758,7 +772,7 @@ __global__ void head_dd_k(const float* __restrict__ g, const float* __restrict__
         bf16x8 v;
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = (__bf16)(gs * w[q * 8 + k]);
-        *reinterpret_cast<bf16x8*>(dd + p * C + q * 8) = v;
+        *reinterpret_cast<bf16x8*>(dd + p * C + q * 8) = relu_mask8(v, mask, p * C + q * 8);
     }
 }
 
@@ -1009,17 +1023,19 @@ hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16*
     return hipGetLastError();
 }
 
-hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s) {
+hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s,
+                        const __bf16* mask) {
     if (C % 8 != 0) return hipErrorInvalidValue;
-    avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C / 8), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0);
+    avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C / 8), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0,
+                                                                            mask);
     return hipGetLastError();
 }
 
 hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
-                          bool accumulate, hipStream_t s) {
+                          bool accumulate, hipStream_t s, const __bf16* mask_u, const __bf16* mask_s) {
     if (Cu % 8 != 0 || Cs % 8 != 0) return hipErrorInvalidValue;
     const long long n = ((long long)N * (H / 2) * (Wd / 2) * Cu + (long long)N * H * Wd * Cs) / 8;
-    up2_concat_bwd_k<<<grid_for(n), 256, 0, s>>>(dz, du, dsk, N, H, Wd, Cu, Cs, accumulate ? 1 : 0);
+    up2_concat_bwd_k<<<grid_for(n), 256, 0, s>>>(dz, du, dsk, N, H, Wd, Cu, Cs, accumulate ? 1 : 0, mask_u, mask_s);
     return hipGetLastError();
 }
 
@@ -1037,9 +1053,9 @@ hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float
 }
 
 hipError_t head_bwd(const float* g, const __bf16* d, const float* w, __bf16* dd, long long P, int C, int S, float scale,
-                    float* part, float* grad_wb, hipStream_t s) {
+                    float* part, float* grad_wb, hipStream_t s, bool mask_dd) {
     if (C % 8 != 0 || C > 512) return hipErrorInvalidValue;
-    head_dd_k<<<grid_for(P * (C / 8)), 256, 0, s>>>(g, w, dd, P, C, scale);
+    head_dd_k<<<grid_for(P * (C / 8)), 256, 0, s>>>(g, w, dd, P, C, scale, mask_dd ? d : nullptr);
     colsum_part_k<true><<<S, 256, 0, s>>>(d, g, P, C, scale, part);
     colsum_reduce_k<<<(C + 4) / 4, 256, 0, s>>>(part, S, C + 1, grad_wb);
     return hipGetLastError();

@@ -228,32 +228,37 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
     const int B = n->cur_b, H = n->cur_h, W = n->cur_w;
     const long long P0 = (long long)B * H * W;
     const Layer& Lh = n->layers.back();
+    // every gradient below leaves its producer already ReLU-masked by the
+    // activation it is the gradient of (head: d0; up / skip: d or e; pool: e)
     HIP_TRY(lbsg::head_bwd(gphi, n->lv[0].d, n->w + Lh.offW, n->lv[0].gd, P0, C[0], 256, n->scale, n->cpart,
-                           n->g + Lh.offW, n->stream));
+                           n->g + Lh.offW, n->stream, true));
     // decoder layers sit after the 2*Lv encoder layers, dec{Lv-2} first
     auto dec_layer = [&](int l, int ab) -> const Layer& { return n->layers[2 * Lv + 2 * (Lv - 2 - l) + ab]; };
     const __bf16* gcur = n->lv[0].gd;
     for (int l = 0; l <= Lv - 2; ++l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w, false, lv.da);
+        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w, true, lv.da);
         if (st != LBCH_OK) return st;
         // the weight gradient reads the concatenated input from its two sources
         const __bf16* up = (l == Lv - 2) ? n->lv[Lv - 1].e : n->lv[l + 1].d;
         st = conv_back(n, dec_layer(l, 0), lv.e, lv.da, lv.gda, lv.gzc, B, h, w, true, nullptr, up, C[l + 1]);
         if (st != LBCH_OK) return st;
         __bf16* du = (l + 1 < Lv - 1) ? n->lv[l + 1].gd : n->lv[Lv - 1].ge;
-        HIP_TRY(lbsg::up2_concat_bwd(lv.gzc, du, lv.ge, B, h, w, C[l + 1], C[l], false, n->stream));
+        const __bf16* du_mask = (l + 1 < Lv - 1) ? n->lv[l + 1].d : n->lv[Lv - 1].e;
+        HIP_TRY(lbsg::up2_concat_bwd(lv.gzc, du, lv.ge, B, h, w, C[l + 1], C[l], false, n->stream, du_mask, lv.e));
         gcur = du;
     }
     for (int l = Lv - 1; l >= 0; --l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.e, lv.ge, lv.ga, B, h, w, false, lv.a);
+        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.e, lv.ge, lv.ga, B, h, w, true, lv.a);
         if (st != LBCH_OK) return st;
         st = conv_back(n, n->layers[2 * l], lv.z, lv.a, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w, true);
         if (st != LBCH_OK) return st;
-        if (l > 0) HIP_TRY(lbsg::avgpool2_bwd(lv.gz, n->lv[l - 1].ge, B, h * 2, w * 2, C[l - 1], true, n->stream));
+        if (l > 0)
+            HIP_TRY(lbsg::avgpool2_bwd(lv.gz, n->lv[l - 1].ge, B, h * 2, w * 2, C[l - 1], true, n->stream,
+                                       n->lv[l - 1].e));
     }
     return ok();
 }
