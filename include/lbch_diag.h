@@ -66,6 +66,17 @@ lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, float* dw, in
 lbch_status lbsg_diag_conv3_wgrad_upcat(const float* u, const float* sk, const float* dy, float* dw, int32_t n,
                                         int32_t h, int32_t wd, int32_t cu, int32_t cs, int32_t co);
 
+/* The data gradient of the decoder's first convolution (input [nearest 2x
+ * upsampling of u (Cu channels), sk (Cs channels)], weights w[Co][Cu + Cs][3][3])
+ * for dy[N][H][W][Co], passed straight through the adjoints of the upsampling
+ * and the concatenation in the convolution's epilogue:
+ * du[N][H/2][W/2][Cu] = bf16(((a + b) + c) + d) over the BF16 data gradient's
+ * 2x2 blocks (a, b the upper row), ds[N][H][W][Cs] its remaining channels;
+ * mask_u / mask_s (nullable, laid out as du / ds) zero them where <= 0. */
+lbch_status lbsg_diag_conv3_dgrad_upadj(const float* dy, const float* w, const float* mask_u, const float* mask_s,
+                                        float* du, float* ds, int32_t n, int32_t h, int32_t wd, int32_t cu,
+                                        int32_t cs, int32_t co);
+
 /* db[Co] = sum over pixels of dy[p][co] (FP32), as the weight-gradient kernel
  * forms it beside dw (split partials, fixed-order reduction). */
 lbch_status lbsg_diag_conv3_bgrad(const float* x, const float* dy, float* db, int32_t n, int32_t h, int32_t wd,

@@ -26,7 +26,13 @@ hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf1
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s);
 // conv3_fwd without bias or activation whose BF16 result is masked:
-// Y = Mask > 0 ? y : 0 (Mask laid out as Y), as relu_bwd would.
+// Y = Mask > 0 ? y : 0 (Mask laid out as Y): the ReLU backward of the result.
+// data gradient of a convolution whose input was [up2(U) (Cu channels), S (Cs
+// channels)]: dU (H/2 x Wd/2 x Cu) receives the upsampling's adjoint (2x2
+// sums) and dS (H x Wd x Cs) the skip channels, each ReLU-masked by its
+// nullable mask (same layout); the full data gradient is never stored
+hipError_t conv3_fwd_upadj(const __bf16* X, const __bf16* Wt, __bf16* dU, __bf16* dS, const __bf16* mask_u,
+                           const __bf16* mask_s, int N, int H, int Wd, int Ci, int Cu, int Cs, hipStream_t s);
 hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mask, __bf16* Y, int N, int H, int Wd,
                             int Ci, int Co, hipStream_t s);
 // ReLU conv3_fwd writing Y and, to Yp (N x H/2 x Wd/2 x Co), its 2x2
@@ -63,10 +69,6 @@ hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16*
 // post-activation, laid out as the result, which is zeroed where mask <= 0
 hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s,
                         const __bf16* mask = nullptr);
-hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
-                          bool accumulate, hipStream_t s, const __bf16* mask_u = nullptr,
-                          const __bf16* mask_s = nullptr);
-hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s);
 hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
                     long long P, int C, float scale, hipStream_t s);
 // mask_dd: dd is ReLU-masked by d (the head's input is a post-ReLU activation)

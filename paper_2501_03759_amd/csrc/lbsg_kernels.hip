@@ -76,8 +76,15 @@ __device__ __forceinline__ void interleave_ds_mfma() {
 // the lower row of the block: the rows belong to one wave (rows r, r + 1),
 // the columns to lanes l16 and l16 ^ 1.
 // Mask (nullable, same layout as Y): Y = Mask > 0 ? y : 0 elementwise, the
-// ReLU backward of relu_bwd_k applied to the BF16 result (for data gradients
-// whose next consumer masks them by the previous layer's activation).
+// ReLU backward applied to the BF16 result (for data gradients whose next
+// consumer masks them by the previous layer's activation).
+// UPADJ (data gradient of a convolution whose input was [nearest 2x upsampling
+// of U (Cu channels), S (Co - Cu channels)]): the output is never formed;
+// channels below Cu go through the upsampling's adjoint, Yp (H/2 x Wd/2 x Cu)
+// = bf16(((a + b) + c) + d) over the BF16 outputs of each 2x2 block (a, b the
+// upper row), channels from Cu on are stored in Y (H x Wd x (Co - Cu)); Mask2
+// (layout of Yp) and Mask (layout of Y), both nullable, ReLU-mask the two
+// results.  Cu is a multiple of TC, so each workgroup feeds one of them.
 // ---------------------------------------------------------------------------
 struct HeadArgs {
     const float* w;      // [Co] head weights
@@ -88,12 +95,13 @@ struct HeadArgs {
     float scale;
 };
 
-template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false>
+template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false, bool UPADJ = false>
 __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
                                                    const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                    __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
                                                    const HeadArgs hd = HeadArgs{}, __bf16* __restrict__ Yp = nullptr,
-                                                   const __bf16* __restrict__ Mask = nullptr) {
+                                                   const __bf16* __restrict__ Mask = nullptr,
+                                                   const __bf16* __restrict__ Mask2 = nullptr) {
     constexpr int NXQ = 18 * 18 * 4;              // 16-byte chunks of the pixel tile
     constexpr int NWQ = 9 * TC * 4;               // 16-byte chunks of the weights
     constexpr int RX = (NXQ + 255) / 256, RW = (NWQ + 255) / 256;
@@ -243,10 +251,30 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
             xr[r] = hd.xin[(((size_t)n * H + ty0 + wave * 4 + r) * Wd + tx0 + l16) * hd.cin];
         hb0 = hd.b[0];
     }
-    bf16x4 prev[POOL ? CB : 1];   // row r - 1 of the 2x2 block (POOL)
+    bf16x4 prev[POOL || UPADJ ? CB : 1];   // row r - 1 of the 2x2 block (POOL, UPADJ)
     // the mask of the lane's outputs, loaded at once (data-gradient use)
-    constexpr bool MASKABLE = !RELU && !HEAD && !POOL;
-    bf16x4 mk[MASKABLE ? 4 : 1][MASKABLE ? CB : 1];
+    constexpr bool MASKABLE = !RELU && !HEAD && !POOL && !UPADJ;
+    bf16x4 mk[MASKABLE || UPADJ ? 4 : 1][MASKABLE || UPADJ ? CB : 1];
+    const bool up_part = UPADJ && co0 < Cu;   // workgroup-uniform
+    if constexpr (UPADJ) {
+        const int cs = Co - Cu;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = ty0 + wave * 4 + r, x = tx0 + l16;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (up_part) {
+                    // the pooled position of rows r - 1, r (r odd)
+                    if ((r & 1) && Mask2)
+                        mk[r][c] = *reinterpret_cast<const bf16x4*>(
+                            Mask2 + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + co0 + c * 16 + kb * 4);
+                } else if (Mask) {
+                    mk[r][c] = *reinterpret_cast<const bf16x4*>(
+                        Mask + (((size_t)n * H + y) * Wd + x) * cs + (co0 - Cu) + c * 16 + kb * 4);
+                }
+            }
+        }
+    }
     if constexpr (MASKABLE) {
         if (Mask) {
 #pragma unroll
@@ -277,6 +305,32 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 #pragma unroll
                     for (int j = 0; j < 4; ++j) o[j] = (float)mk[r][c][j] > 0.f ? o[j] : (__bf16)0.f;
                 }
+            }
+            if constexpr (UPADJ) {
+                if (up_part) {
+                    if ((r & 1) == 0) {
+                        prev[c] = o;
+                    } else {
+                        // even lanes: ((a + b) + c) + d, a and b the upper row
+                        bf16x4 q;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float a = (float)prev[c][j], lo = (float)o[j];
+                            q[j] = (__bf16)(((a + lane_xor1(a)) + lo) + lane_xor1(lo));
+                            if (Mask2) q[j] = (float)mk[r][c][j] > 0.f ? q[j] : (__bf16)0.f;
+                        }
+                        if ((l16 & 1) == 0)
+                            *reinterpret_cast<bf16x4*>(Yp + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu +
+                                                       co) = q;
+                    }
+                } else {
+                    if (Mask) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) o[j] = (float)mk[r][c][j] > 0.f ? o[j] : (__bf16)0.f;
+                    }
+                    *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * (Co - Cu) + (co - Cu)) = o;
+                }
+                continue;
             }
             if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
             if constexpr (POOL) {
@@ -681,70 +735,6 @@ __global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict
     }
 }
 
-// adjoint of up2_concat: du = sum of the 2x2 block of dz[..., :Cu]; dsk (+)= dz[..., Cu:];
-// mask_u / mask_s (nullable, laid out as du / dsk) ReLU-mask the results
-__global__ void up2_concat_bwd_k(const __bf16* __restrict__ dz, __bf16* __restrict__ du, __bf16* __restrict__ dsk,
-                                 int N, int H, int Wd, int Cu, int Cs, int accumulate,
-                                 const __bf16* __restrict__ mask_u, const __bf16* __restrict__ mask_s) {
-    const int C = Cu + Cs, Qu = Cu / 8, Qs = Cs / 8;
-    const int Ho = H / 2, Wo = Wd / 2;
-    const long long tu = (long long)N * Ho * Wo * Qu;
-    const long long ts = (long long)N * H * Wd * Qs;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tu + ts;
-         i += (long long)gridDim.x * blockDim.x) {
-        if (i < tu) {
-            const long long po = i / Qu;
-            const int c0 = (int)(i - po * Qu) * 8;
-            const int xo = (int)(po % Wo);
-            const long long r = po / Wo;
-            const int yo = (int)(r % Ho);
-            const long long nn = r / Ho;
-            float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int bb = 0; bb < 2; ++bb) {
-                    const bf16x8 g = *reinterpret_cast<const bf16x8*>(
-                        dz + ((nn * H + 2 * yo + a) * Wd + 2 * xo + bb) * C + c0);
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) acc[k] += (float)g[k];
-                }
-            bf16x8 o;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) o[k] = (__bf16)acc[k];
-            *reinterpret_cast<bf16x8*>(du + po * Cu + c0) = relu_mask8(o, mask_u, po * Cu + c0);
-        } else {
-            const long long j = i - tu;
-            const long long p = j / Qs;
-            const int c0 = (int)(j - p * Qs) * 8;
-            const bf16x8 g = *reinterpret_cast<const bf16x8*>(dz + p * C + Cu + c0);
-            bf16x8 o;
-            if (accumulate) {
-                const bf16x8 old = *reinterpret_cast<const bf16x8*>(dsk + p * Cs + c0);
-#pragma unroll
-                for (int k = 0; k < 8; ++k) o[k] = (__bf16)((float)g[k] + (float)old[k]);
-            } else {
-                o = g;
-            }
-            *reinterpret_cast<bf16x8*>(dsk + p * Cs + c0) = relu_mask8(o, mask_s, p * Cs + c0);
-        }
-    }
-}
-
-// g = dy * (y > 0)   (ReLU backward from the stored post-activation); n8 = chunks of 8
-__global__ void relu_bwd_k(const __bf16* __restrict__ dy, const __bf16* __restrict__ y, __bf16* __restrict__ g,
-                           long long n8) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n8;
-         i += (long long)gridDim.x * blockDim.x) {
-        const bf16x8 a = reinterpret_cast<const bf16x8*>(dy)[i];
-        const bf16x8 b = reinterpret_cast<const bf16x8*>(y)[i];
-        bf16x8 o;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) o[k] = (float)b[k] > 0.f ? a[k] : (__bf16)0.f;
-        reinterpret_cast<bf16x8*>(g)[i] = o;
-    }
-}
-
 // head: out[p] = phi[p] + scale (b + sum_c w[c] d[p][c])   (phi = input channel 0, fp32)
 __global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict__ w, const float* __restrict__ b,
                            const float* __restrict__ xin, int cin, float* __restrict__ out, long long P, int C,
@@ -903,6 +893,21 @@ hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mas
     return hipGetLastError();
 }
 
+hipError_t conv3_fwd_upadj(const __bf16* X, const __bf16* Wt, __bf16* dU, __bf16* dS, const __bf16* mask_u,
+                           const __bf16* mask_s, int N, int H, int Wd, int Ci, int Cu, int Cs, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || !dU || !dS)
+        return hipErrorInvalidValue;
+    const int tiles = N * (H / 16) * (Wd / 16);
+    const int Co = Cu + Cs;
+    if (Cu % 64 == 0 && Cs % 64 == 0 && (long long)tiles * (Co / 64) >= 512)
+        conv3_fwd_k<64, false, false, false, false, true><<<dim3(tiles, Co / 64), 256, 0, s>>>(
+            X, nullptr, Cu, Wt, nullptr, dS, H, Wd, Ci, Co, HeadArgs{}, dU, mask_s, mask_u);
+    else
+        conv3_fwd_k<32, false, false, false, false, true><<<dim3(tiles, Co / 32), 256, 0, s>>>(
+            X, nullptr, Cu, Wt, nullptr, dS, H, Wd, Ci, Co, HeadArgs{}, dU, mask_s, mask_u);
+    return hipGetLastError();
+}
+
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s) {
     if (H % 16 || Wd % 16 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || Co % 32) return hipErrorInvalidValue;
@@ -1028,20 +1033,6 @@ hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int 
     if (C % 8 != 0) return hipErrorInvalidValue;
     avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C / 8), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0,
                                                                             mask);
-    return hipGetLastError();
-}
-
-hipError_t up2_concat_bwd(const __bf16* dz, __bf16* du, __bf16* dsk, int N, int H, int Wd, int Cu, int Cs,
-                          bool accumulate, hipStream_t s, const __bf16* mask_u, const __bf16* mask_s) {
-    if (Cu % 8 != 0 || Cs % 8 != 0) return hipErrorInvalidValue;
-    const long long n = ((long long)N * (H / 2) * (Wd / 2) * Cu + (long long)N * H * Wd * Cs) / 8;
-    up2_concat_bwd_k<<<grid_for(n), 256, 0, s>>>(dz, du, dsk, N, H, Wd, Cu, Cs, accumulate ? 1 : 0, mask_u, mask_s);
-    return hipGetLastError();
-}
-
-hipError_t relu_bwd(const __bf16* dy, const __bf16* y, __bf16* g, long long n, hipStream_t s) {
-    if (n % 8 != 0) return hipErrorInvalidValue;
-    relu_bwd_k<<<grid_for(n / 8), 256, 0, s>>>(dy, y, g, n / 8);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct Level {
     __bf16 *z = nullptr, *a = nullptr, *e = nullptr;      // encoder block input, mid, output
     __bf16 *da = nullptr, *d = nullptr;                   // decoder block mid, output
     // gradients
-    __bf16 *gz = nullptr, *ga = nullptr, *ge = nullptr, *gzc = nullptr, *gda = nullptr, *gd = nullptr;
+    __bf16 *gz = nullptr, *ga = nullptr, *ge = nullptr, *gda = nullptr, *gd = nullptr;
 };
 
 int round32(int c) { return (c + 31) / 32 * 32; }
@@ -53,7 +53,6 @@ struct lbsg_net {
     std::vector<Level> lv;
     long long nparam = 0;
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
-    __bf16* gtmp = nullptr;          // relu-masked gradient of one conv output
     float* wpart = nullptr;          // weight-gradient split partials
     long long wpart_elems = 0;
     float* cpart = nullptr;          // column-sum partials
@@ -131,20 +130,15 @@ lbch_status repack(lbsg_net* n) {
 // kernels + reduction): 256 -> 1.45 ms, 512 -> 1.00 ms, 1024 -> 1.10 ms
 constexpr int kWgradBlocks = 512;
 
-// gradient of one conv layer: gout = dLoss/d(post-ReLU output y), input z.
-// gout_masked: gout already carries the ReLU mask of y.  dz_mask (nullable):
-// the data gradient dz is written masked by dz_mask > 0 (the layer whose
-// post-ReLU output is z consumes it as its gout_masked).  z_up (nullable):
-// the layer's input is [nearest 2x upsampling of z_up (cu channels), z].
-lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16* y, const __bf16* gout, __bf16* dz,
-                      int B, int H, int W, bool gout_masked = false, const __bf16* dz_mask = nullptr,
-                      const __bf16* z_up = nullptr, int cu = 0) {
+// gradient of one conv layer with input z: g = dLoss/d(pre-ReLU output),
+// i.e. the gradient of the post-ReLU output already masked by it (every
+// producer of such a gradient applies the mask).  dz (nullable) receives the
+// data gradient, masked by dz_mask > 0 when given (the previous layer's
+// activation).  z_up (nullable): the layer's input is [nearest 2x upsampling
+// of z_up (cu channels), z].
+lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16* g, __bf16* dz, int B, int H, int W,
+                      const __bf16* dz_mask = nullptr, const __bf16* z_up = nullptr, int cu = 0) {
     const long long P = (long long)B * H * W;
-    const __bf16* g = gout;
-    if (!gout_masked) {
-        HIP_TRY(lbsg::relu_bwd(gout, y, n->gtmp, P * L.co, n->stream));
-        g = n->gtmp;
-    }
     const int ntiles = B * (H / 16) * (W / 16);
     const int other = (L.co % 64 == 0 ? L.co / 64 : L.co / 32) * (L.ci_pad / 16);
     int S = kWgradBlocks / (other > 0 ? other : 1);
@@ -244,23 +238,29 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
     for (int l = 0; l <= Lv - 2; ++l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, lv.d, gcur, lv.gda, B, h, w, true, lv.da);
+        lbch_status st = conv_back(n, dec_layer(l, 1), lv.da, gcur, lv.gda, B, h, w, lv.da);
         if (st != LBCH_OK) return st;
         // the weight gradient reads the concatenated input from its two sources
         const __bf16* up = (l == Lv - 2) ? n->lv[Lv - 1].e : n->lv[l + 1].d;
-        st = conv_back(n, dec_layer(l, 0), lv.e, lv.da, lv.gda, lv.gzc, B, h, w, true, nullptr, up, C[l + 1]);
+        const Layer& L0 = dec_layer(l, 0);
+        if (L0.ci_pad != C[l + 1] + C[l]) return fail(LBCH_E_STATE, "decoder layer %d: unexpected input width", l);
+        st = conv_back(n, L0, lv.e, lv.gda, nullptr, B, h, w, nullptr, up, C[l + 1]);
         if (st != LBCH_OK) return st;
+        // its data gradient goes straight through the adjoints of the upsampling
+        // (into the lower level's gradient) and of the concatenation (into the
+        // skip's), each ReLU-masked by the activation it is the gradient of
         __bf16* du = (l + 1 < Lv - 1) ? n->lv[l + 1].gd : n->lv[Lv - 1].ge;
         const __bf16* du_mask = (l + 1 < Lv - 1) ? n->lv[l + 1].d : n->lv[Lv - 1].e;
-        HIP_TRY(lbsg::up2_concat_bwd(lv.gzc, du, lv.ge, B, h, w, C[l + 1], C[l], false, n->stream, du_mask, lv.e));
+        HIP_TRY(lbsg::conv3_fwd_upadj(lv.gda, L0.wf, du, lv.ge, du_mask, lv.e, B, h, w, L0.co, C[l + 1], C[l],
+                                      n->stream));
         gcur = du;
     }
     for (int l = Lv - 1; l >= 0; --l) {
         const int h = H >> l, w = W >> l;
         Level& lv = n->lv[l];
-        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.e, lv.ge, lv.ga, B, h, w, true, lv.a);
+        lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.ge, lv.ga, B, h, w, lv.a);
         if (st != LBCH_OK) return st;
-        st = conv_back(n, n->layers[2 * l], lv.z, lv.a, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w, true);
+        st = conv_back(n, n->layers[2 * l], lv.z, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w);
         if (st != LBCH_OK) return st;
         if (l > 0)
             HIP_TRY(lbsg::avgpool2_bwd(lv.gz, n->lv[l - 1].ge, B, h * 2, w * 2, C[l - 1], true, n->stream,
@@ -323,7 +323,6 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
     Alloc A;
     n->w = A.get<float>(n->nparam);
     const long long P0 = (long long)max_batch * max_h * max_w;
-    size_t max_act = 0;
     n->lv.resize(Lv);
     for (int l = 0; l < Lv; ++l) {
         const long long P = P0 >> (2 * l);
@@ -341,12 +340,10 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
             lv.ga = A.get<__bf16>(P * C[l]);
             lv.ge = A.get<__bf16>(P * C[l]);
             if (l < Lv - 1) {
-                lv.gzc = A.get<__bf16>(P * (C[l + 1] + C[l]));
                 lv.gda = A.get<__bf16>(P * C[l]);
                 lv.gd = A.get<__bf16>(P * C[l]);
             }
         }
-        max_act = std::max(max_act, (size_t)(P * C[l]));
     }
     for (Layer& L : n->layers) {
         if (L.k != 3) continue;
@@ -362,11 +359,12 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
         n->g = A.get<float>(n->nparam);
         n->m = A.get<float>(n->nparam);
         n->v = A.get<float>(n->nparam);
-        n->gtmp = A.get<__bf16>(max_act);
         n->gout = A.get<float>(P0);
         long long wp = 0;
         for (const Layer& L : n->layers)
-            if (L.k == 3) wp = std::max(wp, 1024LL * L.co * 9 * L.ci_pad / std::max(1, (L.co % 64 == 0 ? L.co / 64 : L.co / 32) * (L.ci_pad / 16)));
+            if (L.k == 3)
+                wp = std::max(wp, (long long)kWgradBlocks * L.co * 9 * L.ci_pad /
+                                      std::max(1, (L.co % 64 == 0 ? L.co / 64 : L.co / 32) * (L.ci_pad / 16)));
         n->wpart_elems = wp;
         n->wpart = A.get<float>(wp);
         n->dpart = A.get<double>(256);
@@ -656,6 +654,35 @@ extern "C" lbch_status lbsg_diag_conv3_wgrad_upcat(const float* u, const float* 
     HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
     HIP_TRY(lbsg::conv3_dw_upcat(ub, sb, gb, part, splits, n, h, wd, cu, cs, co, nullptr));
     HIP_TRY(lbsg::wgrad_reduce(part, dw, splits, co, ci, ci, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_dgrad_upadj(const float* dy, const float* w, const float* mask_u,
+                                                   const float* mask_s, float* du, float* ds, int32_t n, int32_t h,
+                                                   int32_t wd, int32_t cu, int32_t cs, int32_t co) {
+    if (!dy || !w || !du || !ds) return fail(LBCH_E_INVALID, "NULL argument");
+    if (cu < 32 || cu % 32) return fail(LBCH_E_INVALID, "cu = %d must be a positive multiple of 32", cu);
+    lbch_status st = diag_shape(n, h, wd, cs, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    const int ci = cu + cs;
+    __bf16* gb = S.get<__bf16>(P * co);
+    __bf16* wf = S.get<__bf16>((size_t)co * 9 * ci);
+    __bf16* dub = S.get<__bf16>(P / 4 * cu);
+    __bf16* dsb = S.get<__bf16>(P * cs);
+    __bf16* mub = mask_u ? S.get<__bf16>(P / 4 * cu) : nullptr;
+    __bf16* msb = mask_s ? S.get<__bf16>(P * cs) : nullptr;
+    if (!gb || !wf || !dub || !dsb || (mask_u && !mub) || (mask_s && !msb))
+        return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
+    HIP_TRY(lbsg::pack_wflip(w, wf, co, ci, nullptr));
+    if (mask_u) HIP_TRY(lbsg::pack_input(mask_u, mub, P / 4, cu, cu, nullptr));
+    if (mask_s) HIP_TRY(lbsg::pack_input(mask_s, msb, P, cs, cs, nullptr));
+    HIP_TRY(lbsg::conv3_fwd_upadj(gb, wf, dub, dsb, mub, msb, n, h, wd, co, cu, cs, nullptr));
+    HIP_TRY(lbsg::widen(dub, du, P / 4 * cu, nullptr));
+    HIP_TRY(lbsg::widen(dsb, ds, P * cs, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }

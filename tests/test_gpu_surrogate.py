@@ -166,6 +166,49 @@ def test_mfma_conv_with_fused_pooling_is_bitwise(n, h, w, ci, co):
     assert torch.equal(yp.cpu(), want)
 
 
+@pytest.mark.parametrize("n,h,w,cu,cs,co,masked", [(2, 32, 48, 64, 32, 32, True), (1, 64, 64, 128, 64, 64, True),
+                                                     (2, 256, 256, 64, 64, 32, True), (1, 32, 32, 96, 32, 64, True),
+                                                     (1, 32, 64, 64, 32, 32, False)])
+def test_data_gradient_through_upsampling_adjoint_is_bitwise(n, h, w, cu, cs, co, masked):
+    # the decoder's first convolution: its data gradient's up channels summed over 2x2
+    # blocks in the kernel's order ((a + b) + c) + d, its skip channels stored, both masked,
+    # equal the plain data-gradient kernel followed by those steps, bit for bit
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_dgrad_upadj
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int32] * 6
+    dg = L.lbsg_diag_conv3_dgrad
+    dg.restype = ctypes.c_int
+    dg.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int32] * 5
+    rng = np.random.default_rng(cu + 3 * cs + 11 * co)
+    ci = cu + cs
+    dy = bf16_round(rng.normal(size=(n, h, w, co)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
+    mu = rng.normal(size=(n, h // 2, w // 2, cu))
+    ms = rng.normal(size=(n, h, w, cs))
+    dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    dyt, wt, mut, mst = dev(dy), dev(W), dev(mu), dev(ms)
+    du = torch.empty((n, h // 2, w // 2, cu), dtype=torch.float32, device="cuda")
+    ds = torch.empty((n, h, w, cs), dtype=torch.float32, device="cuda")
+    dx = torch.empty((n, h, w, ci), dtype=torch.float32, device="cuda")
+    print(f"case upadj n={n} h={h} w={w} cu={cu} cs={cs} co={co} masked={masked}", flush=True)
+    assert fn(dyt.data_ptr(), wt.data_ptr(), mut.data_ptr() if masked else None,
+              mst.data_ptr() if masked else None, du.data_ptr(), ds.data_ptr(), n, h, w, cu, cs, co) == 0
+    assert dg(dyt.data_ptr(), wt.data_ptr(), dx.data_ptr(), n, h, w, ci, co) == 0
+    x = dx.cpu()
+    up = x[..., :cu]
+    a, b, c, d = up[:, 0::2, 0::2], up[:, 0::2, 1::2], up[:, 1::2, 0::2], up[:, 1::2, 1::2]
+    want_u = (((a + b) + c) + d).to(torch.bfloat16).to(torch.float32)
+    want_s = x[..., cu:].clone()
+    if masked:
+        want_u = torch.where(torch.tensor(mu) > 0, want_u, torch.zeros_like(want_u))
+        want_s = torch.where(torch.tensor(ms) > 0, want_s, torch.zeros_like(want_s))
+    assert torch.equal(du.cpu(), want_u)
+    assert torch.equal(ds.cpu(), want_s)
+
+
 @pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 32)])
 def test_mfma_conv_with_fused_head(n, h, w, ci, co):
     # the BF16 activations are those of the plain kernel; only the FP32 order of the
