@@ -46,15 +46,17 @@ hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* b
                                int Ci, int Co, const float* hw, const float* hb, const float* xin, int cin, float* out,
                                float scale, hipStream_t s);
 // Weight-gradient split partials; bpart (nullable, S x Co floats) receives the
-// bias gradient's split partials, reduced by colsum_reduce.
+// bias gradient's split partials, reduced beside the weights by wgrad_reduce.
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,
                     hipStream_t s, float* bpart = nullptr);
 // conv3_dw of the channel concatenation [nearest 2x upsampling of U (Cu
 // channels, H/2 x Wd/2), Sk (Cs channels, H x Wd)] without forming it.
 hipError_t conv3_dw_upcat(const __bf16* U, const __bf16* Sk, const __bf16* dY, float* part, int S, int N, int H, int Wd,
                           int Cu, int Cs, int Co, hipStream_t s, float* bpart = nullptr);
-hipError_t colsum_reduce(const float* part, int S, int C, float* out, hipStream_t s);
-hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s);
+// bpart / db (both or neither): the bias gradient's split partials [S][Co]
+// are reduced into db[Co] in the same launch
+hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s,
+                        const float* bpart = nullptr, float* db = nullptr);
 hipError_t colsum_bf16(const __bf16* G, long long P, int C, int S, float* part, float* out, hipStream_t s);
 hipError_t gather(const float* field, int H, int W, const int* yx, int k, int crop, const float* cond, int ncond,
                   float* x, float* y, hipStream_t s);

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 // workgroups of the first ci block also form the bias gradient's split
 // partials bpart[s][co] = sum over the split's pixels of dY[p][co]: each thread
 // always stages the same 8 channels and sums them in tile order, then a fixed
-// order over the threads of a channel (reduced over splits by colsum_reduce_k).
+// order over the threads of a channel (reduced over splits by wgrad_reduce_k).
 // UPCAT: X is the channel concatenation [nearest 2x upsampling of X (Cu
 // channels, H/2 x Wd/2), X2 (Ci - Cu channels)], read from its two sources;
 // a 16-channel ci block lies in one of them (Cu is a multiple of 32).
@@ -519,12 +519,28 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
 // dW[co][ci][tap] = sum_s part[s][co][tap][ci] (ci < ci_real).  A block owns 32
 // consecutive partial entries e = (co * 9 + tap) * Ci + ci; its 8 lanes of 32
 // threads take every 8th split, then a fixed-order tree adds the lanes
-// (deterministic).
+// (deterministic).  With bpart, the blocks past the weights reduce the bias
+// gradient's split partials the same way, 32 columns per block:
+// db[co] = sum_s bpart[s][co] (one launch for both).
 __global__ __launch_bounds__(256) void wgrad_reduce_k(const float* __restrict__ part, float* __restrict__ dW, int S,
-                                                      int Co, int Ci, int ci_real) {
+                                                      int Co, int Ci, int ci_real, const float* __restrict__ bpart,
+                                                      float* __restrict__ db) {
     __shared__ float sh[8][32];
     const long long E = (long long)Co * 9 * Ci;
     const int el = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const long long wblocks = (E + 31) / 32;
+    if ((long long)blockIdx.x >= wblocks) {      // a bias block (uniform over the block)
+        const int c = (int)(blockIdx.x - wblocks) * 32 + el;
+        float acc = 0.f;
+        if (c < Co)
+            for (int s = sl; s < S; s += 8) acc += bpart[(size_t)s * Co + c];
+        sh[sl][el] = acc;
+        __syncthreads();
+        if (sl == 0 && c < Co)
+            db[c] = ((sh[0][el] + sh[1][el]) + (sh[2][el] + sh[3][el])) +
+                    ((sh[4][el] + sh[5][el]) + (sh[6][el] + sh[7][el]));
+        return;
+    }
     const long long e = (long long)blockIdx.x * 32 + el;
     float acc = 0.f;
     if (e < E)
@@ -969,13 +985,12 @@ hipError_t conv3_dw_upcat(const __bf16* U, const __bf16* Sk, const __bf16* dY, f
     return conv3_dw_any<true>(U, Sk, Cu, dY, part, S, N, H, Wd, Cu + Cs, Co, s, bpart);
 }
 
-hipError_t colsum_reduce(const float* part, int S, int C, float* out, hipStream_t s) {
-    colsum_reduce_k<<<(C + 3) / 4, 256, 0, s>>>(part, S, C, out);
-    return hipGetLastError();
-}
-
-hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s) {
-    wgrad_reduce_k<<<(int)(((long long)Co * 9 * Ci + 31) / 32), 256, 0, s>>>(part, dW, S, Co, Ci, ci_real);
+hipError_t wgrad_reduce(const float* part, float* dW, int S, int Co, int Ci, int ci_real, hipStream_t s,
+                        const float* bpart, float* db) {
+    if ((bpart == nullptr) != (db == nullptr)) return hipErrorInvalidValue;
+    const long long wblocks = ((long long)Co * 9 * Ci + 31) / 32;
+    const long long bblocks = bpart ? (Co + 31) / 32 : 0;
+    wgrad_reduce_k<<<(int)(wblocks + bblocks), 256, 0, s>>>(part, dW, S, Co, Ci, ci_real, bpart, db);
     return hipGetLastError();
 }
 

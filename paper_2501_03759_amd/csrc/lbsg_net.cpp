@@ -152,11 +152,9 @@ lbch_status conv_back(lbsg_net* n, const Layer& L, const __bf16* z, const __bf16
         HIP_TRY(lbsg::conv3_dw_upcat(z_up, z, g, n->wpart, S, B, H, W, cu, L.ci_pad - cu, L.co, n->stream, bpart));
     else
         HIP_TRY(lbsg::conv3_dw(z, g, n->wpart, S, B, H, W, L.ci_pad, L.co, n->stream, bpart));
-    HIP_TRY(lbsg::wgrad_reduce(n->wpart, n->g + L.offW, S, L.co, L.ci_pad, L.ci_real, n->stream));
-    if (fused_bias)
-        HIP_TRY(lbsg::colsum_reduce(n->cpart, S, L.co, n->g + L.offB, n->stream));
-    else
-        HIP_TRY(lbsg::colsum_bf16(g, P, L.co, 256, n->cpart, n->g + L.offB, n->stream));
+    HIP_TRY(lbsg::wgrad_reduce(n->wpart, n->g + L.offW, S, L.co, L.ci_pad, L.ci_real, n->stream, bpart,
+                               fused_bias ? n->g + L.offB : nullptr));
+    if (!fused_bias) HIP_TRY(lbsg::colsum_bf16(g, P, L.co, 256, n->cpart, n->g + L.offB, n->stream));
     if (dz) {
         if (dz_mask)
             HIP_TRY(lbsg::conv3_fwd_masked(g, L.wf, dz_mask, dz, B, H, W, L.co, L.ci_pad, n->stream));
@@ -700,11 +698,12 @@ extern "C" lbch_status lbsg_diag_conv3_bgrad(const float* x, const float* dy, fl
     __bf16* gb = S.get<__bf16>(P * co);
     float* part = S.get<float>((size_t)splits * co * 9 * ci);
     float* bpart = S.get<float>((size_t)splits * co);
-    if (!xb || !gb || !part || !bpart) return fail(LBCH_E_OOM, "scratch allocation failed");
+    float* dw = S.get<float>((size_t)co * 9 * ci);
+    if (!xb || !gb || !part || !bpart || !dw) return fail(LBCH_E_OOM, "scratch allocation failed");
     HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
     HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
     HIP_TRY(lbsg::conv3_dw(xb, gb, part, splits, n, h, wd, ci, co, nullptr, bpart));
-    HIP_TRY(lbsg::colsum_reduce(bpart, splits, co, db, nullptr));
+    HIP_TRY(lbsg::wgrad_reduce(part, dw, splits, co, ci, ci, nullptr, bpart, db));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }
