@@ -77,6 +77,15 @@ lbch_status lbsg_diag_conv3_dgrad_upadj(const float* dy, const float* w, const f
                                         float* du, float* ds, int32_t n, int32_t h, int32_t wd, int32_t cu,
                                         int32_t cs, int32_t co);
 
+/* The data gradient of an encoder level's first convolution (input: the 2x2
+ * average of a 2H x 2W tensor, weights w[Co][Ci][3][3]) for dy[N][H][W][Co],
+ * passed through the pooling's adjoint in the convolution's epilogue and
+ * accumulated in place: dx2[N][2H][2W][Ci] = bf16(0.25 dx + bf16(dx2)) at the
+ * four children of each pixel, dx the BF16 data gradient; mask (nullable,
+ * laid out as dx2) zeroes the result where <= 0. */
+lbch_status lbsg_diag_conv3_dgrad_pooladj(const float* dy, const float* w, const float* mask, float* dx2, int32_t n,
+                                          int32_t h, int32_t wd, int32_t ci, int32_t co);
+
 /* db[Co] = sum over pixels of dy[p][co] (FP32), as the weight-gradient kernel
  * forms it beside dw (split partials, fixed-order reduction). */
 lbch_status lbsg_diag_conv3_bgrad(const float* x, const float* dy, float* db, int32_t n, int32_t h, int32_t wd,

@@ -33,6 +33,12 @@ hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, 
 // nullable mask (same layout); the full data gradient is never stored
 hipError_t conv3_fwd_upadj(const __bf16* X, const __bf16* Wt, __bf16* dU, __bf16* dS, const __bf16* mask_u,
                            const __bf16* mask_s, int N, int H, int Wd, int Ci, int Cu, int Cs, hipStream_t s);
+// data gradient of a convolution whose input was the 2x2 average of a
+// 2H x 2Wd tensor, passed through the pooling's adjoint and accumulated into
+// dX2 (2H x 2Wd x Co): dX2 = bf16(0.25 dx + dX2) per child, ReLU-masked by
+// mask (nullable, same layout); the level's own data gradient is never stored
+hipError_t conv3_fwd_pooladj(const __bf16* X, const __bf16* Wt, __bf16* dX2, const __bf16* mask, int N, int H, int Wd,
+                            int Ci, int Co, hipStream_t s);
 hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mask, __bf16* Y, int N, int H, int Wd,
                             int Ci, int Co, hipStream_t s);
 // ReLU conv3_fwd writing Y and, to Yp (N x H/2 x Wd/2 x Co), its 2x2
@@ -66,11 +72,6 @@ hipError_t pack_wflip(const float* W, __bf16* Wf, int Co, int Ci, hipStream_t s)
 hipError_t pack_input(const float* x, __bf16* out, long long P, int cin, int cpad, hipStream_t s);
 hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16* out, float* xin, long long P, int cpad,
                          hipStream_t s);
-// the gradient producers below can fold in the ReLU backward of the layer
-// that consumes their result: mask (nullable) is that layer's stored
-// post-activation, laid out as the result, which is zeroed where mask <= 0
-hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s,
-                        const __bf16* mask = nullptr);
 hipError_t head_fwd(const __bf16* d, const float* w, const float* b, const float* xin, int cin, float* out,
                     long long P, int C, float scale, hipStream_t s);
 // mask_dd: dd is ReLU-masked by d (the head's input is a post-ReLU activation)

@@ -85,6 +85,11 @@ __device__ __forceinline__ void interleave_ds_mfma() {
 // upper row), channels from Cu on are stored in Y (H x Wd x (Co - Cu)); Mask2
 // (layout of Yp) and Mask (layout of Y), both nullable, ReLU-mask the two
 // results.  Cu is a multiple of TC, so each workgroup feeds one of them.
+// POOLADJ (data gradient of a convolution whose input was the 2x2 average of
+// a 2H x 2Wd tensor): the output is never formed; each of its pixels goes
+// through the pooling's adjoint into Y (2H x 2Wd x Co), which is accumulated:
+// Y[child] = bf16(0.25 y + Y[child]) for the four children, then ReLU-masked
+// by Mask (nullable, layout of Y).  Each child belongs to one lane.
 // ---------------------------------------------------------------------------
 struct HeadArgs {
     const float* w;      // [Co] head weights
@@ -95,7 +100,8 @@ struct HeadArgs {
     float scale;
 };
 
-template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false, bool UPADJ = false>
+template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false, bool UPADJ = false,
+          bool POOLADJ = false>
 __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
                                                    const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                    __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
@@ -253,7 +259,7 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
     }
     bf16x4 prev[POOL || UPADJ ? CB : 1];   // row r - 1 of the 2x2 block (POOL, UPADJ)
     // the mask of the lane's outputs, loaded at once (data-gradient use)
-    constexpr bool MASKABLE = !RELU && !HEAD && !POOL && !UPADJ;
+    constexpr bool MASKABLE = !RELU && !HEAD && !POOL && !UPADJ && !POOLADJ;
     bf16x4 mk[MASKABLE || UPADJ ? 4 : 1][MASKABLE || UPADJ ? CB : 1];
     const bool up_part = UPADJ && co0 < Cu;   // workgroup-uniform
     if constexpr (UPADJ) {
@@ -305,6 +311,24 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 #pragma unroll
                     for (int j = 0; j < 4; ++j) o[j] = (float)mk[r][c][j] > 0.f ? o[j] : (__bf16)0.f;
                 }
+            }
+            if constexpr (POOLADJ) {
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab) {
+                    const size_t off =
+                        (((size_t)n * 2 * H + 2 * y + (ab >> 1)) * (2 * (size_t)Wd) + 2 * x + (ab & 1)) * Co + co;
+                    const bf16x4 old = *reinterpret_cast<const bf16x4*>(Y + off);
+                    bf16x4 q;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) q[j] = (__bf16)(0.25f * (float)o[j] + (float)old[j]);
+                    if (Mask) {
+                        const bf16x4 m = *reinterpret_cast<const bf16x4*>(Mask + off);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) q[j] = (float)m[j] > 0.f ? q[j] : (__bf16)0.f;
+                    }
+                    *reinterpret_cast<bf16x4*>(Y + off) = q;
+                }
+                continue;
             }
             if constexpr (UPADJ) {
                 if (up_part) {
@@ -723,34 +747,6 @@ __device__ __forceinline__ bf16x8 relu_mask8(const bf16x8 v, const __bf16* __res
     return o;
 }
 
-// dx (N,H,W,C) (+)= avgpool2 adjoint of dy (N,H/2,W/2,C); mask (nullable, laid
-// out as dx): the result is ReLU-masked by it
-__global__ void avgpool2_bwd_k(const __bf16* __restrict__ dy, __bf16* __restrict__ dx, int N, int H, int Wd, int C,
-                               int accumulate, const __bf16* __restrict__ mask) {
-    const int Q = C / 8;
-    const long long total = (long long)N * H * Wd * Q;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long p = i / Q;
-        const int c0 = (int)(i - p * Q) * 8;
-        const int x = (int)(p % Wd);
-        const long long r = p / Wd;
-        const int y = (int)(r % H);
-        const long long nn = r / H;
-        const bf16x8 g = *reinterpret_cast<const bf16x8*>(dy + ((nn * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c0);
-        bf16x8 o;
-        if (accumulate) {
-            const bf16x8 old = *reinterpret_cast<const bf16x8*>(dx + p * C + c0);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) o[k] = (__bf16)(0.25f * (float)g[k] + (float)old[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) o[k] = (__bf16)(0.25f * (float)g[k]);
-        }
-        *reinterpret_cast<bf16x8*>(dx + p * C + c0) = relu_mask8(o, mask, p * C + c0);
-    }
-}
-
 // head: out[p] = phi[p] + scale (b + sum_c w[c] d[p][c])   (phi = input channel 0, fp32)
 __global__ void head_fwd_k(const __bf16* __restrict__ d, const float* __restrict__ w, const float* __restrict__ b,
                            const float* __restrict__ xin, int cin, float* __restrict__ out, long long P, int C,
@@ -924,6 +920,19 @@ hipError_t conv3_fwd_upadj(const __bf16* X, const __bf16* Wt, __bf16* dU, __bf16
     return hipGetLastError();
 }
 
+hipError_t conv3_fwd_pooladj(const __bf16* X, const __bf16* Wt, __bf16* dX2, const __bf16* mask, int N, int H, int Wd,
+                            int Ci, int Co, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Ci % 32 || Co % 32 || !dX2) return hipErrorInvalidValue;
+    const int tiles = N * (H / 16) * (Wd / 16);
+    if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512)
+        conv3_fwd_k<64, false, false, false, false, false, true><<<dim3(tiles, Co / 64), 256, 0, s>>>(
+            X, nullptr, 0, Wt, nullptr, dX2, H, Wd, Ci, Co, HeadArgs{}, nullptr, mask);
+    else
+        conv3_fwd_k<32, false, false, false, false, false, true><<<dim3(tiles, Co / 32), 256, 0, s>>>(
+            X, nullptr, 0, Wt, nullptr, dX2, H, Wd, Ci, Co, HeadArgs{}, nullptr, mask);
+    return hipGetLastError();
+}
+
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s) {
     if (H % 16 || Wd % 16 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || Co % 32) return hipErrorInvalidValue;
@@ -1040,14 +1049,6 @@ hipError_t pack_phi_cond(const float* phi, const float* cond, int ncond, __bf16*
                          hipStream_t s) {
     if (cpad % 8 != 0) return hipErrorInvalidValue;
     pack_phi_cond_k<<<grid_for(P * cpad / 8), 256, 0, s>>>(phi, cond, ncond, out, xin, P, cpad);
-    return hipGetLastError();
-}
-
-hipError_t avgpool2_bwd(const __bf16* dy, __bf16* dx, int N, int H, int Wd, int C, bool accumulate, hipStream_t s,
-                        const __bf16* mask) {
-    if (C % 8 != 0) return hipErrorInvalidValue;
-    avgpool2_bwd_k<<<grid_for((long long)N * H * Wd * C / 8), 256, 0, s>>>(dy, dx, N, H, Wd, C, accumulate ? 1 : 0,
-                                                                            mask);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct Level {
     __bf16 *z = nullptr, *a = nullptr, *e = nullptr;      // encoder block input, mid, output
     __bf16 *da = nullptr, *d = nullptr;                   // decoder block mid, output
     // gradients
-    __bf16 *gz = nullptr, *ga = nullptr, *ge = nullptr, *gda = nullptr, *gd = nullptr;
+    __bf16 *ga = nullptr, *ge = nullptr, *gda = nullptr, *gd = nullptr;
 };
 
 int round32(int c) { return (c + 31) / 32 * 32; }
@@ -258,11 +258,16 @@ lbch_status backward_body(lbsg_net* n, const float* gphi) {
         Level& lv = n->lv[l];
         lbch_status st = conv_back(n, n->layers[2 * l + 1], lv.a, lv.ge, lv.ga, B, h, w, lv.a);
         if (st != LBCH_OK) return st;
-        st = conv_back(n, n->layers[2 * l], lv.z, lv.ga, l > 0 ? lv.gz : nullptr, B, h, w);
+        const Layer& La = n->layers[2 * l];
+        if (l > 0 && La.ci_pad != C[l - 1]) return fail(LBCH_E_STATE, "encoder layer %d: unexpected input width", l);
+        st = conv_back(n, La, lv.z, lv.ga, nullptr, B, h, w);
         if (st != LBCH_OK) return st;
+        // the data gradient of a level's first layer goes straight through the
+        // pooling's adjoint into the finer level's output gradient (which
+        // already holds the skip's part), ReLU-masked by that output
         if (l > 0)
-            HIP_TRY(lbsg::avgpool2_bwd(lv.gz, n->lv[l - 1].ge, B, h * 2, w * 2, C[l - 1], true, n->stream,
-                                       n->lv[l - 1].e));
+            HIP_TRY(lbsg::conv3_fwd_pooladj(lv.ga, La.wf, n->lv[l - 1].ge, n->lv[l - 1].e, B, h, w, La.co, La.ci_pad,
+                                            n->stream));
     }
     return ok();
 }
@@ -334,7 +339,6 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
             lv.d = A.get<__bf16>(P * C[l]);
         }
         if (n->train) {
-            if (l > 0) lv.gz = A.get<__bf16>(P * cz);
             lv.ga = A.get<__bf16>(P * C[l]);
             lv.ge = A.get<__bf16>(P * C[l]);
             if (l < Lv - 1) {
@@ -681,6 +685,28 @@ extern "C" lbch_status lbsg_diag_conv3_dgrad_upadj(const float* dy, const float*
     HIP_TRY(lbsg::conv3_fwd_upadj(gb, wf, dub, dsb, mub, msb, n, h, wd, co, cu, cs, nullptr));
     HIP_TRY(lbsg::widen(dub, du, P / 4 * cu, nullptr));
     HIP_TRY(lbsg::widen(dsb, ds, P * cs, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_dgrad_pooladj(const float* dy, const float* w, const float* mask, float* dx2,
+                                                     int32_t n, int32_t h, int32_t wd, int32_t ci, int32_t co) {
+    if (!dy || !w || !dx2) return fail(LBCH_E_INVALID, "NULL argument");
+    lbch_status st = diag_shape(n, h, wd, ci, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    __bf16* gb = S.get<__bf16>(P * co);
+    __bf16* wf = S.get<__bf16>((size_t)co * 9 * ci);
+    __bf16* db = S.get<__bf16>(4 * P * ci);
+    __bf16* mb = mask ? S.get<__bf16>(4 * P * ci) : nullptr;
+    if (!gb || !wf || !db || (mask && !mb)) return fail(LBCH_E_OOM, "scratch allocation failed");
+    HIP_TRY(lbsg::pack_input(dy, gb, P, co, co, nullptr));
+    HIP_TRY(lbsg::pack_wflip(w, wf, co, ci, nullptr));
+    HIP_TRY(lbsg::pack_input(dx2, db, 4 * P, ci, ci, nullptr));
+    if (mask) HIP_TRY(lbsg::pack_input(mask, mb, 4 * P, ci, ci, nullptr));
+    HIP_TRY(lbsg::conv3_fwd_pooladj(gb, wf, db, mb, n, h, wd, co, ci, nullptr));
+    HIP_TRY(lbsg::widen(db, dx2, 4 * P * ci, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;
 }

@@ -209,6 +209,40 @@ def test_data_gradient_through_upsampling_adjoint_is_bitwise(n, h, w, cu, cs, co
     assert torch.equal(ds.cpu(), want_s)
 
 
+@pytest.mark.parametrize("n,h,w,ci,co,masked", [(2, 32, 48, 32, 64, True), (1, 64, 64, 64, 128, True),
+                                                 (4, 128, 128, 64, 64, True), (1, 16, 32, 96, 32, False)])
+def test_data_gradient_through_pooling_adjoint_is_bitwise(n, h, w, ci, co, masked):
+    # an encoder level's first convolution: its data gradient, spread over the 2x2 children
+    # and accumulated into the finer level's gradient as bf16(0.25 dx + old), then masked,
+    # equals the plain data-gradient kernel followed by those steps, bit for bit
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_dgrad_pooladj
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 5
+    dg = L.lbsg_diag_conv3_dgrad
+    dg.restype = ctypes.c_int
+    dg.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int32] * 5
+    rng = np.random.default_rng(ci + 5 * co + h)
+    dy = bf16_round(rng.normal(size=(n, h, w, co)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.1)
+    base = bf16_round(rng.normal(size=(n, 2 * h, 2 * w, ci)))
+    mask = rng.normal(size=(n, 2 * h, 2 * w, ci))
+    dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    dyt, wt, mt = dev(dy), dev(W), dev(mask)
+    dx2 = dev(base)
+    dx = torch.empty((n, h, w, ci), dtype=torch.float32, device="cuda")
+    print(f"case pooladj n={n} h={h} w={w} ci={ci} co={co} masked={masked}", flush=True)
+    assert fn(dyt.data_ptr(), wt.data_ptr(), mt.data_ptr() if masked else None, dx2.data_ptr(), n, h, w, ci, co) == 0
+    assert dg(dyt.data_ptr(), wt.data_ptr(), dx.data_ptr(), n, h, w, ci, co) == 0
+    up = dx.cpu().repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)
+    want = (0.25 * up + torch.tensor(base, dtype=torch.float32)).to(torch.bfloat16).to(torch.float32)
+    if masked:
+        want = torch.where(torch.tensor(mask) > 0, want, torch.zeros_like(want))
+    assert torch.equal(dx2.cpu(), want)
+
+
 @pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 32)])
 def test_mfma_conv_with_fused_head(n, h, w, ci, co):
     # the BF16 activations are those of the plain kernel; only the FP32 order of the
