@@ -30,7 +30,9 @@ def make_params(nx, ny, precision, sigma=0.01, width=None, eps_w=None, **kw):
 
 
 def oracle_params(p) -> lbm.Params:
-    """The same problem for the oracle (kappa, beta re-derived by the oracle's own eq 5)."""
+    """The same problem for the oracle.  kappa and beta are the library's values (its eq 5
+    helper, which test_sigma_width and the eq 39 golden file pin); every other field is
+    copied as it is."""
     return lbm.Params(nx=p.nx, ny=p.ny, kappa=p.kappa, beta=p.beta, mobility=p.mobility, alpha=p.alpha,
                       aniso_m=p.aniso_m, theta0=p.aniso_theta0, reg=REG_NAMES[p.regularization],
                       eps_reg=p.eps_reg, q_form=QFORM_NAMES[p.q_form], grad_floor=p.grad_floor,
