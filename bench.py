@@ -52,20 +52,29 @@ def measured_traffic(n_nodes: int, precision: str, depth: int, lattice: str = "d
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(seconds_target: float = 15.0):
-    """The oracle (NumPy, FP64, single thread) on a bounded sample of the same workload:
-    a 256 x 256 periodic window of the spinodal field with the workload's parameters."""
+def host_info():
+    """The host the CPU figures were taken on: usable cores (the process's affinity, what
+    `nproc` prints without OMP variables), online CPUs and the CPU model (as `lscpu`)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "online_cpus": os.cpu_count(), "cpu_model": model}
+
+
+def _oracle_window_worker(args):
+    """One process: the oracle (NumPy FP64, one thread) stepping one periodic window for
+    about seconds_target; returns (lattice updates, seconds)."""
+    phi0, prm, seconds_target = args
     from threadpoolctl import threadpool_limits
 
     from oracle import lbm
-    from paper_2501_03759_amd import inputs
-    d = inputs.C5
-    n = 256
-    width = inputs.width_from_eps(d["eps_w"])
-    kappa, beta = lbm.kappa_beta_from_sigma_width(inputs.SIGMA_PAPER, width)
-    p = lbm.Params(nx=n, ny=n, kappa=kappa, beta=beta, mobility=d["mobility"], alpha=d["alpha"],
-                   aniso_m=d["m"], eps_reg=d["eps_reg"])
-    phi0 = inputs.spinodal(d["n"], d["n"], seed=d["seed"], amp=d["amp"])[:n, :n].copy()
+    p = lbm.Params(**prm)
     with threadpool_limits(limits=1):
         f = lbm.initial_populations(phi0, p)
         t0 = time.perf_counter()
@@ -74,8 +83,40 @@ def cpu_baseline(seconds_target: float = 15.0):
             f = lbm.step(f, p)
             steps += 1
         dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of a {n}x{n} window of the workload (FP64 NumPy oracle, 1 thread)"}
+    return phi0.size * steps, dt
+
+
+def cpu_baseline(seconds_target: float = 12.0, max_procs: int = 16):
+    """The oracle (NumPy, FP64) on a bounded sample of the same workload, on every usable host
+    core: one single-threaded oracle process per 256 x 256 window of the 8192^2 spinodal field
+    (the workload's parameters), all running at once for about seconds_target.  Called before
+    the GPU is initialised (the worker processes are forked)."""
+    import multiprocessing as mp
+
+    from oracle import lbm
+    from paper_2501_03759_amd import inputs
+    d = inputs.C5
+    n = 256
+    width = inputs.width_from_eps(d["eps_w"])
+    kappa, beta = lbm.kappa_beta_from_sigma_width(inputs.SIGMA_PAPER, width)
+    prm = dict(nx=n, ny=n, kappa=kappa, beta=beta, mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"],
+               eps_reg=d["eps_reg"])
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    field = inputs.spinodal(d["n"], d["n"], seed=d["seed"], amp=d["amp"])
+    per_row = d["n"] // n
+    wins = [field[(q // per_row) * n:(q // per_row + 1) * n, (q % per_row) * n:(q % per_row + 1) * n].copy()
+            for q in range(procs)]
+    del field
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_window_worker, [(w, prm, seconds_target) for w in wins])
+    updates = sum(u for u, _ in res)
+    wall = max(t for _, t in res)
+    steps = [u // (n * n) for u, _ in res]
+    return {"value": updates / wall / 1e6, "unit": "MLUPS", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} processes, one per core, each stepping its own {n}x{n} periodic window of the "
+                      f"workload's field ({min(steps)}-{max(steps)} steps in {wall:.1f} s; FP64 NumPy oracle, "
+                      f"1 thread each)",
+            "host": host_info()}
 
 
 def cpu_baseline_3d(seconds_target: float = 10.0):
@@ -154,7 +195,7 @@ def cpu_baseline_unet(chans, c_in, seconds_target: float = 10.0):
             "sample": f"{reps} forwards of one {hw}x{hw} patch (float64 NumPy U-Net oracle, 1 thread)"}
 
 
-def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=5):
+def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=20):
     """Practical HBM copy bandwidth (read + write bytes / time) of the library's plain copy kernel."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
     dst = torch.empty_like(src)
@@ -174,80 +215,58 @@ def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=5):
             "verified": ok}
 
 
-def hybrid_workload(args):
-    """Time-to-t of the jump + correction schedule against the plain scheme on the same GPU.
-
-    The 8192^2 FP32 spinodal run (alpha 0.2) is advanced plainly to the onset of coarsening
-    (--hybrid-warm steps), then --hybrid-steps steps are timed twice from that state: plain, and
-    with the hybrid schedule (rate-extrapolated jumps, optionally plus the trained network's
-    residual).  Reports the wall-time ratio, the relative L2 difference of the final fields and
-    whether the free energy, sampled every --hybrid-chunk steps, never rose."""
+def time_to_t(stream, n, steps, warm, K, NC, inner, chunk, net=None, cond=(), note=None, extrapolate=1):
+    """Wall time to advance the 8192^2-recipe FP32 spinodal run (alpha 0.2, seed 5; side n)
+    by `steps` steps after `warm` untimed plain steps, twice on the same GPU: with the plain
+    scheme, and with the jump + correction + rejection schedule (jumps of K steps, NC correction
+    steps, inner projective cycles `inner`; extrapolate = 1: rate-extrapolated jumps, plus the
+    network's residual when `net` is given; extrapolate = 0: the network's own jump).  The free energy of both runs is sampled every `chunk` steps (rounded
+    to whole cycles); the hybrid's cycles are counted per chunk so that rejections can be told
+    apart by phase (spinodal growth, coarsening)."""
     import torch
 
     from paper_2501_03759_amd import inputs, lbch
 
+    note = note or (lambda m: None)
     d = inputs.C5
-    n = args.n
     p = lbch.default_params(nx=n, ny=n, precision=lbch.FP32,
                             sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"])),
                             mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
-    torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()
-    K, NC = args.hybrid_jump, args.hybrid_correct
     cyc = K + NC
-    chunk = max(cyc, args.hybrid_chunk // cyc * cyc)
-    net, cond = None, []
-    train_s = 0.0
+    chunk = max(cyc, chunk // cyc * cyc)
     with torch.cuda.stream(stream):
-        if args.surrogate:
-            from paper_2501_03759_amd import lbsg, surrogate_train as st
-            t0 = time.time()
-            runs = st.draw_runs(64, seed=1)
-            X, Y = st.generate(runs, 256, 60000, 300000, 4000, K, 256, 1, seed=7, stream=stream,
-                               log=lambda m: print(m, file=sys.stderr, flush=True), extrapolate=True)
-            tr = lbsg.Surrogate((32, 32), 1 + st.N_COND, 16, 256, 256, train=True, seed=0, stream=stream,
-                                out_scale=0.02)
-            st.train(tr, X, Y, epochs=8, batch=16, lr=1e-3, margin=0, log=lambda m: None)
-            w = tr.get_params()
-            tr.close()
-            del X, Y
-            torch.cuda.empty_cache()
-            net = lbsg.Surrogate((32, 32), 1 + st.N_COND, 1, n, n, train=False, seed=0, stream=stream,
-                                 out_scale=0.02)
-            net.set_params(w)
-            cond = list(st.conditioning(d["alpha"], d["m"], 0.0))
-            train_s = time.time() - t0
-        def note(msg):
-            print(msg, file=sys.stderr, flush=True)
-
+        phi0 = inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"])
         plain = lbch.Sim(p, stream)
-        plain.init(inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"]))
-        for k in range(0, args.hybrid_warm, 20000):
-            plain.step(min(20000, args.hybrid_warm - k))
+        plain.init(phi0)
+        for k in range(0, warm, 20000):
+            plain.step(min(20000, warm - k))
             plain.synchronize()
             note(f"warm-up: step {plain.nstep}")
-        blob = plain.save_state()
         hyb = lbch.Sim(p, stream)
-        hyb.load_state(blob)
-        del blob
+        if warm:
+            blob = plain.save_state()
+            hyb.load_state(blob)
+            del blob
+        else:
+            hyb.init(phi0)
+        del phi0
 
         def run(advance):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             done = 0
-            while done < args.hybrid_steps:
-                k = min(chunk, args.hybrid_steps - done)
+            while done < steps:
+                k = min(chunk, steps - done)
                 advance(k)
                 done += k
             torch.cuda.synchronize()
             return time.perf_counter() - t0
 
         e_plain, e_hyb = [plain.free_energy()[0]], [hyb.free_energy()[0]]
-        inner = [int(v) for v in args.hybrid_inner.split(",")]
         o = lbch.hybrid_opts(jump=K, correct_steps=NC, windows=4, window_interior=192, window_margin=64,
-                             tol_window=1e-2, tol_energy=0.0, check_every=4, extrapolate=1, cond=cond,
-                             inner_steps=inner[0], inner_jump=inner[1])
-        totals = {}
+                             tol_window=1e-2, tol_energy=0.0, check_every=4, extrapolate=extrapolate,
+                             cond=list(cond), inner_steps=inner[0], inner_jump=inner[1])
+        totals, phases = {}, []
 
         def adv_plain(k):
             plain.step(k)
@@ -262,27 +281,171 @@ def hybrid_workload(args):
                     totals[f] = max(totals.get(f, 0.0), v)
                 elif f != "last_energy":
                     totals[f] = totals.get(f, 0) + v
+            phases.append([int(hyb.nstep), int(st_.cycles), int(st_.accepted), int(st_.rejected_energy),
+                           int(st_.rejected_window)])
             e_hyb.append(hyb.free_energy()[0])
             note(f"hybrid: step {hyb.nstep}, E = {e_hyb[-1]:.6f}, accepted {st_.accepted}/{st_.cycles}")
 
         t_plain = run(adv_plain)
         t_hyb = run(adv_hyb)
         pa, ph = plain.phi(), hyb.phi()
-        rel = float(np.linalg.norm(ph - pa) / np.linalg.norm(pa))
-    out = {
-        "metric": "time-to-t speedup of the jump + correction schedule over the plain scheme (1 GPU)",
-        "value": round(t_plain / t_hyb, 3), "unit": "x", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "f32", "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
-        "config": {"workload": f"spinodal-{n}x{n}-fp32-coarsening", "warm_steps": args.hybrid_warm,
-                   "timed_steps": args.hybrid_steps, "jump": K, "correct_steps": NC, "windows": 4,
-                   "check_every": 4, "jump_form": "rate extrapolation" + (" + network residual" if net else ""),
-                   "inner_steps": inner[0], "inner_jump": inner[1]},
-        "plain_s": round(t_plain, 3), "hybrid_s": round(t_hyb, 3), "rel_l2": rel,
+        plain.close()
+        hyb.close()
+    rel = float(np.linalg.norm(ph - pa) / np.linalg.norm(pa))
+    return {
+        "workload": f"spinodal-{n}x{n}-fp32", "from_step": warm, "steps": steps,
+        "plain_s": round(t_plain, 3), "hybrid_s": round(t_hyb, 3), "speedup": round(t_plain / t_hyb, 3),
+        "rel_l2": rel, "rel_l2_ok": rel <= 1e-2,
         "energy_nonincreasing": {"plain": bool(np.all(np.diff(e_plain) <= 0)),
                                  "hybrid": bool(np.all(np.diff(e_hyb) <= 0)), "samples": len(e_hyb)},
         "energy_final": {"plain": e_plain[-1], "hybrid": e_hyb[-1]},
-        "stats": totals, "surrogate_train_s": round(train_s, 1),
+        "jump_form": ("rate extrapolation" + (" + network residual" if net is not None else "")) if extrapolate
+                     else "network",
+        "jump": K, "correct_steps": NC, "inner_steps": inner[0], "inner_jump": inner[1], "windows": 4,
+        "check_every": 4, "tol_energy": 0.0, "tol_window": 1e-2,
+        "cycles": int(totals.get("cycles", 0)), "accepted": int(totals.get("accepted", 0)),
+        "rejected_energy": int(totals.get("rejected_energy", 0)),
+        "rejected_window": int(totals.get("rejected_window", 0)),
+        "max_window_err": totals.get("max_window_err", 0.0),
+        "ms_split": {k: round(totals.get(k, 0.0), 1) for k in ("ms_surrogate", "ms_correct", "ms_checks", "ms_plain")},
+        "per_chunk": {"columns": ["end_step", "cycles", "accepted", "rejected_energy", "rejected_window"],
+                      "rows": phases},
     }
+
+
+def hybrid_workload(args):
+    """Time-to-t of the jump + correction schedule against the plain scheme on the same GPU
+    (the 8192^2 FP32 spinodal run, alpha 0.2): --hybrid-warm untimed plain steps, then
+    --hybrid-steps steps timed twice (see time_to_t), optionally with a trained network's
+    residual added to the rate-extrapolated jump (--surrogate)."""
+    import torch
+
+    from paper_2501_03759_amd import inputs
+
+    d = inputs.C5
+    n = args.n
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    K, NC = args.hybrid_jump, args.hybrid_correct
+    net, cond = None, []
+    train_s = 0.0
+
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if args.surrogate:
+        from paper_2501_03759_amd import lbsg, surrogate_train as st
+        with torch.cuda.stream(stream):
+            t0 = time.time()
+            runs = st.draw_runs(64, seed=1)
+            X, Y = st.generate(runs, 256, 60000, 300000, 4000, K, 256, 1, seed=7, stream=stream, log=note,
+                               extrapolate=True)
+            tr = lbsg.Surrogate((32, 32), 1 + st.N_COND, 16, 256, 256, train=True, seed=0, stream=stream,
+                                out_scale=0.02)
+            st.train(tr, X, Y, epochs=8, batch=16, lr=1e-3, margin=0, log=lambda m: None)
+            w = tr.get_params()
+            tr.close()
+            del X, Y
+            torch.cuda.empty_cache()
+            net = lbsg.Surrogate((32, 32), 1 + st.N_COND, 1, n, n, train=False, seed=0, stream=stream,
+                                 out_scale=0.02)
+            net.set_params(w)
+            cond = list(st.conditioning(d["alpha"], d["m"], 0.0))
+            train_s = time.time() - t0
+    inner = [int(v) for v in args.hybrid_inner.split(",")]
+    r = time_to_t(stream, n, args.hybrid_steps, args.hybrid_warm, K, args.hybrid_correct, inner,
+                  args.hybrid_chunk, net=net, cond=cond, note=note)
+    out = {
+        "metric": "time-to-t speedup of the jump + correction schedule over the plain scheme (1 GPU)",
+        "value": r["speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
+        "config": {"workload": f"spinodal-{n}x{n}-fp32-time-to-t", "warm_steps": args.hybrid_warm,
+                   "timed_steps": args.hybrid_steps, "jump": K, "correct_steps": NC, "windows": 4,
+                   "check_every": 4, "jump_form": r["jump_form"], "inner_steps": inner[0], "inner_jump": inner[1]},
+        "time_to_t": r, "surrogate_train_s": round(train_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def learned_workload(args):
+    """The learned surrogate at its stated configuration: the 5-level periodic U-Net (32, 64, 128,
+    256, 256 channels; phi plus alpha, cos / sin(m theta0), m / 6 planes; BF16 storage, FP32
+    accumulation) trained on the GPU by the library's kernels to predict phi(t + 200) on 256^2
+    crops of 1024^2 FP32 spinodal runs (one ensemble of --c4-runs runs, snapshots every 1000
+    steps up to 50000, 8 crops each; alpha ~ U[0, 0.3], m in {4, 6}, theta0 ~ U[0, 2 pi)), then
+    measured on held-out runs (other seeds) against the plain scheme, beside the jump without the
+    network and the rate-extrapolated jump.  Reports the 8192^2 inference time and, with
+    --c4-hybrid, the time-to-t of the schedule whose jump is the network's."""
+    import torch
+
+    from paper_2501_03759_amd import inputs, lbsg, surrogate_train as st
+
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    chans, K, crop, margin = (32, 64, 128, 256, 256), 200, 256, 32
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    out = {"metric": "surrogate held-out relative L2 of phi(t + 200) (1 GPU)", "unit": "rel-L2", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "bf16", "data": "synthetic (seeded 1024^2 spinodal runs)",
+           "config": {"workload": "unet5-32-256-c4", "chans": list(chans), "jump": K, "crop": crop,
+                      "loss_margin": margin, "runs": args.c4_runs, "heldout_runs": 6, "epochs": args.c4_epochs}}
+    with torch.cuda.stream(stream):
+        t0 = time.time()
+        if args.c4_weights:
+            w = np.load(args.c4_weights)
+            hist = []
+        else:
+            runs = st.draw_runs(args.c4_runs, seed=1)
+            X, Y = st.generate(runs, 1024, 1000, 50000, 1000, K, crop, 8, seed=7, stream=stream, log=note)
+            out["config"]["pairs"] = int(X.shape[0])
+            net = lbsg.Surrogate(chans, 1 + st.N_COND, 16, crop, crop, train=True, seed=0, stream=stream,
+                                 out_scale=0.02)
+            t1 = time.time()
+            hist = st.train(net, X, Y, epochs=args.c4_epochs, batch=16, lr=args.c4_lr, margin=margin, log=note)
+            torch.cuda.synchronize()
+            out["train_s"] = round(time.time() - t1, 1)
+            w = net.get_params()
+            net.close()
+            del X, Y
+            torch.cuda.empty_cache()
+            if args.c4_save:
+                np.save(args.c4_save, w)
+        out["loss_history"] = [float(v) for v in hist]
+        held = st.draw_runs(6, seed=2)
+        Xh, Yh, Rh, Th = st.generate(held, 1024, 1000, 50000, 7000, K, crop, 8, seed=8, stream=stream, log=note,
+                                     with_rate=True)
+        ev = lbsg.Surrogate(chans, 1 + st.N_COND, 8, crop, crop, train=False, seed=0, stream=stream, out_scale=0.02)
+        ev.set_params(w)
+        out["heldout"] = st.evaluate_jumps(ev, Xh, Yh, Rh, K, Th, split=10000, margin=margin)
+        ev.close()
+        del Xh, Yh, Rh
+        torch.cuda.empty_cache()
+        out["value"] = round(out["heldout"]["all"]["network"], 6)
+        # inference on the whole 8192^2 periodic field (the hybrid's jump)
+        n = args.n
+        inf = lbsg.Surrogate(chans, 1 + st.N_COND, 1, n, n, train=False, seed=0, stream=stream, out_scale=0.02)
+        inf.set_params(w)
+        phi = torch.empty((n, n), dtype=torch.float32, device="cuda").uniform_(-1, 1)
+        o = torch.empty_like(phi)
+        cond = list(st.conditioning(inputs.C5["alpha"], inputs.C5["m"], 0.0))
+        for _ in range(2):
+            inf.predict(phi.data_ptr(), cond, n, n, o.data_ptr())
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(5):
+            inf.predict(phi.data_ptr(), cond, n, n, o.data_ptr())
+        e.record(stream)
+        e.synchronize()
+        out["inference_ms_8192"] = round(a.elapsed_time(e) / 5, 2)
+        del phi, o
+        if args.c4_hybrid:
+            inner = [int(v) for v in args.c4_hybrid_inner.split(",")]
+            out["time_to_t"] = time_to_t(stream, n, args.time_to_t_steps, args.hybrid_warm, K, args.c4_correct,
+                                         inner, args.hybrid_chunk, net=inf, cond=cond, note=note,
+                                         extrapolate=0)
+        inf.close()
+    out["wall_s"] = round(time.time() - t0, 1)
     print(json.dumps(out), flush=True)
 
 
@@ -479,9 +642,11 @@ def main():
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block (ensemble: [,depth], a fixed shape instead of the autotuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n3", type=int, default=256, help="box side of the D3Q15 workload")
-    ap.add_argument("--workload", choices=["step", "step3d", "hybrid", "ensemble", "surrogate"], default="step",
+    ap.add_argument("--workload", choices=["step", "step3d", "hybrid", "ensemble", "surrogate", "learned"],
+                    default="step",
                     help="step: throughput of lbch_step (the default line); hybrid: time-to-t of the jump "
-                         "schedule; ensemble: the 512-member batch; surrogate: the network's MFMA throughput")
+                         "schedule; ensemble: the 512-member batch; surrogate: the network's MFMA throughput; "
+                         "learned: the 5-level network trained and measured on held-out runs")
     ap.add_argument("--hybrid-warm", type=int, default=80000)
     ap.add_argument("--hybrid-steps", type=int, default=200000)
     ap.add_argument("--hybrid-jump", type=int, default=400)
@@ -490,6 +655,17 @@ def main():
     ap.add_argument("--hybrid-inner", type=str, default="4,16",
                     help="inner_steps,inner_jump: projective steps of the populations inside the correction phase")
     ap.add_argument("--surrogate", action="store_true", help="hybrid: add the trained network's residual")
+    ap.add_argument("--c4-runs", type=int, default=50, help="learned: training runs (50 x 50 snapshots x 8 crops)")
+    ap.add_argument("--c4-epochs", type=int, default=40)
+    ap.add_argument("--c4-lr", type=float, default=1e-3)
+    ap.add_argument("--c4-save", type=str, default="", help="learned: write the trained parameters (.npy)")
+    ap.add_argument("--c4-weights", type=str, default="", help="learned: load parameters instead of training")
+    ap.add_argument("--c4-hybrid", action="store_true", help="learned: also the time-to-t with the network's jump")
+    ap.add_argument("--c4-correct", type=int, default=10, help="learned hybrid: correction steps per jump")
+    ap.add_argument("--c4-hybrid-inner", type=str, default="0,0")
+    ap.add_argument("--time-to-t-steps", type=int, default=200000,
+                    help="default line: steps of the plain / hybrid time-to-t comparison from the initial field "
+                         "(0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -506,9 +682,15 @@ def main():
     if args.workload == "surrogate":
         surrogate_workload(args)
         return
+    if args.workload == "learned":
+        learned_workload(args)
+        return
     if args.workload == "step3d":
         step3d_workload(args)
         return
+
+    # the oracle's CPU figure first: its worker processes are forked before the GPU is touched
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     import torch
 
@@ -522,7 +704,6 @@ def main():
                             mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    copy = copy_ceiling(torch, lbch, stream)
     sim = lbch.Sim(p, stream)
     sim.set_time_blocking(args.depth)
     if args.tiling:
@@ -531,25 +712,35 @@ def main():
     phi0 = inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"])
     sim.init(phi0)
     del phi0
+    copy = copy_ceiling(torch, lbch, stream)
+    depth = args.depth
     sim.step(args.warmup)
     sim.synchronize()
 
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the K timed steps, in up to five windows of whole launches (HIP events on the step's
+    # stream between them); value and roofline come from the whole region
+    nwin = 5 if args.steps >= 5 * depth else 1
+    sizes = [args.steps // nwin // depth * depth] * nwin
+    sizes[-1] += args.steps - sum(sizes)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nwin + 1)]
     torch.cuda.synchronize()
-    start.record(stream)
-    sim.step(args.steps)
-    end.record(stream)
-    end.synchronize()
+    t_wall = time.perf_counter()
+    ev[0].record(stream)
+    for w in range(nwin):
+        sim.step(sizes[w])
+        ev[w + 1].record(stream)
+    ev[-1].synchronize()
     torch.cuda.synchronize()
-    ms_total = start.elapsed_time(end)
+    wall_ms = (time.perf_counter() - t_wall) * 1e3
+    ms_total = ev[0].elapsed_time(ev[-1])
     ms_step = ms_total / args.steps
+    win_ms = [ev[w].elapsed_time(ev[w + 1]) / sizes[w] for w in range(nwin)]
     _, mass, lo, hi = sim.moments(want_phi=False)
     tiling = sim.tiling()
     sim.close()
 
     nodes = n * n
     mlups = nodes * args.steps / (ms_total * 1e-3) / 1e6
-    depth = args.depth
     # every launch advances `depth` steps (an odd tail step, if any, is one
     # single-step launch of about half the time: the average below counts it
     # as half a launch)
@@ -558,15 +749,22 @@ def main():
     alg_bytes = bytes_per_update * nodes * depth       # per launch
     min_bytes = bytes_per_update * nodes               # one read + one write of the state per launch
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(nodes, args.precision, depth)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(nodes, args.precision, depth),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "basis": f"algorithmic: {bytes_per_update} B per lattice update x {depth} updates per node per "
+                         "launch (effective bandwidth; a launch moves the state once per launch)",
                 "kernel": "step2_fused" if depth == 2 else "step_fused",
                 "launch_ms": round(launch_ms, 4), "updates_per_launch": depth * nodes,
                 "bytes_per_update": bytes_per_update, "algorithmic_bytes_per_launch": alg_bytes,
                 "min_bytes_per_launch": min_bytes,
                 "min_bytes_GBs": round(min_bytes / (launch_ms * 1e-3) / 1e9, 1),
                 "min_bytes_frac": round(min_bytes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if traffic:
+        # the HBM bytes the counters saw per launch, over this run's launch time
+        roofline["traffic_GBs"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    med = float(np.median(win_ms))
     out = {
         "metric": "MLUPS & % HBM peak (1 GPU)",
         "value": round(mlups, 1),
@@ -584,11 +782,25 @@ def main():
                    "alpha": d["alpha"], "m": d["m"], "regularization": "willmore", "eps_reg": d["eps_reg"],
                    "mobility": d["mobility"], "time_steps_per_launch": depth, "tiling": list(tiling)},
         "roofline": roofline,
+        "windows": {"count": nwin, "steps": sizes, "ms_per_step": [round(v, 4) for v in win_ms],
+                    "median_ms_per_step": round(med, 4), "median_MLUPS": round(nodes / (med * 1e-3) / 1e6, 1),
+                    "spread": round((max(win_ms) - min(win_ms)) / med, 4), "wall_ms": round(wall_ms, 3)},
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},
         "hbm_copy": copy,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if args.time_to_t_steps > 0 and args.precision == "fp32":
+        # the second half of the metric: time to the workload's final step, plain against the
+        # jump + correction schedule, both from the initial field
+        def note(msg):
+            print(msg, file=sys.stderr, flush=True)
+        try:
+            out["time_to_t"] = time_to_t(stream, n, args.time_to_t_steps, 0, args.hybrid_jump, args.hybrid_correct,
+                                         [int(v) for v in args.hybrid_inner.split(",")], args.hybrid_chunk,
+                                         note=note)
+        except Exception as exc:                  # the throughput line stands on its own
+            out["time_to_t"] = {"error": f"{type(exc).__name__}: {exc}"}
     print(json.dumps(out), flush=True)
 
 

@@ -193,9 +193,12 @@ lbch_status lbch_init_device(lbch_sim* sim, const void* phi0_dev, int32_t dtype,
 /* Advances nsteps (>= 0) time steps of eq 17: per node phi (eq 22), the
  * eq 26 stencils, the anisotropic chemical potential (eqs 13/15/16), the
  * modified equilibrium (eq 18), the source (eq 19), the MRT collision in
- * moment space (eqs 17, 23, 25) and periodic streaming.  One fused kernel
- * launch per step, enqueued on the simulation's stream; returns without
- * waiting.  Before init -> LBCH_E_STATE. */
+ * moment space (eqs 17, 23, 25) and periodic streaming.  Fused kernel
+ * launches enqueued on the simulation's stream, each advancing the time
+ * blocking depth of steps (lbch_set_time_blocking: two steps per launch by
+ * default on D2Q9 grids above 512^2 nodes, one otherwise; an odd remainder is
+ * one single-step launch); returns without waiting.  Before init ->
+ * LBCH_E_STATE. */
 lbch_status lbch_step(lbch_sim* sim, int64_t nsteps);
 
 /* Two time steps in one two-step launch, storing the populations

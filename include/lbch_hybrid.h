@@ -91,7 +91,12 @@ lbch_status lbch_hybrid_default_opts(lbch_hybrid_opts* opts);
 
 /* Advances sim by nsteps (>= 0) with the cycle above; stats (nullable) are
  * filled (not accumulated).  net may be NULL only with dry_run or
- * extrapolate.  Synchronises. */
+ * extrapolate.  Synchronises.  The first call on a simulation allocates the
+ * schedule's workspace, which stays with the simulation until lbch_destroy: a
+ * third population buffer (the snapshot), three FP32 fields of the grid and
+ * the shadow-window ensemble; later calls allocate nothing unless the window
+ * count or size changes (then the ensemble is rebuilt).  A failed allocation
+ * returns LBCH_E_DEVICE before the state is touched. */
 lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const lbch_hybrid_opts* opts, int64_t nsteps,
                                 lbch_hybrid_stats* stats);
 

@@ -13,10 +13,41 @@ conv3 pads periodically (circular), stride 1; avgpool2 is the 2x2 mean; up2
 repeats each pixel 2x2; concat puts the upsampled tensor first.
 Weights of a 3x3 conv: W[co, ci, ky, kx] with tap (ky, kx) reading pixel
 (y + ky - 1, x + kx - 1).
+
+Storage precision (``bf16=True``): the surrogate's configuration stores weights and
+activations in BF16 and accumulates in FP32.  With the option on, every tensor the
+definition above names is rounded to BF16 where it is formed, and nothing else:
+the input planes fed to the first convolution, the 3x3 weights, each convolution's
+post-ReLU output, each pooled tensor; in the backward pass the gradient with respect
+to each of those tensors (the head's, each data gradient, the upsampling adjoint's
+block sums, the skip gradient after the pooling adjoint has been added to it).
+Biases, the 1x1 head, the residual base and every sum stay in float64.  With the
+option off the network is the plain float64 definition.
 """
 from __future__ import annotations
 
 import numpy as np
+
+
+def bf16(x):
+    """Round to the nearest BF16 value (8 significant bits, ties to even), from float64.
+
+    x = m 2^e with 0.5 <= |m| < 1 (frexp); m 2^8 rounded half-to-even (rint) keeps 8 bits.
+    Normal range only (the network's values are far from BF16's limits)."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)
+    return np.ldexp(np.rint(m * 256.0), e - 8)
+
+
+def _ident(x):
+    return x
+
+
+def _pix(a):
+    """[B, H, W, C] as a [B*H*W, C] matrix: each tap is one library matrix product (on
+    contiguous operands, which the library multiplies blockwise; a strided weight view
+    falls back to a slow elementwise loop)."""
+    return a.reshape(-1, a.shape[-1])
 
 
 def conv3(x, W, b):
@@ -25,7 +56,7 @@ def conv3(x, W, b):
     for ky in range(3):
         for kx in range(3):
             xs = np.roll(x, shift=(1 - ky, 1 - kx), axis=(1, 2))
-            out += xs @ W[:, :, ky, kx].T
+            out += (_pix(xs) @ np.ascontiguousarray(W[:, :, ky, kx].T)).reshape(out.shape)
     return out + b
 
 
@@ -35,8 +66,9 @@ def conv3_backward(x, W, dout):
     for ky in range(3):
         for kx in range(3):
             xs = np.roll(x, shift=(1 - ky, 1 - kx), axis=(1, 2))
-            dW[:, :, ky, kx] = np.einsum("nyxo,nyxi->oi", dout, xs)
-            dx += np.roll(dout @ W[:, :, ky, kx], shift=(ky - 1, kx - 1), axis=(1, 2))
+            dW[:, :, ky, kx] = _pix(dout).T @ _pix(xs)
+            dx += np.roll((_pix(dout) @ np.ascontiguousarray(W[:, :, ky, kx])).reshape(x.shape),
+                          shift=(ky - 1, kx - 1), axis=(1, 2))
     return dx, dW, dout.sum(axis=(0, 1, 2))
 
 
@@ -87,23 +119,25 @@ def init_params(levels, chans, c_in, seed=0):
     return params
 
 
-def forward(params, x, levels, chans, scale=1.0):
-    """Returns (phi_pred [B,H,W], cache)."""
-    cache = {}
+def forward(params, x, levels, chans, scale=1.0, bf16=False):
+    """Returns (phi_pred [B,H,W], cache).  bf16: storage rounding (module docstring)."""
+    r = globals()["bf16"] if bf16 else _ident
+    cache = {"round": r}
 
     def block(z, tag):
-        a_pre = conv3(z, params[tag + "a.W"], params[tag + "a.b"])
-        a = relu(a_pre)
-        b_pre = conv3(a, params[tag + "b.W"], params[tag + "b.b"])
-        out = relu(b_pre)
-        cache[tag] = (z, a_pre, a, b_pre)
+        Wa, Wb = r(params[tag + "a.W"]), r(params[tag + "b.W"])
+        a_pre = conv3(z, Wa, params[tag + "a.b"])
+        a = r(relu(a_pre))
+        b_pre = conv3(a, Wb, params[tag + "b.b"])
+        out = r(relu(b_pre))
+        cache[tag] = (z, a_pre, a, b_pre, Wa, Wb)
         return out
 
     enc = []
-    z = x
+    z = r(x)
     for l in range(levels):
         if l > 0:
-            z = avgpool2(enc[-1])
+            z = r(avgpool2(enc[-1]))
         enc.append(block(z, f"enc{l}"))
     d = enc[-1]
     for l in range(levels - 2, -1, -1):
@@ -119,21 +153,22 @@ def forward(params, x, levels, chans, scale=1.0):
 
 def backward(params, cache, dphi, levels, chans):
     """Gradients of sum(dphi * phi_pred) w.r.t. every parameter (and the input)."""
+    r = cache["round"]
     grads = {}
     d = cache["head"]
     W = params["head.W"][:, :, 0, 0]
     dy = cache["scale"] * dphi[..., None]
     grads["head.W"] = np.einsum("nyxo,nyxi->oi", dy, d)[:, :, None, None]
     grads["head.b"] = dy.sum(axis=(0, 1, 2))
-    dd = dy @ W
+    dd = r(dy @ W)
 
     def block_back(tag, dout):
-        z, a_pre, a, b_pre = cache[tag]
+        z, a_pre, a, b_pre, Wa, Wb = cache[tag]
         g = dout * (b_pre > 0)
-        da, grads[tag + "b.W"], grads[tag + "b.b"] = conv3_backward(a, params[tag + "b.W"], g)
-        g = da * (a_pre > 0)
-        dz, grads[tag + "a.W"], grads[tag + "a.b"] = conv3_backward(z, params[tag + "a.W"], g)
-        return dz
+        da, grads[tag + "b.W"], grads[tag + "b.b"] = conv3_backward(a, Wb, g)
+        g = r(da) * (a_pre > 0)
+        dz, grads[tag + "a.W"], grads[tag + "a.b"] = conv3_backward(z, Wa, g)
+        return r(dz)
 
     enc = cache["enc"]
     denc = [np.zeros_like(e) for e in enc]
@@ -141,13 +176,13 @@ def backward(params, cache, dphi, levels, chans):
         dz = block_back(f"dec{l}", dd)
         cu = chans[l + 1]
         denc[l] += dz[..., cu:]
-        dd = up2_backward(dz[..., :cu])
+        dd = r(up2_backward(dz[..., :cu]))
     denc[levels - 1] += dd
     dx = None
     for l in range(levels - 1, -1, -1):
         dz = block_back(f"enc{l}", denc[l])
         if l > 0:
-            denc[l - 1] += avgpool2_backward(dz)
+            denc[l - 1] = r(denc[l - 1] + avgpool2_backward(dz))
         else:
             dx = dz
     dx = dx.copy()

@@ -1,6 +1,7 @@
 // C-ABI layer of liblbch: parameter handling, buffers, launches, reductions,
 // checkpointing.  See include/lbch.h for the contract of every entry point.
 #include "../../include/lbch.h"
+#include "../../include/lbch_batch.h"
 #include "../../include/lbch_diag.h"
 #include "lbch_internal.h"
 
@@ -404,12 +405,11 @@ lbch_status check_init(const lbch_sim* s) {
 }
 
 void free_all(lbch_sim* s) {
-    if (s->f[0]) (void)hipFree(s->f[0]);
-    if (s->f[1]) (void)hipFree(s->f[1]);
-    if (s->phi64) (void)hipFree(s->phi64);
-    if (s->partials) (void)hipFree(s->partials);
-    if (s->result) (void)hipFree(s->result);
-    if (s->bad) (void)hipFree(s->bad);
+    if (s->hyb_win) (void)lbch_batch_destroy(s->hyb_win);
+    for (void* p : {(void*)s->f[0], (void*)s->f[1], (void*)s->phi64, (void*)s->partials, (void*)s->result,
+                    (void*)s->bad, s->hyb_snap, (void*)s->hyb_phi[0], (void*)s->hyb_phi[1], (void*)s->hyb_phi[2],
+                    (void*)s->hyb_dsum, (void*)s->hyb_part, (void*)s->hyb_wphi})
+        if (p) (void)hipFree(p);
 }
 
 struct StateHeader {

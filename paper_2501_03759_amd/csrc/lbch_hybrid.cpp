@@ -42,17 +42,36 @@ extern "C" lbch_status lbch_hybrid_default_opts(lbch_hybrid_opts* o) {
 
 namespace {
 
-struct Buffers {
-    std::vector<void*> p;
-    ~Buffers() {
-        for (void* q : p) (void)hipFree(q);
+// The schedule's workspace, kept with the simulation (freed by lbch_destroy):
+// allocated by the first call, the window ensemble again only when the window
+// count or size changes.
+lbch_status ensure_workspace(lbch_sim* sim, const lbch_hybrid_opts* o, int side) {
+    const size_t fbytes = (size_t)sim->g.plane * 9 * sim->esize;
+    const size_t nbytes = (size_t)sim->g.nx * sim->g.ny * sizeof(float);
+    auto get = [](void** p, size_t bytes) -> hipError_t { return *p ? hipSuccess : hipMalloc(p, bytes); };
+    HIP_TRY(get(&sim->hyb_snap, fbytes));
+    for (float*& q : sim->hyb_phi) HIP_TRY(get((void**)&q, nbytes));
+    HIP_TRY(get((void**)&sim->hyb_dsum, 8 * sizeof(double)));
+    HIP_TRY(get((void**)&sim->hyb_part, (size_t)kRedBlocks * 4 * sizeof(double)));
+    if (o->windows > 0 && (sim->hyb_windows != o->windows || sim->hyb_side != side)) {
+        if (sim->hyb_win) {
+            (void)lbch_batch_destroy(sim->hyb_win);
+            sim->hyb_win = nullptr;
+        }
+        if (sim->hyb_wphi && sim->hyb_side != side) {
+            (void)hipFree(sim->hyb_wphi);
+            sim->hyb_wphi = nullptr;
+        }
+        sim->hyb_windows = sim->hyb_side = 0;
+        HIP_TRY(get((void**)&sim->hyb_wphi, (size_t)side * side * sizeof(float)));
+        std::vector<lbch_params> mp(o->windows, sim->p);
+        for (auto& q : mp) q.nx = q.ny = side;
+        ST_TRY(lbch_batch_create(mp.data(), o->windows, sim->stream, &sim->hyb_win));
+        sim->hyb_windows = o->windows;
+        sim->hyb_side = side;
     }
-    hipError_t get(void** out, size_t bytes) {
-        hipError_t e = hipMalloc(out, bytes);
-        if (e == hipSuccess) p.push_back(*out);
-        return e;
-    }
-};
+    return LBCH_OK;
+}
 
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -101,29 +120,11 @@ extern "C" lbch_status lbch_hybrid_advance(lbch_sim* sim, lbsg_net* net, const l
     } tiling_guard{sim, sim->t};
     if (o->inner_steps > 0 && o->inner_jump > 0 && sim->t.depth != 2) ST_TRY(lbch_set_time_blocking(sim, 2));
     lbch_hybrid_stats st{};
-    Buffers B;
-    void *snap = nullptr, *phi = nullptr, *phin = nullptr, *phi1 = nullptr, *dsum = nullptr, *part = nullptr,
-         *wphi = nullptr;
+    ST_TRY(ensure_workspace(sim, o, side));
+    void *snap = sim->hyb_snap, *phi = sim->hyb_phi[0], *phin = sim->hyb_phi[1], *phi1 = sim->hyb_phi[2],
+         *dsum = sim->hyb_dsum, *part = sim->hyb_part, *wphi = sim->hyb_wphi;
+    lbch_batch* win = o->windows > 0 ? sim->hyb_win : nullptr;
     const size_t fbytes = (size_t)sim->g.plane * 9 * sim->esize;
-    HIP_TRY(B.get(&snap, fbytes));
-    HIP_TRY(B.get(&phi, N * sizeof(float)));
-    HIP_TRY(B.get(&phin, N * sizeof(float)));
-    if (o->extrapolate) HIP_TRY(B.get(&phi1, N * sizeof(float)));
-    HIP_TRY(B.get(&dsum, 8 * sizeof(double)));
-    HIP_TRY(B.get(&part, (size_t)kRedBlocks * 4 * sizeof(double)));
-    lbch_batch* win = nullptr;
-    if (o->windows > 0) {
-        HIP_TRY(B.get(&wphi, (size_t)side * side * sizeof(float)));
-        std::vector<lbch_params> mp(o->windows, sim->p);
-        for (auto& q : mp) q.nx = q.ny = side;
-        ST_TRY(lbch_batch_create(mp.data(), o->windows, s, &win));
-    }
-    struct BatchGuard {
-        lbch_batch* b;
-        ~BatchGuard() {
-            if (b) lbch_batch_destroy(b);
-        }
-    } guard{win};
     // Three population buffers rotate: the simulation's pair f[cur], f[cur ^ 1] and one
     // outside it, which holds the snapshot of the cycle's start state while a cycle runs
     // (no copy): the first write of a cycle goes to a pair buffer that is not the snapshot,

@@ -104,6 +104,43 @@ Tiling make_tiling(int nx, int ny, int nt, int hc, int depth = 1, int esize = 4,
 constexpr int kRedBlocks = 1024;   // partial-sum blocks of every reduction
 constexpr int kRedThreads = 256;
 
+// Workgroup reduction of NV float64 values per lane (kind: 0 = sum, 1 = min,
+// 2 = max) for blocks of kRedThreads lanes, stored by lane 0 to out[0..NV).
+// Each wavefront reduces its 64 lanes by lane exchange (butterfly over 32, 16,
+// ..., 1 lanes; every lane ends with the same value), then lane 0 combines the
+// wavefronts' results in wavefront order: one LDS exchange and one barrier, a
+// fixed order, so the result is deterministic.
+template <int NV>
+__device__ __forceinline__ void block_reduce_waves(double (&v)[NV], const int (&kind)[NV], double* out) {
+    constexpr int kWaves = kRedThreads / 64;
+    __shared__ double sh[NV][kWaves];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const double b = __shfl_xor(v[q], off, 64);
+            v[q] = kind[q] == 0 ? v[q] + b : (kind[q] == 1 ? fmin(v[q], b) : fmax(v[q], b));
+        }
+    }
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sh[q][wave] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double a = sh[q][0];
+            for (int w = 1; w < kWaves; ++w) {
+                const double b = sh[q][w];
+                a = kind[q] == 0 ? a + b : (kind[q] == 1 ? fmin(a, b) : fmax(a, b));
+            }
+            out[q] = a;
+        }
+    }
+}
+
 // Hybrid-schedule helpers (lbch_kernels.hip)
 hipError_t launch_sum_f32(const float* x, long long n, double* partials, double* out, hipStream_t s);
 hipError_t launch_add_f32(float* x, long long n, const double* num, const double* den_minus, double inv_n,
@@ -197,6 +234,17 @@ struct lbch_sim {
     lbch::StepCoef3<float> c3f{};
     long long nodes = 0;             // nx * ny * nz
     int nq = 9;                      // populations per node
+    // workspace of lbch_hybrid_advance: allocated by its first call, kept until
+    // lbch_destroy (a third population buffer for the snapshot, FP32 fields of
+    // phi, the jumped phi and phi one step on, sums, and the shadow-window
+    // ensemble of hyb_windows windows of side hyb_side with their phi output)
+    void* hyb_snap = nullptr;
+    float* hyb_phi[3] = {nullptr, nullptr, nullptr};
+    double* hyb_dsum = nullptr;
+    double* hyb_part = nullptr;
+    float* hyb_wphi = nullptr;
+    struct lbch_batch* hyb_win = nullptr;
+    int hyb_windows = 0, hyb_side = 0;
 };
 
 // Ensemble helper used by the hybrid schedule: member `member` of batch b

@@ -56,12 +56,14 @@ def run_params(spec: RunSpec, side: int, precision=lbch.FP32):
 
 def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: int, jump: int, crop: int,
              crops_per_snapshot: int, seed: int, stream=None, log=print, extrapolate: bool = False,
-             amp: float = 0.05):
+             amp: float = 0.05, with_rate: bool = False):
     """Returns device tensors X [N, crop, crop, 1 + N_COND], Y [N, crop, crop] (torch float32).
 
     Y is phi(t + jump); with extrapolate it is phi(t + jump) - jump (phi(t+1) - phi(t)), the residual
     the network adds to the rate-extrapolated jump of the hybrid schedule (one plain step gives the
-    rate, as there)."""
+    rate, as there).  with_rate: a third tensor R [N, crop, crop] holds phi(t + 1) of the same crops
+    (for measuring the rate-extrapolated jump beside the network), and the function returns
+    (X, Y, R, T) with T [N] the snapshot time of each pair."""
     import torch
     rng = np.random.default_rng(seed)
     times = list(range(t_first, t_last + 1, every))
@@ -70,9 +72,13 @@ def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: i
     Y = torch.empty((n, crop, crop), dtype=torch.float32, device="cuda")
     field = torch.empty((side, side), dtype=torch.float32, device="cuda")
     per = len(runs) * crops_per_snapshot
-    if extrapolate:
+    rate = extrapolate or with_rate
+    if rate:
         T0 = torch.empty((per, crop, crop), dtype=torch.float32, device="cuda")
         T1 = torch.empty_like(T0)
+    if with_rate:
+        R = torch.empty((n, crop, crop), dtype=torch.float32, device="cuda")
+        tt = np.repeat(np.array(times, dtype=np.int64), per)
     params = [run_params(r, side) for r in runs]
     t0 = time.time()
     with lbch.Batch(params, stream) as b:
@@ -94,15 +100,17 @@ def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: i
                 b.phi_device(k, field.data_ptr(), lbch.FP32)
                 lbsg.gather(field.data_ptr(), side, side, yx, crop, cond,
                             X[row + k * crops_per_snapshot].data_ptr(),
-                            T0[k * crops_per_snapshot].data_ptr() if extrapolate else None, stream)
+                            T0[k * crops_per_snapshot].data_ptr() if rate else None, stream)
             steps = jump
-            if extrapolate:
+            if rate:
                 b.step(1)
                 steps -= 1
                 for k in range(len(runs)):
                     b.phi_device(k, field.data_ptr(), lbch.FP32)
                     lbsg.gather(field.data_ptr(), side, side, offsets[k], crop, None, None,
                                 T1[k * crops_per_snapshot].data_ptr(), stream)
+                if with_rate:
+                    R[row:row + per].copy_(T1)
             b.step(steps)
             t += jump
             for k, r in enumerate(runs):
@@ -116,6 +124,8 @@ def generate(runs: list[RunSpec], side: int, t_first: int, t_last: int, every: i
         b.synchronize()
     log(f"generated {n} pairs ({len(runs)} runs x {len(times)} snapshots x {crops_per_snapshot} crops) "
         f"in {time.time() - t0:.1f} s")
+    if with_rate:
+        return X, Y, R, tt
     return X, Y
 
 
@@ -165,3 +175,43 @@ def evaluate(net: lbsg.Surrogate, X, Y, margin: int, batch: int = 16):
         num_id += float(((X[i:i + batch, s, s, 0].double() - tgt) ** 2).sum())
         den += float((tgt ** 2).sum())
     return math.sqrt(num_net / den), math.sqrt(num_id / den)
+
+
+def evaluate_jumps(net: lbsg.Surrogate, X, Y, R, jump: int, T=None, split: int = 0, batch: int = 8,
+                   margin: int = 0):
+    """Held-out relative L2 errors of three predictions of phi(t + jump) against the plain
+    scheme's: the network, no jump (phi(t)), and the rate-extrapolated jump phi(t) + jump
+    (phi(t+1) - phi(t)); each also relative to the size of the true change
+    |phi(t + jump) - phi(t)| (1 = no better than not jumping).  With T and split, the same
+    for the pairs with t < split and t >= split.  Errors are taken over the crop interiors
+    (margin pixels dropped on every side: a crop is not periodic at its edges)."""
+    import torch
+    n, crop = X.shape[0], X.shape[1]
+    out = torch.empty((batch, crop, crop), dtype=torch.float32, device="cuda")
+    acc = {}
+
+    def add(key, k, v):
+        acc.setdefault(key, np.zeros(5))
+        acc[key][k] += v
+
+    for i in range(0, n - batch + 1, batch):
+        net.forward(X[i:i + batch].data_ptr(), batch, crop, crop, out.data_ptr())
+        torch.cuda.synchronize()
+        s = slice(margin, crop - margin)
+        tgt = Y[i:i + batch, s, s].double()
+        x0 = X[i:i + batch, s, s, 0].double()
+        ext = x0 + jump * (R[i:i + batch, s, s].double() - x0)
+        terms = [float(((out[:, s, s].double() - tgt) ** 2).sum()), float(((x0 - tgt) ** 2).sum()),
+                 float(((ext - tgt) ** 2).sum()), float((tgt ** 2).sum()), float(((tgt - x0) ** 2).sum())]
+        keys = ["all"]
+        if T is not None and split:
+            keys.append("early" if T[i] < split else "late")
+        for key in keys:
+            for k, v in enumerate(terms):
+                add(key, k, v)
+    res = {}
+    for key, a in acc.items():
+        res[key] = {"network": math.sqrt(a[0] / a[3]), "no_jump": math.sqrt(a[1] / a[3]),
+                    "rate_extrapolation": math.sqrt(a[2] / a[3]),
+                    "network_vs_change": math.sqrt(a[0] / a[4]), "rate_extrapolation_vs_change": math.sqrt(a[2] / a[4])}
+    return res

@@ -196,3 +196,29 @@ def test_extrapolating_step_errors():
         with pytest.raises(L.LbchError) as ei:
             s.step_extrapolated(8.0)
         assert ei.value.status == L.E_UNSUPPORTED
+
+
+def test_workspace_is_kept_across_calls_and_rebuilt_for_other_windows():
+    # The schedule's workspace (snapshot buffer, fields, window ensemble) stays with the
+    # simulation: calls with the same options, then other window counts and sizes, give the
+    # same trajectory as the same calls on a simulation that never ran the schedule before
+    # each of them (a fresh copy of the state for every call).
+    import torch
+    L = lb()
+    stream = torch.cuda.Stream()
+    sim, _ = spinodal_sim(384, stream=stream, steps=1000)
+    opts = [dict(windows=3, window_interior=96, window_margin=48), dict(windows=3, window_interior=96, window_margin=48),
+            dict(windows=2, window_interior=96, window_margin=48), dict(windows=2, window_interior=64, window_margin=32),
+            dict(windows=0)]
+    for k, w in enumerate(opts):
+        print(f"case hybrid workspace call {k} {w}", flush=True)
+        o = L.hybrid_opts(jump=100, correct_steps=10, tol_window=1e-2, extrapolate=1, tol_energy=1e-3, seed=k + 1, **w)
+        fresh = L.Sim(sim.params, stream)
+        fresh.load_state(sim.save_state())
+        st_a = L.hybrid_advance(sim, None, o, 220)
+        st_b = L.hybrid_advance(fresh, None, o, 220)
+        assert (st_a.cycles, st_a.accepted, st_a.rejected_window) == (st_b.cycles, st_b.accepted, st_b.rejected_window)
+        assert st_a.max_window_err == st_b.max_window_err
+        assert np.array_equal(sim.phi(), fresh.phi())
+        fresh.close()
+    sim.close()

@@ -173,3 +173,46 @@ def test_spinodal_eq42_separates_and_coarsens():
     # after the noise has been smoothed (sample 1): separation grows, interfaces thin out
     assert all(y >= x for x, y in zip(frac[1:], frac[2:])) and frac[-1] >= 0.25
     assert all(y <= x for x, y in zip(crossings[1:], crossings[2:])) and crossings[-1] <= 0.8 * crossings[1]
+
+
+def _grid64_case():
+    n = 64
+    dx = 100.0 / n
+    x = np.arange(n) * dx
+    X, Y = np.meshgrid(x, x)
+    return dict(dx=dx, dt=dx * dx, alpha=0.2, nx=n, ny=n), np.tanh(2.0 * (25.0 - np.hypot(X - 50.0, Y - 50.0)) / 5.0)
+
+
+PREFIX_CASES = {
+    "eq41-iso": (dict(alpha=0.0), lambda: inputs.two_droplets(100, 100, 5.0)),
+    "eq41-aniso": (dict(alpha=0.3), lambda: inputs.two_droplets(100, 100, 5.0)),
+    "eq42": (dict(alpha=0.3), lambda: np.random.default_rng(42).uniform(-1.0, 1.0, (100, 100))),
+    "grid64": _grid64_case,
+}
+
+
+@pytest.mark.parametrize("case", sorted(PREFIX_CASES))
+def test_paper_workload_first_200_steps_match_the_oracle(case):
+    # The regression tests above run these initial fields far beyond what the oracle can
+    # follow; their first 200 FP64 steps are compared with the oracle node by node (the
+    # single-simulation path, and for the eq 41 pair the ensemble path as well).
+    from tests.common import oracle_phi
+    L = lb()
+    spec = PREFIX_CASES[case]
+    kw, phi0 = spec() if callable(spec) else (spec[0], spec[1]())
+    p = L.default_params(**kw)
+    print(f"case prefix {case} {kw}", flush=True)
+    want = oracle_phi(phi0, p, 200)
+    with L.Sim(p) as s:
+        s.init(phi0)
+        s.step(200)
+        got = s.phi()
+    assert np.abs(got - want).max() <= 1e-11, np.abs(got - want).max()
+    if case.startswith("eq41"):
+        b = L.Batch([L.default_params(alpha=0.0), L.default_params(**kw)])
+        for k in range(2):
+            b.init(k, phi0)
+        b.step(200)
+        got_b = b.moments(1)[0]
+        b.close()
+        assert np.abs(got_b - want).max() <= 1e-11

@@ -36,27 +36,68 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def run_both(levels, chans, hw, bias_shift, seed):
+def calibrate_biases(params, x, levels, chans, k=5.0):
+    """Biases that put every channel's pre-activation k standard deviations away from the
+    ReLU kink, on alternating sides (even channels mostly active, odd ones mostly zero), set
+    layer by layer on the BF16-storage reference's own forward pass.  Near the kink, a
+    pre-activation that FP32 and float64 accumulation round to different BF16 values flips
+    its ReLU decision, and such flips cascade through the later layers; away from it the
+    comparison measures the network's composition."""
+    names = [n for n, *_ in unet.layer_shapes(levels, chans, x.shape[-1]) if n != "head"]
+    for n in names:
+        params[n + ".b"] = np.zeros_like(params[n + ".b"])
+    for n in names:
+        _, cache = unet.forward(params, x, levels, chans, bf16=True)
+        z, a_pre, a, b_pre, Wa, Wb = cache[n[:-1]]
+        pre = a_pre if n.endswith("a") else b_pre
+        mu, sd = pre.mean(axis=(0, 1, 2)), pre.std(axis=(0, 1, 2))
+        side = np.where(np.arange(pre.shape[-1]) % 2 == 0, 1.0, -1.0)
+        params[n + ".b"] = bf16_round(side * k * sd - mu)
+
+
+def run_both(levels, chans, hw, bias_shift, seed, B=2, bf16=True, conditioned=False):
+    """The HIP network and the float64 reference on the same BF16 parameters and inputs;
+    bf16: the reference rounds its stored tensors to BF16 where the definition forms them
+    (its storage-precision option), else it is the plain float64 network.
+
+    conditioned: a case whose sums do not cancel, so that relative differences measure the
+    composition rather than amplified rounding noise: the input is shaped as the surrogate's
+    (phi, then four constant conditioning planes), biases from calibrate_biases, positive
+    head weights, and an output gradient of mostly one sign (1 + 0.5 N(0, 1), as for a
+    prediction biased high).  Otherwise: normal inputs and output gradient, the
+    initialisation's biases (plus bias_shift)."""
     import torch
     from paper_2501_03759_amd import lbsg
-    c_in, B = 5, 2
+    c_in = 5
     rng = np.random.default_rng(seed)
     net = lbsg.Surrogate(chans, c_in, B, hw, hw, train=True, seed=1)
     params = unet.init_params(levels, chans, c_in, seed=seed)
     params["head.W"] *= 0.5
+    if conditioned:
+        params["head.W"] = np.abs(params["head.W"])
     for k in params:
         if k.endswith(".b") and not k.startswith("head"):
             params[k] = params[k] + bias_shift
         params[k] = bf16_round(params[k])
+    if conditioned:
+        x = np.empty((B, hw, hw, c_in))
+        x[..., 0] = rng.normal(size=(B, hw, hw)) * 0.5
+        x[..., 1:] = [0.2, 0.7, -0.7, 2.0 / 3.0]
+        x = bf16_round(x)
+        calibrate_biases(params, x, levels, chans)
+    else:
+        x = bf16_round(rng.normal(size=(B, hw, hw, c_in)) * 0.5)
     net.set_params(dict_to_flat(params, levels, chans, c_in))
-    x = bf16_round(rng.normal(size=(B, hw, hw, c_in)) * 0.5)
     xt = torch.tensor(x, dtype=torch.float32, device="cuda")
     out = torch.empty((B, hw, hw), dtype=torch.float32, device="cuda")
     net.forward(xt.data_ptr(), B, hw, hw, out.data_ptr())
     torch.cuda.synchronize()
-    pred_ref, cache = unet.forward(params, x, levels, chans)
+    pred_ref, cache = unet.forward(params, x, levels, chans, bf16=bf16)
     got = out.cpu().numpy().astype(np.float64)
     dphi = rng.normal(size=(B, hw, hw))
+    if conditioned:
+        dphi = 1.0 + 0.5 * dphi
+    dphi = dphi.astype(np.float32).astype(np.float64)
     dt = torch.tensor(dphi, dtype=torch.float32, device="cuda")
     grads = torch.empty(net.nparam, dtype=torch.float32, device="cuda")
     net.backward(dt.data_ptr(), grads.data_ptr())
@@ -209,8 +250,10 @@ def test_data_gradient_through_upsampling_adjoint_is_bitwise(n, h, w, cu, cs, co
     assert torch.equal(ds.cpu(), want_s)
 
 
+# (4, 128, 128, 128, 64): 256 tiles x 2 blocks of 64 output channels reach the 64-channel workgroups
 @pytest.mark.parametrize("n,h,w,ci,co,masked", [(2, 32, 48, 32, 64, True), (1, 64, 64, 64, 128, True),
-                                                 (4, 128, 128, 64, 64, True), (1, 16, 32, 96, 32, False)])
+                                                 (4, 128, 128, 64, 64, True), (1, 16, 32, 96, 32, False),
+                                                 (4, 128, 128, 128, 64, True)])
 def test_data_gradient_through_pooling_adjoint_is_bitwise(n, h, w, ci, co, masked):
     # an encoder level's first convolution: its data gradient, spread over the 2x2 children
     # and accumulated into the finer level's gradient as bf16(0.25 dx + old), then masked,
@@ -328,14 +371,47 @@ def test_mfma_weight_gradient_of_upsampled_concat(n, h, w, cu, cs, co):
     assert np.abs(dw - dw_ref).max() <= 1e-5 * np.abs(dw_ref).max()
 
 
-def test_forward_and_gradients_default_init():
-    # Whole-network composition (pool / upsample / concat adjoints, layer order) against the
-    # float64 reference.  Each operator is exact on BF16 inputs (tests above); here BF16
-    # rounding of activations and gradients flips ReLU masks of near-zero pre-activations and
-    # the differences compound layer by layer in the backward pass, so the bound is on the
-    # typical output channel and on the whole tensor.  A composition mistake (a wrong channel
-    # offset, a missing adjoint) gives O(1) errors.
-    y_gpu, y_ref, g_gpu, g_ref = run_both(2, (32, 64), 32, bias_shift=0.0, seed=2)
+# (levels, channels, side, batch): every level count the kernels serve up to the 5-level,
+# 32 -> 256-channel configuration with its 16 x 16 bottom level, and the 3-level
+# (32, 64, 96) net whose intermediate decoder level (upsampling adjoint into a decoder
+# gradient, not the bottom encoder's) the 2-level net does not have
+WHOLE_NETS = [(2, (32, 64), 32, 2), (3, (32, 64, 96), 64, 2), (4, (32, 64, 128, 128), 128, 2),
+              (5, (32, 64, 128, 256, 256), 256, 2)]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("levels,chans,hw,B", WHOLE_NETS)
+def test_forward_and_gradients_match_bf16_storage_reference(levels, chans, hw, B):
+    # Whole-network composition (pool / upsample / concat adjoints, layer order, the fused
+    # epilogues, every ReLU mask) against the float64 reference with BF16 storage at the
+    # definition's tensor boundaries: what differs is FP32 against float64 accumulation
+    # inside each operator.  The output and every parameter tensor's gradient within 2e-2
+    # relative L2; a composition mistake (a wrong channel offset, a missing adjoint or mask)
+    # gives O(1) errors.  The case is the conditioned one of run_both.  Where the
+    # pre-activations sit near the ReLU kink, accumulation-order differences flip ReLU
+    # decisions and BF16 roundings, the flips cascade through the later layers, and sums of
+    # terms of both signs (a bias gradient under a random output gradient) magnify them: a
+    # CPU emulation (the reference with its convolution results rounded to FP32) differs from
+    # the reference itself by up to 5 % in the 3-level net's gradients at the
+    # initialisation's parameters, and by at most 2e-4 in the conditioned case.  The
+    # unconditioned case is the float64-network test below.
+    print(f"case whole net levels={levels} chans={chans} side={hw} batch={B}", flush=True)
+    y_gpu, y_ref, g_gpu, g_ref = run_both(levels, chans, hw, bias_shift=0.0, seed=2 + levels, B=B,
+                                          conditioned=True)
+    worst = max((rel(g_gpu[k], g_ref[k]), k) for k in g_ref)
+    print(f"  output rel {rel(y_gpu, y_ref):.2e}, worst gradient rel {worst[0]:.2e} ({worst[1]})", flush=True)
+    assert rel(y_gpu, y_ref) < 2e-2
+    for name in g_ref:
+        assert rel(g_gpu[name], g_ref[name]) < 2e-2, (name, rel(g_gpu[name], g_ref[name]))
+
+
+def test_forward_and_gradients_against_float64_network():
+    # The same composition against the plain float64 network (no storage rounding): the
+    # output residual stays within a few BF16 steps; parameter gradients are sums over
+    # pixels of terms of both signs, where rounding the activations to 8 bits moves the
+    # typical channel by several percent, so only the typical channel and the whole tensor
+    # are bounded here (the per-tensor 2e-2 bar is the test above)
+    y_gpu, y_ref, g_gpu, g_ref = run_both(2, (32, 64), 32, bias_shift=0.0, seed=2, bf16=False)
     assert rel(y_gpu, y_ref) < 3e-2
     for name in g_ref:
         if name.startswith("head"):
@@ -349,7 +425,7 @@ def test_forward_and_gradients_default_init():
 def test_forward_with_wide_first_level():
     # 128 channels at the first level: the output head runs as its own kernel (the fused
     # epilogue covers 32 or 64), and the pooled / upsampled paths carry 128 channels
-    y_gpu, y_ref, g_gpu, g_ref = run_both(2, (128, 64), 32, bias_shift=0.0, seed=4)
+    y_gpu, y_ref, g_gpu, g_ref = run_both(2, (128, 64), 32, bias_shift=0.0, seed=4, bf16=False)
     assert rel(y_gpu, y_ref) < 3e-2
     assert rel(g_gpu["head.W"], g_ref["head.W"]) < 2e-2
 

@@ -29,16 +29,17 @@ def test_pool_and_upsample_are_adjoint_up_to_scale():
 
 @pytest.mark.parametrize("levels,chans,scale", [(2, (4, 6), 1.0), (3, (3, 4, 5), 0.3)])
 def test_gradients_match_finite_differences(levels, chans, scale):
+    # the plain float64 network (storage rounding off, passed explicitly)
     c_in = 3
     params = unet.init_params(levels, chans, c_in, seed=3)
     x = RNG.normal(size=(2, 8, 8, c_in))
     target = RNG.normal(size=(2, 8, 8))
 
     def loss_of(p, xx):
-        pred, _ = unet.forward(p, xx, levels, chans, scale)
+        pred, _ = unet.forward(p, xx, levels, chans, scale, bf16=False)
         return unet.masked_mse(pred, target, 1)[0]
 
-    pred, cache = unet.forward(params, x, levels, chans, scale)
+    pred, cache = unet.forward(params, x, levels, chans, scale, bf16=False)
     _, g = unet.masked_mse(pred, target, 1)
     grads, dx = unet.backward(params, cache, g, levels, chans)
     h = 1e-6
@@ -72,3 +73,48 @@ def test_residual_output_identity_when_head_is_zero():
     x = RNG.normal(size=(1, 4, 4, 2))
     pred, _ = unet.forward(params, x, 2, (4, 6))
     assert np.array_equal(pred, x[..., 0])
+
+
+def test_bf16_rounding_matches_the_library_conversion():
+    # torch's float32 -> bfloat16 conversion rounds to nearest, ties to even; on float32
+    # inputs (exact ties included) the oracle's float64 rounding must give the same values
+    import torch
+    rng = np.random.default_rng(5)
+    a = (rng.normal(size=4000) * np.exp(rng.uniform(-20, 20, size=4000))).astype(np.float32)
+    bits = a.view(np.uint32).copy()
+    ties = bits[:1000] & np.uint32(0xFFFF0000) | np.uint32(0x8000)     # exactly halfway
+    near = bits[1000:2000] & np.uint32(0xFFFF0000) | np.uint32(0x7FFF)  # just below halfway
+    bits[:1000], bits[1000:2000] = ties, near
+    a = bits.view(np.float32)
+    want = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    got = unet.bf16(a.astype(np.float64))
+    assert np.array_equal(got, want)
+    assert np.array_equal(unet.bf16(np.array([0.0, -0.0, 1.0, -3.5])), [0.0, -0.0, 1.0, -3.5])
+
+
+def test_bf16_option_rounds_the_stored_tensors_and_stays_close_to_float64():
+    levels, chans, c_in = 3, (4, 6, 8), 3
+    params = unet.init_params(levels, chans, c_in, seed=7)
+    x = RNG.normal(size=(2, 16, 16, c_in))
+    dphi = RNG.normal(size=(2, 16, 16))
+    p64, c64 = unet.forward(params, x, levels, chans, 0.5)
+    p16, c16 = unet.forward(params, x, levels, chans, 0.5, bf16=True)
+    for tag in [f"enc{l}" for l in range(levels)] + [f"dec{l}" for l in range(levels - 1)]:
+        z, a_pre, a, b_pre, Wa, Wb = c16[tag]
+        for t in (z, a, Wa, Wb):
+            assert np.array_equal(unet.bf16(t), t), tag
+    for e in c16["enc"]:
+        assert np.array_equal(unet.bf16(e), e)
+    # storage at 8 significant bits moves the output residual by O(2^-8) per layer.  The
+    # parameter gradients are sums over pixels of terms of both signs, which magnifies the
+    # per-element rounding (here up to ~0.4 relative on 512 pixels), so they are only
+    # checked to stay of the float64 network's size and direction
+    def rel(u, v):
+        return np.linalg.norm(u - v) / np.linalg.norm(v)
+    assert 1e-5 < rel(p16 - x[..., 0], p64 - x[..., 0]) < 3e-2
+    g64, _ = unet.backward(params, c64, dphi, levels, chans)
+    g16, _ = unet.backward(params, c16, dphi, levels, chans)
+    for k in g64:
+        if k != "head.b":
+            assert 0 < rel(g16[k], g64[k]) < 0.6, k
+    assert g16["head.b"] == g64["head.b"]
