@@ -195,7 +195,7 @@ def cpu_baseline_unet(chans, c_in, seconds_target: float = 10.0):
             "sample": f"{reps} forwards of one {hw}x{hw} patch (float64 NumPy U-Net oracle, 1 thread)"}
 
 
-def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=20):
+def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=300):
     """Practical HBM copy bandwidth (read + write bytes / time) of the library's plain copy kernel."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
     dst = torch.empty_like(src)

@@ -307,32 +307,6 @@ __global__ __launch_bounds__(256) void init3_k(const P* __restrict__ phi0, T* __
     }
 }
 
-namespace {
-
-template <int NV>
-__device__ __forceinline__ void block_reduce3(double (&v)[NV], const int (&kind)[NV], double* out) {
-    __shared__ double sh[NV][kRedThreads];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const double a = sh[q][threadIdx.x], b = sh[q][threadIdx.x + s];
-                sh[q][threadIdx.x] = kind[q] == 0 ? a + b : (kind[q] == 1 ? fmin(a, b) : fmax(a, b));
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) out[q] = sh[q][0];
-    }
-}
-
-}  // namespace
-
 // phi = sum_i f*_i(x - e_i) (eq 22) in float64: optional dense copy [z][y][x]
 // and partial {sum, min, max, non-finite count}.
 template <typename T>
@@ -363,7 +337,7 @@ __global__ __launch_bounds__(kRedThreads) void moments3_k(const T* __restrict__ 
             v[3] += 1.0;
         }
     }
-    block_reduce3<4>(v, kind, partials + 4 * blockIdx.x);
+    block_reduce_waves<4>(v, kind, partials + 4 * blockIdx.x);
 }
 
 // Discrete free energy (eq 7, d = 3) from phi [z][y][x] (float64): partials of
@@ -411,7 +385,7 @@ __global__ __launch_bounds__(kRedThreads) void energy3_k(const double* __restric
             v[3] += 1.0;
         }
     }
-    block_reduce3<4>(v, kind, partials + 4 * blockIdx.x);
+    block_reduce_waves<4>(v, kind, partials + 4 * blockIdx.x);
 }
 
 // canonical pre-collision populations f_i(x) = f*_i(x - e_i) <-> internal layout

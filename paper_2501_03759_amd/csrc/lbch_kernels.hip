@@ -780,35 +780,9 @@ __global__ __launch_bounds__(256) void init_eq(const P* __restrict__ phi0, T* __
 }
 
 // ---------------------------------------------------------------------------
-// Reductions (float64 partials in a fixed order: deterministic).
+// Reductions: float64 partials per workgroup (block_reduce_waves), combined by
+// finalize_k, in a fixed order: deterministic.
 // ---------------------------------------------------------------------------
-namespace {
-
-template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const int (&kind)[NV], double* out) {
-    // kind: 0 = sum, 1 = min, 2 = max
-    __shared__ double sh[NV][kRedThreads];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const double a = sh[q][threadIdx.x], b = sh[q][threadIdx.x + s];
-                sh[q][threadIdx.x] = kind[q] == 0 ? a + b : (kind[q] == 1 ? fmin(a, b) : fmax(a, b));
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) out[q] = sh[q][0];
-    }
-}
-
-}  // namespace
-
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void moments_k(const T* __restrict__ fin, const Grid g, void* phi_out,
                                                          int out_dtype, double* partials) {
@@ -836,7 +810,7 @@ __global__ __launch_bounds__(kRedThreads) void moments_k(const T* __restrict__ f
             v[3] += 1.0;
         }
     }
-    block_reduce_store<4>(v, kind, partials + 4 * blockIdx.x);
+    block_reduce_waves<4>(v, kind, partials + 4 * blockIdx.x);
 }
 
 __global__ __launch_bounds__(kRedThreads) void energy_k(const double* __restrict__ phi, const Grid g,
@@ -873,7 +847,7 @@ __global__ __launch_bounds__(kRedThreads) void energy_k(const double* __restrict
             v[3] += 1.0;
         }
     }
-    block_reduce_store<4>(v, kind, partials + 4 * blockIdx.x);
+    block_reduce_waves<4>(v, kind, partials + 4 * blockIdx.x);
 }
 
 // Combines nparts partial records of nvals values; kinds[q]: 0 sum, 1 min, 2 max.
@@ -891,7 +865,7 @@ __global__ __launch_bounds__(kRedThreads) void finalize_k(const double* __restri
             v[q] = kind[q] == 0 ? v[q] + b : (kind[q] == 1 ? fmin(v[q], b) : fmax(v[q], b));
         }
     }
-    block_reduce_store<4>(v, kind, out);
+    block_reduce_waves<4>(v, kind, out);
 }
 
 // Canonical pre-collision populations f_i(x) = f*_i(x - c_i) <-> internal layout.
@@ -1254,7 +1228,7 @@ __global__ __launch_bounds__(kRedThreads) void sum_f32_k(const float* __restrict
     const int kind[4] = {0, 0, 0, 0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         v[0] += (double)x[i];
-    block_reduce_store<4>(v, kind, partials + 4 * blockIdx.x);
+    block_reduce_waves<4>(v, kind, partials + 4 * blockIdx.x);
 }
 
 // x += (num[0] - den_minus[0]) * inv_n   (exact mass projection: shift by the mean defect)
@@ -1318,7 +1292,7 @@ __global__ __launch_bounds__(kRedThreads) void window_err_k(const float* __restr
         v[0] += (a - b) * (a - b);
         v[1] += b * b;
     }
-    block_reduce_store<4>(v, kind, partials + 4 * blockIdx.x);
+    block_reduce_waves<4>(v, kind, partials + 4 * blockIdx.x);
 }
 
 hipError_t launch_sum_f32(const float* x, long long n, double* partials, double* out, hipStream_t s) {
