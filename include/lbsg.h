@@ -80,6 +80,21 @@ lbch_status lbsg_predict(lbsg_net* net, const float* phi_dev, const float* cond,
 lbch_status lbsg_gather(const float* field_dev, int32_t h, int32_t w, const int32_t* yx, int32_t k, int32_t crop,
                         const float* cond, int32_t ncond, float* x_dev, float* y_dev, void* hip_stream);
 
+/* As lbsg_gather, for callers that cannot allocate device memory (a training
+ * loop that must not call hipMalloc, code that runs under a memory budget or
+ * beside graph capture): the crop origins and conditioning values are staged in
+ * a fixed device array of the library (2,162,688 bytes per device, held until
+ * the process ends) instead of a per-call allocation, so at most
+ * LBSG_GATHER_NOALLOC_MAX_CROPS crops per call (more -> LBCH_E_INVALID).  Calls
+ * nothing that allocates.  Every call on a device shares that array: calls that
+ * overlap on one device (other threads or streams) race; a call has finished
+ * with it when it returns (it synchronises hip_stream).  Other arguments, errors
+ * and results as lbsg_gather, bit for bit. */
+#define LBSG_GATHER_NOALLOC_MAX_CROPS 16384
+lbch_status lbsg_gather_noalloc(const float* field_dev, int32_t h, int32_t w, const int32_t* yx, int32_t k,
+                                int32_t crop, const float* cond, int32_t ncond, float* x_dev, float* y_dev,
+                                void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -752,6 +753,64 @@ extern "C" lbch_status lbsg_diag_conv3_wgrad(const float* x, const float* dy, fl
     HIP_TRY(lbsg::conv3_dw(xb, gb, part, splits, n, h, wd, ci, co, nullptr));
     HIP_TRY(lbsg::wgrad_reduce(part, dw, splits, co, ci, ci, nullptr));
     HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+// ------------------------------------------------ allocation-free crop gather
+// The crop origins (two int32 per crop) followed by the crops' conditioning
+// values (up to 31 floats per crop), in device memory that lives as long as
+// the library.  Each device holds its own copy of the array; host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kGatherYxBytes = (size_t)LBSG_GATHER_NOALLOC_MAX_CROPS * 2 * sizeof(int32_t);
+constexpr size_t kGatherScratchBytes = kGatherYxBytes + (size_t)LBSG_GATHER_NOALLOC_MAX_CROPS * 31 * sizeof(float);
+static_assert(kGatherYxBytes % 256 == 0, "the conditioning values start on a 256-byte boundary");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kGatherScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// this device's address of `scratch`, looked up once per device (with it current)
+lbch_status gather_scratch(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBCH_E_UNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBCH_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return LBCH_OK;
+}
+}  // namespace
+
+extern "C" lbch_status lbsg_gather_noalloc(const float* field, int32_t h, int32_t w, const int32_t* yx, int32_t k,
+                                           int32_t crop, const float* cond, int32_t ncond, float* x, float* y,
+                                           void* hip_stream) {
+    if (!field || !yx || (!x && !y) || (ncond > 0 && !cond)) return fail(LBCH_E_INVALID, "NULL argument");
+    if (h < 1 || w < 1 || k < 1 || crop < 1 || ncond < 0 || ncond > 31) return fail(LBCH_E_INVALID, "bad sizes");
+    if (k > LBSG_GATHER_NOALLOC_MAX_CROPS)
+        return fail(LBCH_E_INVALID, "%d crops exceed the allocation-free gather's limit of %d per call", k,
+                    LBSG_GATHER_NOALLOC_MAX_CROPS);
+    void* base = nullptr;
+    lbch_status st = gather_scratch(&base);
+    if (st != LBCH_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int* dyx = (int*)base;
+    float* dc = (float*)((char*)base + kGatherYxBytes);
+    HIP_TRY(hipMemcpyAsync(dyx, yx, 2 * (size_t)k * sizeof(int), hipMemcpyHostToDevice, s));
+    if (ncond > 0) HIP_TRY(hipMemcpyAsync(dc, cond, (size_t)k * ncond * sizeof(float), hipMemcpyHostToDevice, s));
+    HIP_TRY(lbsg::gather(field, h, w, dyx, k, crop, dc, ncond, x, y, s));
+    // the next call reuses the scratch: this one's kernel has read it on return
+    HIP_TRY(hipStreamSynchronize(s));
     return LBCH_OK;
 }
 

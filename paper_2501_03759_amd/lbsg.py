@@ -42,6 +42,10 @@ _SIGS = {
     "lbsg_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbsg_gather_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_float), ctypes.c_int32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "lbsg_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
 }
@@ -125,8 +129,10 @@ def layer_names(levels):
 
 
 def gather(field_ptr: int, h: int, w: int, yx: np.ndarray, crop: int, cond: np.ndarray | None,
-           x_ptr: int | None, y_ptr: int | None, stream=None):
-    """Crops of a periodic device field into training inputs / targets (lbsg_gather)."""
+           x_ptr: int | None, y_ptr: int | None, stream=None, noalloc: bool = False):
+    """Crops of a periodic device field into training inputs / targets (lbsg_gather, or
+    lbsg_gather_noalloc when noalloc: no device allocation, at most
+    LBSG_GATHER_NOALLOC_MAX_CROPS crops)."""
     yx = np.ascontiguousarray(yx, dtype=np.int32).reshape(-1, 2)
     k = yx.shape[0]
     if cond is None or cond.size == 0:
@@ -134,6 +140,7 @@ def gather(field_ptr: int, h: int, w: int, yx: np.ndarray, crop: int, cond: np.n
     else:
         cond = np.ascontiguousarray(cond, dtype=np.float32).reshape(k, -1)
         c, nc = cond.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), cond.shape[1]
-    _check(_bind().lbsg_gather(ctypes.c_void_p(field_ptr), h, w, yx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                               k, crop, c, nc, ctypes.c_void_p(x_ptr) if x_ptr else None,
-                               ctypes.c_void_p(y_ptr) if y_ptr else None, _stream_handle(stream)), "lbsg_gather")
+    name = "lbsg_gather_noalloc" if noalloc else "lbsg_gather"
+    _check(getattr(_bind(), name)(ctypes.c_void_p(field_ptr), h, w, yx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  k, crop, c, nc, ctypes.c_void_p(x_ptr) if x_ptr else None,
+                                  ctypes.c_void_p(y_ptr) if y_ptr else None, _stream_handle(stream)), name)
