@@ -215,14 +215,16 @@ def copy_ceiling(torch, lbch, stream, nbytes=1 << 30, reps=300):
             "verified": ok}
 
 
-def time_to_t(stream, n, steps, warm, K, NC, inner, chunk, net=None, cond=(), note=None, extrapolate=1):
+def time_to_t(stream, n, steps, warm, K, NC, inner, chunk, net=None, cond=(), note=None, extrapolate=1,
+              plain_until=0):
     """Wall time to advance the 8192^2-recipe FP32 spinodal run (alpha 0.2, seed 5; side n)
     by `steps` steps after `warm` untimed plain steps, twice on the same GPU: with the plain
     scheme, and with the jump + correction + rejection schedule (jumps of K steps, NC correction
     steps, inner projective cycles `inner`; extrapolate = 1: rate-extrapolated jumps, plus the
     network's residual when `net` is given; extrapolate = 0: the network's own jump).  The free energy of both runs is sampled every `chunk` steps (rounded
     to whole cycles); the hybrid's cycles are counted per chunk so that rejections can be told
-    apart by phase (spinodal growth, coarsening)."""
+    apart by phase (spinodal growth, coarsening).  plain_until: the hybrid run advances
+    plainly (timed) up to that step before its first jump."""
     import torch
 
     from paper_2501_03759_amd import inputs, lbch
@@ -257,8 +259,7 @@ def time_to_t(stream, n, steps, warm, K, NC, inner, chunk, net=None, cond=(), no
             done = 0
             while done < steps:
                 k = min(chunk, steps - done)
-                advance(k)
-                done += k
+                done += advance(k) or k
             torch.cuda.synchronize()
             return time.perf_counter() - t0
 
@@ -286,14 +287,25 @@ def time_to_t(stream, n, steps, warm, K, NC, inner, chunk, net=None, cond=(), no
             e_hyb.append(hyb.free_energy()[0])
             note(f"hybrid: step {hyb.nstep}, E = {e_hyb[-1]:.6f}, accepted {st_.accepted}/{st_.cycles}")
 
+        def adv_mixed(k):
+            # plain steps up to plain_until, then the schedule (chunks never straddle it)
+            if hyb.nstep - warm < plain_until:
+                k = min(k, plain_until - (hyb.nstep - warm))
+                hyb.step(k)
+                e_hyb.append(hyb.free_energy()[0])
+                note(f"hybrid (plain prefix): step {hyb.nstep}, E = {e_hyb[-1]:.6f}")
+                return k
+            adv_hyb(k)
+            return k
+
         t_plain = run(adv_plain)
-        t_hyb = run(adv_hyb)
+        t_hyb = run(adv_mixed)
         pa, ph = plain.phi(), hyb.phi()
         plain.close()
         hyb.close()
     rel = float(np.linalg.norm(ph - pa) / np.linalg.norm(pa))
     return {
-        "workload": f"spinodal-{n}x{n}-fp32", "from_step": warm, "steps": steps,
+        "workload": f"spinodal-{n}x{n}-fp32", "from_step": warm, "steps": steps, "plain_prefix": plain_until,
         "plain_s": round(t_plain, 3), "hybrid_s": round(t_hyb, 3), "speedup": round(t_plain / t_hyb, 3),
         "rel_l2": rel, "rel_l2_ok": rel <= 1e-2,
         "energy_nonincreasing": {"plain": bool(np.all(np.diff(e_plain) <= 0)),
@@ -443,7 +455,7 @@ def learned_workload(args):
             inner = [int(v) for v in args.c4_hybrid_inner.split(",")]
             out["time_to_t"] = time_to_t(stream, n, args.time_to_t_steps, args.hybrid_warm, K, args.c4_correct,
                                          inner, args.hybrid_chunk, net=inf, cond=cond, note=note,
-                                         extrapolate=0)
+                                         extrapolate=0, plain_until=args.time_to_t_plain)
         inf.close()
     out["wall_s"] = round(time.time() - t0, 1)
     print(json.dumps(out), flush=True)
@@ -638,7 +650,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=8192, help="grid side (default: the 8192^2 workload)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--depth", type=int, default=2, choices=[1, 2], help="time steps per kernel launch")
+    ap.add_argument("--depth", type=int, default=0, choices=[0, 1, 2],
+                    help="time steps per kernel launch (0: the autotuner's choice with its launch shape)")
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block (ensemble: [,depth], a fixed shape instead of the autotuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n3", type=int, default=256, help="box side of the D3Q15 workload")
@@ -663,6 +676,9 @@ def main():
     ap.add_argument("--c4-hybrid", action="store_true", help="learned: also the time-to-t with the network's jump")
     ap.add_argument("--c4-correct", type=int, default=10, help="learned hybrid: correction steps per jump")
     ap.add_argument("--c4-hybrid-inner", type=str, default="0,0")
+    ap.add_argument("--time-to-t-plain", type=int, default=20000,
+                    help="default line: plain steps of the hybrid run before its first jump (the spinodal "
+                         "growth amplifies early jump errors)")
     ap.add_argument("--time-to-t-steps", type=int, default=200000,
                     help="default line: steps of the plain / hybrid time-to-t comparison from the initial field "
                          "(0 = skip)")
@@ -705,7 +721,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     sim = lbch.Sim(p, stream)
-    sim.set_time_blocking(args.depth)
+    if args.depth:
+        sim.set_time_blocking(args.depth)
     if args.tiling:
         bt, rows = (int(v) for v in args.tiling.split(","))
         sim.set_tiling(bt, rows)
@@ -713,7 +730,14 @@ def main():
     sim.init(phi0)
     del phi0
     copy = copy_ceiling(torch, lbch, stream)
-    depth = args.depth
+    tuned = None
+    if not args.depth and not args.tiling:
+        # launch shape (steps per launch, lanes, rows per workgroup) from the library's autotuner,
+        # which times the step kernel on the live state without changing it; it also brings the
+        # GPU's clocks to where the step kernel runs them
+        nt_, hc_, ms_ = sim.autotune(2)
+        tuned = {"block_threads": nt_, "rows_per_block": hc_, "ms_per_step": round(ms_, 4)}
+    depth = sim.time_blocking()
     sim.step(args.warmup)
     sim.synchronize()
 
@@ -780,7 +804,8 @@ def main():
         "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
         "config": {"workload": f"spinodal-{n}x{n}-{args.precision}", "grid": [n, n], "lattice": "D2Q9",
                    "alpha": d["alpha"], "m": d["m"], "regularization": "willmore", "eps_reg": d["eps_reg"],
-                   "mobility": d["mobility"], "time_steps_per_launch": depth, "tiling": list(tiling)},
+                   "mobility": d["mobility"], "time_steps_per_launch": depth, "tiling": list(tiling),
+                   "autotuned": tuned},
         "roofline": roofline,
         "windows": {"count": nwin, "steps": sizes, "ms_per_step": [round(v, 4) for v in win_ms],
                     "median_ms_per_step": round(med, 4), "median_MLUPS": round(nodes / (med * 1e-3) / 1e6, 1),
@@ -798,7 +823,7 @@ def main():
         try:
             out["time_to_t"] = time_to_t(stream, n, args.time_to_t_steps, 0, args.hybrid_jump, args.hybrid_correct,
                                          [int(v) for v in args.hybrid_inner.split(",")], args.hybrid_chunk,
-                                         note=note)
+                                         note=note, plain_until=args.time_to_t_plain)
         except Exception as exc:                  # the throughput line stands on its own
             out["time_to_t"] = {"error": f"{type(exc).__name__}: {exc}"}
     print(json.dumps(out), flush=True)

@@ -84,6 +84,49 @@ def stats_only(args):
     print("\n".join(lines))
 
 
+def shader_counters(dirs, kernel_substr, last=0):
+    """Mean per dispatch of every counter collected in the given --pmc runs for the kernel
+    (its last `last` dispatches when given)."""
+    out = {}
+    for d in dirs:
+        path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if kernel_substr in r["Kernel_Name"]:
+                per.setdefault(r["Counter_Name"], []).append((int(r.get("Dispatch_Id") or 0),
+                                                             float(r["Counter_Value"])))
+        for name, vals in per.items():
+            vals = [v for _, v in sorted(vals)]
+            if last:
+                vals = vals[-last:]
+            out[name] = statistics.mean(vals)
+    return out
+
+
+def shader_lines(c):
+    """Markdown lines of the shader counters and the ratios derived from them (counter units:
+    SQ_*_CYCLES, SQ_WAIT_* and SQ_ACTIVE_INST_* in quad-cycles summed over the waves of every
+    SIMD; VALUBusy = 100 sum SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE)."""
+    lines = ["| counter | mean per dispatch |", "|---|---|"]
+    for k in sorted(c):
+        lines.append(f"| {k} | {c[k]:.6g} |")
+    d = []
+    if "SQ_WAVES" in c and c["SQ_WAVES"]:
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"):
+            if k in c:
+                d.append(f"- {k} per wave: {c[k] / c['SQ_WAVES']:.1f}")
+    if "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"]:
+        for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                  "SQ_ACTIVE_INST_ANY"):
+            if k in c:
+                d.append(f"- {k} / SQ_WAVE_CYCLES (share of wave lifetime): {c[k] / c['SQ_WAVE_CYCLES']:.3f}")
+    if "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_LDS_IDX_ACTIVE"):
+        d.append(f"- SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: {c['SQ_LDS_BANK_CONFLICT'] / c['SQ_LDS_IDX_ACTIVE']:.3f}")
+    if "VALUBusy" in c:
+        d.append(f"- VALUBusy: {c['VALUBusy']:.1f} %")
+    return lines + [""] + d
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -98,6 +141,8 @@ def main():
     ap.add_argument("--title", default="", help="summary title (stats-only mode)")
     ap.add_argument("--kernel", default="", help="kernel name substring (default: the lattice's step kernel)")
     ap.add_argument("--tiling", default="", help="launch shape of the profiled runs (block_threads,rows), recorded")
+    ap.add_argument("--sq", action="append", default=[],
+                    help="a --pmc run of shader counters of the step kernel (repeatable), summarised beside the traffic")
     ap.add_argument("--last", type=int, default=0,
                     help="use only the last N dispatches of the kernel (runs that also launch it in other shapes)")
     args = ap.parse_args()
@@ -172,6 +217,13 @@ def main():
               f"{f' (last {args.last} dispatches)' if args.last else ''} -> {rec['achieved_alg_GBs']:.0f} GB/s algorithmic, "
               f"{rec['achieved_traffic_GBs']:.0f} GB/s measured traffic (8000 GB/s peak)",
               f"- kernel source sha256[:16] = {rec['kernel_sha256_16']}"]
+    if args.sq:
+        sq = shader_counters(args.sq, STEP_KERNEL, args.last)
+        rec["shader_counters"] = sq
+        with open(args.out + ".json", "w") as fh:
+            json.dump(rec, fh, indent=1)
+        lines += ["", "Shader counters of the step kernel (further --pmc runs of the same command):", ""]
+        lines += shader_lines(sq)
     with open(args.out + ".md", "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps(rec))
