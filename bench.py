@@ -652,6 +652,7 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--depth", type=int, default=0, choices=[0, 1, 2],
                     help="time steps per kernel launch (0: the autotuner's choice with its launch shape)")
+    ap.add_argument("--autotune-steps", type=int, default=40, help="launches per autotuner trial (default line)")
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block (ensemble: [,depth], a fixed shape instead of the autotuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n3", type=int, default=256, help="box side of the D3Q15 workload")
@@ -733,10 +734,14 @@ def main():
     tuned = None
     if not args.depth and not args.tiling:
         # launch shape (steps per launch, lanes, rows per workgroup) from the library's autotuner,
-        # which times the step kernel on the live state without changing it; it also brings the
-        # GPU's clocks to where the step kernel runs them
-        nt_, hc_, ms_ = sim.autotune(2)
-        tuned = {"block_threads": nt_, "rows_per_block": hc_, "ms_per_step": round(ms_, 4)}
+        # which times every candidate for --autotune-steps launches on the live state without
+        # changing it.  Long trials also leave the GPU in the power state the step kernel runs
+        # in: after a pause the first ~20 launches of the step kernel run up to 40 % slower
+        # (kernel trace in the committed profile)
+        t_at = time.perf_counter()
+        nt_, hc_, ms_ = sim.autotune(args.autotune_steps)
+        tuned = {"block_threads": nt_, "rows_per_block": hc_, "ms_per_step": round(ms_, 4),
+                 "launches_per_trial": args.autotune_steps, "seconds": round(time.perf_counter() - t_at, 2)}
     depth = sim.time_blocking()
     sim.step(args.warmup)
     sim.synchronize()

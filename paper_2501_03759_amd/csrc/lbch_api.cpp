@@ -297,14 +297,14 @@ Tiling make_tiling(int nx, int ny, int nt, int hc, int depth, int esize, int slo
             long long want = (long long)t.strips * ny / 2048;
             hc = (int)(want < 32 ? 32 : (want > 512 ? 512 : want));
         } else {
-            // a chunk of h rows costs about (h + 14) first-step rows and
-            // (h + 7) second-step rows; the launch takes ceil(tiles / slots)
-            // rounds of the longest chunk: minimise rounds * (2h + 21)
+            // a chunk of h rows costs h + 17 iterations of the two-step
+            // sweep (17 start-up rows); the launch takes ceil(tiles / slots)
+            // rounds of the longest chunk: minimise rounds * (h + 17)
             long long best = -1;
             const int hmax = ny < 512 ? ny : 512;
             for (int h = 32; h <= hmax; ++h) {
                 const long long tiles = (long long)t.strips * ((ny + h - 1) / h);
-                const long long cost = ((tiles + slots - 1) / slots) * (2LL * h + 21);
+                const long long cost = ((tiles + slots - 1) / slots) * (h + 17LL);
                 if (best < 0 || cost < best) {
                     best = cost;
                     hc = h;
@@ -870,7 +870,7 @@ extern "C" lbch_status lbch_autotune(lbch_sim* s, int32_t steps_per_trial, int32
             if (depth == 2 && (nt == 64 || (s->esize == 8 && nt == 512))) continue;
             for (int hc : hcs) {
                 if (hc > 8 && hc > s->g.ny) continue;
-                if (depth == 2 && hc > 0 && hc < 32) continue;   // 14 start-up rows per chunk
+                if (depth == 2 && hc > 0 && hc < 32) continue;   // 17 start-up rows per chunk
                 Tiling t = hc == 0 ? sim_tiling(s, depth, nt, 0)
                                    : make_tiling(s->g.nx, s->g.ny, nt, hc, depth, (int)s->esize);
                 t.staged = staged;

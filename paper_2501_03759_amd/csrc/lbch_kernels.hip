@@ -471,23 +471,32 @@ __device__ __forceinline__ void sweep_strip(const T* __restrict__ fin, T* __rest
 // ---------------------------------------------------------------------------
 // Two time steps per sweep (temporal blocking).  Lane t owns column
 // x0 - 7 + t; a strip yields W = NT - 16 columns of the second step.  Each
-// iteration j loads row a = y0 - 7 + j and runs eight lagging stages:
-//   A1..D1 (rows a .. a-3): the first step exactly as in sweep_strip, except
-//          that D1 keeps its post-collision row d = a-3 on chip;
-//   A2 (row a-4)          : pull of the second step from that on-chip row
-//                           buffer (planes 0, 2, 4 pull along the lane's own
-//                           column and stay in registers; 1/3, 5/6 and 7/8
-//                           go through LDS rings of 2, 3 and 1 rows, the lag
-//                           of their pull: 1, 2 and 0 rows);
-//   B2..D2 (rows a-5 .. a-7): the second step; D2 stores to HBM.
-// Every population is read from and written to HBM once per two updates.
-// Valid lanes shrink by one per stage: A1 all, B1 [1, NT-1), C1 [2, NT-2),
-// D1 [3, NT-3), A2 [4, NT-4), B2 [5, NT-5), C2 [6, NT-6), D2 [7, NT-7).
+// iteration j loads row a = y0 - 7 + j and runs the eight stages of the two
+// steps in two phases with one barrier between them; every stage reads only
+// rows that an earlier phase has finished, so a stage trails its producer by
+// the rows that needs (offsets below a):
+//   phase 1: A1 (a), C1 (a-3), A2 (a-6), C2 (a-9)
+//   phase 2: B1 (a-1), D1 (a-4), B2 (a-7), D2 (a-10, stored)
+// A1..D1 are the first step as in sweep_strip, except that D1 keeps its
+// post-collision row d on chip: planes 0, 2, 4 (whose pull stays in the
+// lane's column) in registers, 1/3, 5/6 and 7/8 in LDS rings of 2, 3 and 1
+// rows (A2 pulls them 2, 3 and 1 iterations after D1 wrote them).  A2..D2
+// are the second step; D2 stores.  Every population is read from and written
+// to HBM once per two updates.  With the staged row loader one more barrier
+// separates parking a row in LDS from reading it: three barriers per row.
+// Every ring slot is indexed by the iteration that wrote it (LDS rings: j mod
+// 3, register rings: j mod 6); the loop is unrolled six times so that all of
+// them are static.  Valid lanes shrink by one per stage: A1 all, B1
+// [1, NT-1), C1 [2, NT-2), D1 [3, NT-3), A2 [4, NT-4), B2 [5, NT-5),
+// C2 [6, NT-6), D2 [7, NT-7).
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
 struct Pass2Lds {
     T phi[3][NT], qx[3][NT], qy[3][NT], w[3][NT], mb[3][NT];
 };
+
+constexpr int mod3(int v) { return ((v % 3) + 3) % 3; }
+constexpr int mod6(int v) { return ((v % 6) + 6) % 6; }
 
 // EXTRAP: the stored state is f_{n+2} + ext (f_{n+2} - f_n) elementwise, f_n
 // being this launch's input at the same element (a projective step of the
@@ -498,10 +507,10 @@ __device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __res
                                              const StepCoef<T>& c, Pass2Lds<T, NT>& L1, Pass2Lds<T, NT>& L2,
                                              T (*s_13)[2][NT], T (*s_56)[2][NT], T (*s_78)[NT], T* s_f,
                                              const T ext = T(0)) {
-    constexpr int U = 4;
+    constexpr int U = 6;
     using Loader = RowLoader<T, NT, STAGED>;
     const int nx = g.nx, ny = g.ny, pitch = g.pitch;
-    const int niter = hlen + 14;
+    const int niter = hlen + 17;
     const int t = threadIdx.x;
 
     Loader ld;
@@ -511,10 +520,10 @@ __device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __res
     int rA = (y0 - 7) % ny;
     if (rA < 0) rA += ny;
 
-    typename Loader::Buf buf[U];
+    typename Loader::Buf buf[2];
     T pop1[U][9], red1[U][3], mua1[U], tl1[U];
     T pop2[U][9], red2[U][3], mua2[U], tl2[U];
-    T o0r[U], o2r[U], o4r[U];         // D1 planes 0, 2, 4 of the lane (A2 uses them 1, 2, 0 iterations later)
+    T o0r[U], o2r[U], o4r[U];          // D1 planes 0, 2, 4 of the lane (A2 pulls them 2, 3, 1 iterations later)
 #pragma unroll
     for (int k = 0; k < U; ++k) o0r[k] = o2r[k] = o4r[k] = T(0);
 
@@ -526,74 +535,73 @@ __device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __res
         for (int k = 0; k < U; ++k) {
             const int j = jb + k;
             if (j < niter) {
-                const int sN = j % 3, sC = (j + 2) % 3, sS = (j + 1) % 3;
-                // ---- A1: row a ----
+                // slots written by iterations j, j-1, j-2, j-3 (LDS rings of three rows)
+                const int s0 = mod3(k), s1 = mod3(k - 1), s2 = mod3(k - 2);
                 if (Loader::kNeedsBarrier) {
-                    ld.park(buf[k], s_f);
+                    ld.park(buf[k & 1], s_f);
                     lds_barrier();
                 }
+                // ======== phase 1 ========
+                // ---- A1: row a ----
                 {
                     T f[9];
-                    ld.fetch(buf[k], s_f, f);
-                    L1.phi[sN][t] = stage_a<T, UNIT>(f, pop1[k], red1[k]);
+                    ld.fetch(buf[k & 1], s_f, f);
+                    L1.phi[s0][t] = stage_a<T, UNIT>(f, pop1[k], red1[k]);
                 }
-                ld.issue(rA, buf[(k + 1) % U]);
+                // unconditional: past the last row of the sweep this fetches a
+                // (wrapped, valid) row that is never used
+                ld.issue(rA, buf[(k + 1) & 1]);
                 rA = (rA == ny - 1) ? 0 : rA + 1;
+                // ---- C1: row a-3 (its q, w rows come from B1 of iterations j-1 .. j-3) ----
+                if (j >= 5 && t >= 2 && t < NT - 2)
+                    L1.mb[s0][t] = stage_c<T, NT>(c, L1.qx, L1.qy, L1.w, s1, s2, s0, t, tl1[mod6(k - 2)]);
+                // ---- A2: row a-6, pulled from D1's rows of iterations j-1 .. j-3 ----
+                if (j >= 10 && t >= 4 && t < NT - 4) {
+                    T f[9];
+                    const int p13 = (k + U - 2) & 1, p56 = mod3(k - 3);
+                    f[0] = o0r[mod6(k - 2)];
+                    f[1] = s_13[p13][0][t - 1];
+                    f[2] = o2r[mod6(k - 3)];
+                    f[3] = s_13[p13][1][t + 1];
+                    f[4] = o4r[mod6(k - 1)];
+                    f[5] = s_56[p56][0][t - 1];
+                    f[6] = s_56[p56][1][t + 1];
+                    f[7] = s_78[0][t + 1];
+                    f[8] = s_78[1][t - 1];
+                    L2.phi[s0][t] = stage_a<T, UNIT>(f, pop2[k], red2[k]);
+                }
+                // ---- C2: row a-9 ----
+                if (j >= 15 && t >= 6 && t < NT - 6)
+                    L2.mb[s0][t] = stage_c<T, NT>(c, L2.qx, L2.qy, L2.w, s1, s2, s0, t, tl2[mod6(k - 2)]);
                 lds_barrier();
+                // ======== phase 2 ========
                 // ---- B1: row a-1 ----
                 if (j >= 2 && t >= 1 && t < NT - 1)
-                    stage_b<T, NT>(c, L1.phi, L1.qx, L1.qy, L1.w, sN, sC, sS, t, tl1[k], mua1[k]);
-                lds_barrier();
-                // ---- C1: row a-2 ----
-                if (j >= 4 && t >= 2 && t < NT - 2)
-                    L1.mb[sN][t] = stage_c<T, NT>(c, L1.qx, L1.qy, L1.w, sN, sC, sS, t, tl1[(k + U - 1) % U]);
-                lds_barrier();
-                // ---- D1: row d = a-3, kept on chip ----
-                if (j >= 6 && t >= 3 && t < NT - 3) {
+                    stage_b<T, NT>(c, L1.phi, L1.qx, L1.qy, L1.w, s0, s1, s2, t, tl1[k], mua1[k]);
+                // ---- D1: row d = a-4, kept on chip ----
+                if (j >= 7 && t >= 3 && t < NT - 3) {
                     T o[9];
-                    stage_d<T, NT, UNIT>(c, L1.mb, sN, sC, sS, t, pop1[(k + U - 3) % U], red1[(k + U - 3) % U],
-                                         mua1[(k + U - 2) % U], o);
+                    stage_d<T, NT, UNIT>(c, L1.mb, s0, s1, s2, t, pop1[mod6(k - 4)], red1[mod6(k - 4)],
+                                         mua1[mod6(k - 3)], o);
                     o0r[k] = o[0];
                     o2r[k] = o[2];
                     o4r[k] = o[4];
-                    s_13[j & 1][0][t] = o[1];
-                    s_13[j & 1][1][t] = o[3];
-                    s_56[j % 3][0][t] = o[5];
-                    s_56[j % 3][1][t] = o[6];
+                    s_13[k & 1][0][t] = o[1];
+                    s_13[k & 1][1][t] = o[3];
+                    s_56[s0][0][t] = o[5];
+                    s_56[s0][1][t] = o[6];
                     s_78[0][t] = o[7];
                     s_78[1][t] = o[8];
                 }
-                lds_barrier();
-                // ---- A2: row a-4 = d-1, pulled from the first step's rows d-2 .. d ----
-                if (j >= 8 && t >= 4 && t < NT - 4) {
-                    T f[9];
-                    const int p1 = (j + 1) & 1, p2 = (j + 1) % 3;   // slots of rows d-1 and d-2
-                    f[0] = o0r[(k + U - 1) % U];
-                    f[1] = s_13[p1][0][t - 1];
-                    f[2] = o2r[(k + U - 2) % U];
-                    f[3] = s_13[p1][1][t + 1];
-                    f[4] = o4r[k];
-                    f[5] = s_56[p2][0][t - 1];
-                    f[6] = s_56[p2][1][t + 1];
-                    f[7] = s_78[0][t + 1];
-                    f[8] = s_78[1][t - 1];
-                    L2.phi[sN][t] = stage_a<T, UNIT>(f, pop2[k], red2[k]);
-                }
-                lds_barrier();
-                // ---- B2: row a-5 ----
-                if (j >= 10 && t >= 5 && t < NT - 5)
-                    stage_b<T, NT>(c, L2.phi, L2.qx, L2.qy, L2.w, sN, sC, sS, t, tl2[k], mua2[k]);
-                lds_barrier();
-                // ---- C2: row a-6 ----
-                if (j >= 12 && t >= 6 && t < NT - 6)
-                    L2.mb[sN][t] = stage_c<T, NT>(c, L2.qx, L2.qy, L2.w, sN, sC, sS, t, tl2[(k + U - 1) % U]);
-                lds_barrier();
-                // ---- D2: row a-7, stored ----
-                if (j >= 14 && t >= 7 && t < 7 + wlen) {
+                // ---- B2: row a-7 ----
+                if (j >= 12 && t >= 5 && t < NT - 5)
+                    stage_b<T, NT>(c, L2.phi, L2.qx, L2.qy, L2.w, s0, s1, s2, t, tl2[k], mua2[k]);
+                // ---- D2: row a-10, stored ----
+                if (j >= 17 && t >= 7 && t < 7 + wlen) {
                     T o[9];
-                    stage_d<T, NT, UNIT>(c, L2.mb, sN, sC, sS, t, pop2[(k + U - 3) % U], red2[(k + U - 3) % U],
-                                         mua2[(k + U - 2) % U], o);
-                    const int rd = y0 - 14 + j;
+                    stage_d<T, NT, UNIT>(c, L2.mb, s0, s1, s2, t, pop2[mod6(k - 4)], red2[mod6(k - 4)],
+                                         mua2[mod6(k - 3)], o);
+                    const int rd = y0 - 17 + j;
                     T* __restrict__ q = fout + ((long long)rd * pitch + xc);
                     if constexpr (EXTRAP) {
                         const T* __restrict__ pv = fin + ((long long)rd * pitch + xc);
@@ -607,6 +615,7 @@ __device__ __forceinline__ void sweep_strip2(const T* __restrict__ fin, T* __res
                         for (int i = 0; i < 9; ++i) q[i * g.plane] = o[i];
                     }
                 }
+                lds_barrier();
             }
         }
     }
@@ -632,9 +641,18 @@ __global__ __launch_bounds__(NT) void step_fused(const T* __restrict__ fin, T* _
                                      s_qx, s_qy, s_w, s_mb, s_f);
 }
 
+// Waves per SIMD the two-step sweep is compiled for (the launch bound's second
+// argument): the LDS of one CU holds three FP32 workgroups of 256 lanes or six
+// of 128, twelve waves, and with unit free rates the register budget is held
+// to that (three waves per SIMD, 168 VGPRs).  The general-rate collision keeps all nine
+// populations of five rows per step in registers (about 190 VGPRs, two waves);
+// FP64 rings and 512-lane workgroups are limited by LDS.
+template <typename T, int NT, bool UNIT>
+constexpr int kStep2Waves = (UNIT && sizeof(T) == 4 && NT <= 256) ? 3 : 1;
+
 // Two steps per launch: fin holds the state at step n, fout receives step n + 2.
 template <typename T, int NT, bool UNIT, bool STAGED>
-__global__ __launch_bounds__(NT) void step2_fused(const T* __restrict__ fin, T* __restrict__ fout,
+__global__ __launch_bounds__(NT, (kStep2Waves<T, NT, UNIT>)) void step2_fused(const T* __restrict__ fin, T* __restrict__ fout,
                                                   const Grid g, const Tiling tl, const StepCoef<T> c) {
     __shared__ Pass2Lds<T, NT> L1;
     __shared__ Pass2Lds<T, NT> L2;
@@ -656,7 +674,7 @@ __global__ __launch_bounds__(NT) void step2_fused(const T* __restrict__ fin, T* 
 // Two steps per launch with the projective extrapolation of the populations
 // in the store: fout = f_{n+2} + ext (f_{n+2} - f_n), fin holding f_n.
 template <typename T, int NT, bool UNIT, bool STAGED>
-__global__ __launch_bounds__(NT) void step2_extrap(const T* __restrict__ fin, T* __restrict__ fout,
+__global__ __launch_bounds__(NT, (kStep2Waves<T, NT, UNIT>)) void step2_extrap(const T* __restrict__ fin, T* __restrict__ fout,
                                                    const Grid g, const Tiling tl, const StepCoef<T> c, const T ext) {
     __shared__ Pass2Lds<T, NT> L1;
     __shared__ Pass2Lds<T, NT> L2;
