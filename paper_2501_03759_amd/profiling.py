@@ -127,6 +127,89 @@ def shader_lines(c):
     return lines + [""] + d
 
 
+def unet_layers(chans, c_in, batch, side):
+    """The forward pass's 3x3 convolutions in launch order: (name, pixels, real input channels,
+    output channels, bytes of one BF16 read of the input and one write of the output)."""
+    L = len(chans)
+    out = []
+    for l in range(L):
+        px = batch * (side >> l) ** 2
+        ci = c_in if l == 0 else chans[l - 1]
+        cin_stored = 32 if l == 0 else chans[l - 1]
+        out.append((f"enc{l}a", px, ci, chans[l], 2 * px * (cin_stored + chans[l])))
+        pooled = px // 4 * chans[l] if l + 1 < L else 0
+        out.append((f"enc{l}b", px, chans[l], chans[l], 2 * (px * 2 * chans[l] + pooled)))
+    for l in range(L - 2, -1, -1):
+        px = batch * (side >> l) ** 2
+        up = px // 4 * chans[l + 1]
+        out.append((f"dec{l}a", px, chans[l + 1] + chans[l], chans[l], 2 * (up + px * chans[l] + px * chans[l])))
+        out.append((f"dec{l}b", px, chans[l], chans[l], 2 * px * chans[l] * (1 if l == 0 else 2) + (4 * px if l == 0 else 0)))
+    return out
+
+
+def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500.0, peak_gbs=8000.0):
+    """Per-layer table of the network's forward convolutions: launch time (kernel trace),
+    TFLOP/s, MfmaUtil and HBM traffic (--pmc runs), and each layer's roofline
+    min(peak MFMA, arithmetic intensity x peak HBM) on its algorithmic bytes.  Dispatches of
+    conv3_fwd_k before the first weight-gradient dispatch are the forward passes, in layer order."""
+    layers = unet_layers(chans, c_in, batch, side)
+    n = len(layers)
+
+    def fwd_rows(rows, start_key):
+        rows = sorted(rows, key=lambda r: int(r[start_key]))
+        first_dw = next((i for i, r in enumerate(rows) if "conv3_dw_k" in r["Kernel_Name"]), len(rows))
+        return [r for r in rows[:first_dw] if "conv3_fwd_k" in r["Kernel_Name"]]
+
+    trace = fwd_rows(list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))))),
+                     "Start_Timestamp")
+    groups = len(trace) // n
+    if groups < 2:
+        raise ValueError(f"{len(trace)} forward convolutions in the trace, not several passes of {n}")
+    durs = [[int(trace[g * n + i]["End_Timestamp"]) - int(trace[g * n + i]["Start_Timestamp"])
+             for g in range(1, groups)] for i in range(n)]        # the first pass is a warm-up
+    ctr = [dict() for _ in range(n)]
+    for d in pmc_dirs:
+        rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
+        for r in rows:
+            r["_id"] = int(r.get("Dispatch_Id") or 0)
+        names = sorted({r["Counter_Name"] for r in rows})
+        for cname in names:
+            cr = fwd_rows([r for r in rows if r["Counter_Name"] == cname], "_id")
+            g2 = len(cr) // n
+            for i in range(n):
+                vals = [float(cr[g * n + i]["Counter_Value"]) for g in range(1, g2)]
+                if vals:
+                    ctr[i][cname] = statistics.mean(vals)
+    table = []
+    for i, (name, px, ci, co, abytes) in enumerate(layers):
+        ns = statistics.mean(durs[i])
+        flop = 18.0 * px * ci * co
+        ai = flop / abytes
+        roof = min(peak_tflops, ai * peak_gbs / 1e3)
+        tf = flop / (ns * 1e-9) / 1e12
+        row = {"layer": name, "pixels": px, "c_in": ci, "c_out": co, "gflop": flop / 1e9, "us": ns / 1e3,
+               "tflops": tf, "alg_bytes": abytes, "ai": ai, "roofline_tflops": roof, "frac_of_roofline": tf / roof}
+        if "MfmaUtil" in ctr[i]:
+            row["mfma_util_pct"] = ctr[i]["MfmaUtil"]
+        if "FETCH_SIZE" in ctr[i] or "WRITE_SIZE" in ctr[i]:
+            row["traffic_kib"] = ctr[i].get("FETCH_SIZE", 0.0) + ctr[i].get("WRITE_SIZE", 0.0)
+        table.append(row)
+    return table
+
+
+def unet_lines(table):
+    lines = ["| layer | pixels | c_in → c_out | GFLOP | µs | TFLOP/s | roofline TFLOP/s (AI flop/B) | of roofline | MfmaUtil % |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for r in table:
+        mu = f"{r['mfma_util_pct']:.1f}" if "mfma_util_pct" in r else "—"
+        lines.append(f"| {r['layer']} | {r['pixels']} | {r['c_in']} → {r['c_out']} | {r['gflop']:.1f} | {r['us']:.1f} | "
+                     f"{r['tflops']:.0f} | {r['roofline_tflops']:.0f} ({r['ai']:.0f}) | {r['frac_of_roofline']:.2f} | {mu} |")
+    tot_f = sum(r["gflop"] for r in table)
+    tot_us = sum(r["us"] for r in table)
+    lines.append(f"| all 3x3 convolutions | | | {tot_f:.0f} | {tot_us:.0f} | {tot_f / tot_us * 1e-3 * 1e3:.0f} | | | |")
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -145,7 +228,24 @@ def main():
                     help="a --pmc run of shader counters of the step kernel (repeatable), summarised beside the traffic")
     ap.add_argument("--last", type=int, default=0,
                     help="use only the last N dispatches of the kernel (runs that also launch it in other shapes)")
+    ap.add_argument("--unet", default="", help="per-layer summary of the network's forward: "
+                    "chans,c_in,batch,side (e.g. 32-64-128-256-256,5,16,256); --trace plus --sq runs")
     args = ap.parse_args()
+    if args.unet:
+        ch, cin, bsz, side = args.unet.split(",")
+        table = unet_profile(args.trace, args.sq, [int(v) for v in ch.split("-")], int(cin), int(bsz), int(side))
+        lines = [f"# rocprofv3 summary: {args.title or 'network forward, per layer'}", "", "Commands:", ""]
+        lines += ["    " + c for c in args.command.split(";;")]
+        lines += ["", "Forward 3x3 convolutions in launch order (pooling, upsampling-concatenation and the head "
+                  "are fused into them); roofline = min(2500 TFLOP/s BF16 MFMA, arithmetic intensity x 8000 GB/s) "
+                  "on the algorithmic bytes (one BF16 read of the input, one write of the output):", ""]
+        lines += unet_lines(table)
+        with open(args.out + ".md", "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        with open(args.out + ".json", "w") as fh:
+            json.dump(table, fh, indent=1)
+        print("\n".join(lines))
+        return
     d3 = args.lattice == "d3q15"
     if d3:
         args.depth = 1

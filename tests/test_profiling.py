@@ -60,3 +60,28 @@ def test_measured_traffic_requires_matching_source_size_depth_and_shape(tmp_path
     json.dump(dict(rec, kernel_sha256_16="0" * 16), open(p, "w"))
     assert bench.measured_traffic(1000, "fp32", 2, path=p, tiling=(128, 32)) is None
     assert bench.measured_traffic(1000, "fp32", 2, path=str(tmp_path / "missing.json")) is None
+
+
+def test_unet_layer_table_from_a_synthetic_trace(tmp_path):
+    # three forward passes of a 2-level net (6 convolutions each) and one weight-gradient
+    # dispatch after them; the first pass is dropped as a warm-up, the training step's
+    # forward convolutions after the weight gradient are not counted
+    from paper_2501_03759_amd import profiling
+    layers = profiling.unet_layers((32, 64), 5, 2, 32)
+    assert [l[0] for l in layers] == ["enc0a", "enc0b", "enc1a", "enc1b", "dec0a", "dec0b"]
+    rows, t = [], 0
+    for g in range(3):
+        rows.append(["lbch::pack_input_k", t, t + 5])
+        t += 10
+        for i in range(6):
+            dur = 1000 * (i + 1) * (2 if g == 0 else 1)
+            rows.append([f"void lbsg::conv3_fwd_k<32, true, false>", t, t + dur])
+            t += dur + 10
+    rows.append(["void lbsg::conv3_dw_k<64>", t, t + 100])
+    rows.append(["void lbsg::conv3_fwd_k<32, true, false>", t + 200, t + 99999])
+    _write_csv(str(tmp_path / "tr" / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    table = profiling.unet_profile(str(tmp_path / "tr"), [], (32, 64), 5, 2, 32)
+    assert [round(r["us"], 3) for r in table] == [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    r0 = table[0]
+    assert r0["gflop"] == 18.0 * 2 * 32 * 32 * 5 * 32 / 1e9
+    assert r0["roofline_tflops"] == min(2500.0, r0["ai"] * 8.0)
