@@ -206,7 +206,7 @@ def unet_lines(table):
                      f"{r['tflops']:.0f} | {r['roofline_tflops']:.0f} ({r['ai']:.0f}) | {r['frac_of_roofline']:.2f} | {mu} |")
     tot_f = sum(r["gflop"] for r in table)
     tot_us = sum(r["us"] for r in table)
-    lines.append(f"| all 3x3 convolutions | | | {tot_f:.0f} | {tot_us:.0f} | {tot_f / tot_us * 1e-3 * 1e3:.0f} | | | |")
+    lines.append(f"| all 3x3 convolutions | | | {tot_f:.0f} | {tot_us:.0f} | {tot_f / tot_us * 1e3:.0f} | | | |")
     return lines
 
 
