@@ -461,6 +461,105 @@ def learned_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def droplet_workload(args):
+    """The droplet workload in FP64 (64 x 64 periodic, centred tanh disc of radius 16 with
+    eps_w = 2, alpha = 0.05, m = 4, tau_phi = 1, Willmore 0.03; 2000 steps): MLUPS of the HIP
+    path (one launch per step at this size; launch-bound), the oracle timed on the same
+    workload on one host core, and the two results compared node by node."""
+    import torch
+
+    from oracle import lbm
+    from paper_2501_03759_amd import inputs, lbch
+
+    d = inputs.C1
+    n, steps = d["n"], d["steps"]
+    p = lbch.default_params(nx=n, ny=n, precision=lbch.FP64,
+                            sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"])),
+                            mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
+    phi0 = inputs.droplet(n, n, d["radius"], d["eps_w"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sim = lbch.Sim(p, stream)
+    sim.init(phi0)
+    sim.step(args.warmup)
+    sim.init(phi0)
+    sim.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    sim.step(steps)
+    e.record(stream)
+    e.synchronize()
+    ms = a.elapsed_time(e)
+    got = sim.phi()
+    sim.close()
+    out = {"metric": "MLUPS, droplet 64^2 FP64 (1 GPU)", "value": round(n * n * steps / (ms * 1e-3) / 1e6, 2),
+           "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / steps, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic (centred tanh droplet, deterministic)",
+           "config": {"workload": "droplet-64x64-fp64", "alpha": d["alpha"], "m": d["m"], "steps": steps}}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+        kappa, beta = lbm.kappa_beta_from_sigma_width(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"]))
+        op = lbm.Params(nx=n, ny=n, kappa=kappa, beta=beta, mobility=d["mobility"], alpha=d["alpha"],
+                        aniso_m=d["m"], eps_reg=d["eps_reg"])
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            want = lbm.phi_of(lbm.run(phi0, op, steps))
+            dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole workload ({steps} steps of {n}x{n}; FP64 NumPy oracle, 1 thread)",
+                               "host": host_info()}
+        out["max_abs_dphi_vs_oracle"] = float(np.abs(got - want).max())
+    print(json.dumps(out), flush=True)
+
+
+def c2_workload(args):
+    """The 1024^2 FP32 spinodal workload (phi0 = U(-0.05, 0.05) from seed 0, eps_w = 1.5,
+    alpha = 0.3, m = 4, Willmore 0.03, M = 0.1): 50 000 steps with phi and the free energy
+    checkpointed every 1000 steps (phi copied to the host).  Reports MLUPS over the whole
+    run, checkpoints included, the energy series' monotonicity and the growth of phi's rms.
+    The 75 MB working set fits the GPU's 256 MB last-level cache: an on-chip figure, not an
+    HBM one."""
+    import torch
+
+    from paper_2501_03759_amd import inputs, lbch
+
+    d = inputs.C2
+    n, steps, every = d["n"], d["steps"], 1000
+    p = lbch.default_params(nx=n, ny=n, precision=lbch.FP32,
+                            sigma_width=(inputs.SIGMA_PAPER, inputs.width_from_eps(d["eps_w"])),
+                            mobility=d["mobility"], alpha=d["alpha"], aniso_m=d["m"], eps_reg=d["eps_reg"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sim = lbch.Sim(p, stream)
+    sim.init(inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"]))
+    sim.step(args.warmup)
+    sim.init(inputs.spinodal(n, n, seed=d["seed"], amp=d["amp"]))
+    sim.synchronize()
+    energy, rms = [sim.free_energy()[0]], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(0, steps, every):
+        sim.step(every)
+        phi, mass, lo, hi = sim.moments()
+        energy.append(sim.free_energy()[0])
+        rms.append(float(np.sqrt(np.mean(phi * phi))))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    out = {"metric": "MLUPS, 1024^2 spinodal with checkpoints every 1000 steps (1 GPU)",
+           "value": round(n * n * steps / wall / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / steps, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 0)",
+           "config": {"workload": "spinodal-1024x1024-fp32-checkpointed", "alpha": d["alpha"], "m": d["m"],
+                      "checkpoint_every": every, "residency": "last-level cache (75 MB working set)"},
+           "energy_nonincreasing": bool(np.all(np.diff(energy) <= 0)),
+           "energy": {"start": energy[0], "end": energy[-1], "samples": len(energy)},
+           "phi_rms": {"after_10k": rms[9], "after_25k": rms[24], "after_50k": rms[-1]}}
+    print(json.dumps(out), flush=True)
+
+
 def ensemble_workload(args):
     """Throughput of the ragged ensemble: 512 periodic members (side log-uniform in [64, 512],
     alpha ~ U[0, 0.3], m in {4, 6}, spinodal / droplet 50/50, seed 3), FP32, advanced by one
@@ -656,11 +755,13 @@ def main():
     ap.add_argument("--tiling", type=str, default="", help="block_threads,rows_per_block (ensemble: [,depth], a fixed shape instead of the autotuner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n3", type=int, default=256, help="box side of the D3Q15 workload")
-    ap.add_argument("--workload", choices=["step", "step3d", "hybrid", "ensemble", "surrogate", "learned"],
+    ap.add_argument("--workload", choices=["step", "step3d", "hybrid", "ensemble", "surrogate", "learned", "droplet",
+                                           "c2"],
                     default="step",
                     help="step: throughput of lbch_step (the default line); hybrid: time-to-t of the jump "
                          "schedule; ensemble: the 512-member batch; surrogate: the network's MFMA throughput; "
-                         "learned: the 5-level network trained and measured on held-out runs")
+                         "learned: the 5-level network trained and measured on held-out runs; droplet: the "
+                         "64^2 FP64 droplet against the oracle; c2: the 1024^2 run with checkpoints")
     ap.add_argument("--hybrid-warm", type=int, default=80000)
     ap.add_argument("--hybrid-steps", type=int, default=200000)
     ap.add_argument("--hybrid-jump", type=int, default=400)
@@ -701,6 +802,12 @@ def main():
         return
     if args.workload == "learned":
         learned_workload(args)
+        return
+    if args.workload == "droplet":
+        droplet_workload(args)
+        return
+    if args.workload == "c2":
+        c2_workload(args)
         return
     if args.workload == "step3d":
         step3d_workload(args)

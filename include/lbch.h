@@ -287,9 +287,9 @@ lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t
  * rows_per_block in {the launch model's own height (the default tiling),
  * 8, ..., 512} (steps_per_trial launches each, reading
  * the current state and writing the idle buffer, so the state and the step
- * counter are unchanged), keeps the fastest per step (depth and tiling) and
- * returns its tiling (rows_per_block: the height in use) and time per
- * step.  Synchronises.  Before init ->
+ * counter are unchanged), keeps the fastest per step (depth and tiling),
+ * times it once more (steps_per_trial launches) and returns its tiling
+ * (rows_per_block: the height in use) and that time per step.  Synchronises.  Before init ->
  * LBCH_E_STATE.  D3Q15: every tile shape of lbch_set_tiling x z-sweep lengths
  * {model default, 4, 8, ..., 128} (at most nz). */
 lbch_status lbch_autotune(lbch_sim* sim, int32_t steps_per_trial, int32_t* block_threads,
