@@ -624,7 +624,8 @@ def ensemble_workload(args):
 def step3d_workload(args):
     """Throughput of the D3Q15 step (eq 21): a periodic n^3 box (default 256^3) of spinodal noise
     U(-0.05, 0.05) from seed 5 with the parameters of the two-dimensional workload (alpha = 0.2,
-    Willmore eps = 0.03, M = 0.1, D = 2 sqrt(2) 1.5, sigma = 0.01), one launch per step.
+    Willmore eps = 0.03, M = 0.1, D = 2 sqrt(2) 1.5, sigma = 0.01), one launch per step, tile
+    shape and z-sweep length from the autotuner unless --tiling is given.
     Algorithmic bytes per update: 15 populations read + 15 written."""
     import torch
 
@@ -646,6 +647,14 @@ def step3d_workload(args):
     phi0 = inputs.spinodal3(n, n, n, seed=d["seed"], amp=d["amp"])
     sim.init(phi0)
     del phi0
+    tuned = None
+    if not args.tiling:
+        # tile shape and z-sweep length from the library's autotuner (trials on the live state,
+        # which they leave untouched)
+        t_at = time.perf_counter()
+        bt_, hz_, ms_ = sim.autotune(args.autotune_steps)
+        tuned = {"block_threads": bt_, "z_slabs": hz_, "ms_per_step": round(ms_, 4),
+                 "launches_per_trial": args.autotune_steps, "seconds": round(time.perf_counter() - t_at, 2)}
     sim.step(args.warmup)
     sim.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -669,10 +678,12 @@ def step3d_workload(args):
         "data": "synthetic (seeded spinodal noise U(-0.05,0.05), seed 5)",
         "config": {"workload": f"spinodal-{n}^3-d3q15-{args.precision}", "grid": [n, n, n], "lattice": "D3Q15",
                    "alpha": d["alpha"], "regularization": "willmore", "eps_reg": d["eps_reg"],
-                   "mobility": d["mobility"], "time_steps_per_launch": 1, "tiling": list(tiling)},
+                   "mobility": d["mobility"], "time_steps_per_launch": 1, "tiling": list(tiling),
+                   "autotuned": tuned},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(nodes, args.precision, 1, "d3q15"), "kernel": "step3_fused",
+                     "traffic": measured_traffic(nodes, args.precision, 1, "d3q15", tiling=tiling),
+                     "kernel": "step3_fused",
                      "launch_ms": round(ms_step, 4), "updates_per_launch": nodes,
                      "bytes_per_update": bytes_per_update},
         "checks": {"mass": mass, "phi_min": lo, "phi_max": hi},

@@ -278,8 +278,9 @@ lbch_status lbch_get_time_blocking(const lbch_sim* sim, int32_t* depth);
  * CUs at the usual chunk, the shortest chunk of at least 4 rows that keeps at
  * most 2.5 tiles per CU).  D3Q15: block_threads is 512
  * (32 x 16 lanes storing 26 x 10 nodes) or, in FP32, 1024 (32 x 32 lanes
- * storing 26 x 26; the FP32 default) and rows_per_block is the number of z
- * slabs swept per workgroup. */
+ * storing 26 x 26; the FP32 default) or 988 (38 x 26 lanes storing 32 x 20:
+ * whole 128-byte rows when nx is a multiple of 32) and rows_per_block is the
+ * number of z slabs swept per workgroup. */
 lbch_status lbch_set_tiling(lbch_sim* sim, int32_t block_threads, int32_t rows_per_block);
 lbch_status lbch_get_tiling(const lbch_sim* sim, int32_t* block_threads, int32_t* rows_per_block);
 

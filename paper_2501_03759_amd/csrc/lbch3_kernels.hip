@@ -94,16 +94,20 @@ struct Stencil3 {
 // Fused step on D3Q15.  A workgroup of TX x TY lanes owns an x-y tile
 // (lane (tx, ty) -> column x0 - 3 + tx, row y0 - 3 + ty, wrapped) and sweeps
 // hz planes along z; iteration j pulls plane a = z0 - 3 + j and runs the four
-// lagging stages of the D2Q9 sweep (A: pull, phi, flux; B: grad phi, lap phi,
-// gamma, Q, w, mu_alpha at a-1; C: div Q, lap w -> mu_beta at a-2; D: grad
-// mu_beta, collision, store at a-3).  Stage outputs live in LDS rings of three
-// padded planes; every lane computes every stage and only the tile interior
-// (TX - 6) x (TY - 6) is stored.
+// stages of the D2Q9 sweep in two phases separated by one barrier, each stage
+// reading only planes that an earlier phase finished: phase 1 A (pull, phi,
+// flux at a) and C (div Q, lap w -> mu_beta at a-3); phase 2 B (grad phi,
+// lap phi, gamma, Q, w, mu_alpha at a-1) and D (grad mu_beta, collision,
+// store at a-4).  Two barriers per plane.  Stage outputs live in LDS rings of
+// three padded planes, each slot indexed by the iteration that wrote it
+// (j mod 3; register rings j mod 6, the plane loop unrolled six times so that
+// every slot is static); every lane computes every stage and only the tile
+// interior (TX - 6) x (TY - 6) is stored.
 // ---------------------------------------------------------------------------
 template <typename T, int TX, int TY, bool GEN>
 __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin, T* __restrict__ fout,
                                                        const Grid3 g, const Tiling3 tl, const StepCoef3<T> c) {
-    constexpr int RW = TX + 2, RH = TY + 2, U = 4;
+    constexpr int RW = TX + 2, RH = TY + 2, U = 6;
     __shared__ T s_phi[3][RH][RW];
     __shared__ T s_qx[3][RH][RW];
     __shared__ T s_qy[3][RH][RW];
@@ -133,12 +137,14 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
     const unsigned rc = (unsigned)(y * g.pitch), rm = (unsigned)(ym * g.pitch), rp = (unsigned)(yp * g.pitch);
     const unsigned oxy[9] = {(rc + x) * ES,  (rc + xm) * ES, (rc + xp) * ES, (rm + x) * ES, (rp + x) * ES,
                              (rm + xm) * ES, (rp + xp) * ES, (rp + xm) * ES, (rm + xp) * ES};
-    const int niter = hl + 6;
+    // D stores plane a - 4; the last iteration runs only C and D (no stage
+    // needs its planes a and a - 1)
+    const int niter = hl + 7;
 
-    T red[U][4];      // phi, j_x, j_y, j_z of the pulled node (A -> D)
-    T mua[U], tloc[U];
-    T buf[2][15];     // pulled populations of the next plane in flight
-    T fr[GEN ? 15 : 1];  // s_e, s_q != 1: the populations of plane a-3, pulled again
+    T red[U][4];        // phi, j_x, j_y, j_z of the pulled node (A -> D, four iterations later)
+    T mua[U], tloc[U];  // B -> D (three iterations later), B -> C (two)
+    T buf[2][15];       // pulled populations of the next plane in flight
+    T fr[GEN ? 15 : 1];  // s_e, s_q != 1: the populations of plane a-4, pulled again
 
     auto issue = [&](int za, T (&b)[15]) {
         const int zr = wrapi(za, g.nz);
@@ -161,78 +167,52 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
         for (int k = 0; k < U; ++k) {
             const int j = jb + k;
             if (j < niter) {
-                const int sN = j % 3, sC = (j + 2) % 3, sS = (j + 1) % 3;
+                const bool head = j + 1 < niter;
+                // LDS slots written by iterations j, j-1, j-2
+                const int s0 = k % 3, s1 = (k + 2) % 3, s2 = (k + 1) % 3;
+                // ======== phase 1 ========
                 // ---- A: plane a ----
-                {
+                if (head) {
                     const T(&f)[15] = buf[j & 1];
-                    const T s1 = ((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]);
-                    const T s2 = ((f[7] + f[8]) + (f[9] + f[10])) + ((f[11] + f[12]) + (f[13] + f[14]));
-                    const T phi = f[0] + s1 + s2;
+                    const T s1_ = ((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]);
+                    const T s2_ = ((f[7] + f[8]) + (f[9] + f[10])) + ((f[11] + f[12]) + (f[13] + f[14]));
+                    const T phi = f[0] + s1_ + s2_;
                     // flux sum_i e_i f_i from the four body-diagonal pairs
                     const T d7 = f[7] - f[8], d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14];
                     red[k][0] = phi;
                     red[k][1] = (f[1] - f[2]) + ((d7 + d9) + (d11 - d13));
                     red[k][2] = (f[3] - f[4]) + ((d7 + d9) - (d11 - d13));
                     red[k][3] = (f[5] - f[6]) + ((d7 - d9) + (d11 + d13));
-                    s_phi[sN][ly][lx] = phi;
+                    s_phi[s0][ly][lx] = phi;
                 }
-                if (j + 1 < niter) issue(z0 - 3 + j + 1, buf[(j + 1) & 1]);
-                // the addresses stage A read three iterations ago
+                if (j + 2 < niter) issue(z0 - 3 + j + 1, buf[(j + 1) & 1]);
+                // the addresses stage A read four iterations ago
                 if constexpr (GEN) {
-                    if (j >= 6) issue(z0 - 6 + j, fr);
+                    if (j >= 7) issue(z0 - 7 + j, fr);
                 }
-                lds_barrier3();
-                // ---- B: plane a-1 ----
-                if (j >= 2) {
-                    const Stencil3<T, RW> st{s_phi[sN], s_phi[sC], s_phi[sS]};
-                    const T px = st.gx(ly, lx, c), py = st.gy(ly, lx, c), pz = st.gz(ly, lx, c);
-                    const T lap = st.lap(ly, lx, c);
-                    const T pC = s_phi[sC][ly][lx];
-                    const T fb = c.beta4 * pC * (pC * pC - T(1));
-                    T gamma, hx, hy, hz;
-                    aniso3<T>(px, py, pz, c, gamma, hx, hy, hz);
-                    if (c.qform == 0) {
-                        s_qx[sN][ly][lx] = c.kappa * px * (gamma + hx);
-                        s_qy[sN][ly][lx] = c.kappa * py * (gamma + hy);
-                        s_qz[sN][ly][lx] = c.kappa * pz * (gamma + hz);
-                    } else {
-                        s_qx[sN][ly][lx] = gamma * c.kappa * px + px * hx;
-                        s_qy[sN][ly][lx] = gamma * c.kappa * py + py * hy;
-                        s_qz[sN][ly][lx] = gamma * c.kappa * pz + pz * hz;
-                    }
-                    T w, tl0 = (gamma - T(1)) * fb + c.kappa * lap;
-                    if (c.reg == REG_WILLMORE) {
-                        w = lap - fb;
-                        tl0 -= c.eps * (c.beta4 * (T(3) * pC * pC - T(1))) * w;
-                    } else if (c.reg == REG_LINEAR) {
-                        w = lap;
-                    } else {
-                        w = T(0);
-                    }
-                    s_w[sN][ly][lx] = w;
-                    tloc[k] = tl0;
-                    mua[k] = fb - c.kappa * lap;
-                }
-                lds_barrier3();
-                // ---- C: plane a-2 ----
-                if (j >= 4) {
-                    const Stencil3<T, RW> qx{s_qx[sN], s_qx[sC], s_qx[sS]};
-                    const Stencil3<T, RW> qy{s_qy[sN], s_qy[sC], s_qy[sS]};
-                    const Stencil3<T, RW> qz{s_qz[sN], s_qz[sC], s_qz[sS]};
-                    T mb = tloc[(k + U - 1) % U] - ((qx.gx(ly, lx, c) + qy.gy(ly, lx, c)) + qz.gz(ly, lx, c));
+                // ---- C: plane a-3; its Q and w planes come from B of iterations j-1 .. j-3 ----
+                if (j >= 5) {
+                    const Stencil3<T, RW> qx{s_qx[s1], s_qx[s2], s_qx[s0]};
+                    const Stencil3<T, RW> qy{s_qy[s1], s_qy[s2], s_qy[s0]};
+                    const Stencil3<T, RW> qz{s_qz[s1], s_qz[s2], s_qz[s0]};
+                    T mb = tloc[(k + U - 2) % U] - ((qx.gx(ly, lx, c) + qy.gy(ly, lx, c)) + qz.gz(ly, lx, c));
                     if (c.reg != REG_NONE) {
-                        const Stencil3<T, RW> ws{s_w[sN], s_w[sC], s_w[sS]};
+                        const Stencil3<T, RW> ws{s_w[s1], s_w[s2], s_w[s0]};
                         mb += c.eps * ws.lap(ly, lx, c);
                     }
-                    s_mb[sN][ly][lx] = mb;
+                    s_mb[s0][ly][lx] = mb;
                 }
                 lds_barrier3();
-                // ---- D: plane a-3 ----
-                if (j >= 6) {
-                    const Stencil3<T, RW> ms{s_mb[sN], s_mb[sC], s_mb[sS]};
+                // ======== phase 2 ========
+                // ---- D: plane a-4; its mu_beta planes come from C of iterations j .. j-2.
+                // D goes first so that its stores have B's time to complete before
+                // the next iteration waits on its loads (that wait covers every
+                // earlier load and store) ----
+                if (j >= 7) {
+                    const Stencil3<T, RW> ms{s_mb[s0], s_mb[s1], s_mb[s2]};
                     const T gx = ms.gx(ly, lx, c), gy = ms.gy(ly, lx, c), gz = ms.gz(ly, lx, c);
-                    const T(&r)[4] = red[(k + U - 3) % U];
-                    const T mu_a = mua[(k + U - 2) % U];
+                    const T(&r)[4] = red[(k + U - 4) % U];
+                    const T mu_a = mua[(k + U - 3) % U];
                     // e_i.(j - v g) and e_i.g for every direction
                     const T ax = c.u * (r[1] - c.v * gx), ay = c.u * (r[2] - c.v * gy), az = c.u * (r[3] - c.v * gz);
                     const T bx = c.hd * gx, by = c.hd * gy, bz = c.hd * gz;
@@ -264,7 +244,7 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                         }
                     }
                     if (store_lane) {
-                        const int rd = z0 - 6 + j;
+                        const int rd = z0 - 7 + j;
 #pragma unroll
                         for (int i = 0; i < 15; ++i) {
                             char* __restrict__ q = (char*)(fout + ((long long)i * g.plane + (long long)rd * g.slab));
@@ -272,6 +252,38 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                         }
                     }
                 }
+                // ---- B: plane a-1 ----
+                if (j >= 2 && head) {
+                    const Stencil3<T, RW> st{s_phi[s0], s_phi[s1], s_phi[s2]};
+                    const T px = st.gx(ly, lx, c), py = st.gy(ly, lx, c), pz = st.gz(ly, lx, c);
+                    const T lap = st.lap(ly, lx, c);
+                    const T pC = s_phi[s1][ly][lx];
+                    const T fb = c.beta4 * pC * (pC * pC - T(1));
+                    T gamma, hx, hy, hz;
+                    aniso3<T>(px, py, pz, c, gamma, hx, hy, hz);
+                    if (c.qform == 0) {
+                        s_qx[s0][ly][lx] = c.kappa * px * (gamma + hx);
+                        s_qy[s0][ly][lx] = c.kappa * py * (gamma + hy);
+                        s_qz[s0][ly][lx] = c.kappa * pz * (gamma + hz);
+                    } else {
+                        s_qx[s0][ly][lx] = gamma * c.kappa * px + px * hx;
+                        s_qy[s0][ly][lx] = gamma * c.kappa * py + py * hy;
+                        s_qz[s0][ly][lx] = gamma * c.kappa * pz + pz * hz;
+                    }
+                    T w, tl0 = (gamma - T(1)) * fb + c.kappa * lap;
+                    if (c.reg == REG_WILLMORE) {
+                        w = lap - fb;
+                        tl0 -= c.eps * (c.beta4 * (T(3) * pC * pC - T(1))) * w;
+                    } else if (c.reg == REG_LINEAR) {
+                        w = lap;
+                    } else {
+                        w = T(0);
+                    }
+                    s_w[s0][ly][lx] = w;
+                    tloc[k] = tl0;
+                    mua[k] = fb - c.kappa * lap;
+                }
+                lds_barrier3();
             }
         }
     }
@@ -446,18 +458,29 @@ int occ3(bool gen) {
 }
 }  // namespace
 
-bool tile3_supported(int precision, int tx, int ty) {
-    return (tx == 32 && ty == 16) || (precision == 1 && tx == 32 && ty == 32);
+// Tile shapes (lanes in x, lanes in y) by workgroup size: 512 = 32 x 16,
+// 1024 = 32 x 32 (FP32), 988 = 38 x 26 (FP32: a 32-column interior, so every
+// stored row is one whole 128-byte line when nx is a multiple of 32).
+bool tile3_shape(int precision, int block_threads, int* tx, int* ty) {
+    int x = 0, y = 0;
+    if (block_threads == 512) x = 32, y = 16;
+    else if (precision == 1 && block_threads == 1024) x = 32, y = 32;
+    else if (precision == 1 && block_threads == 988) x = 38, y = 26;
+    else return false;
+    if (tx) *tx = x;
+    if (ty) *ty = y;
+    return true;
 }
 
 int step3_blocks_per_cu(int precision, int tx, int ty, bool gen) {
     if (precision == 0) return occ3<double, 32, 16>(gen);
+    if (tx == 38) return occ3<float, 38, 26>(gen);
     return ty == 32 ? occ3<float, 32, 32>(gen) : occ3<float, 32, 16>(gen);
 }
 
-// hz = 0: the sweep length that minimises rounds * (hz + 6), where a round is
-// one wave of `slots` resident workgroups and hz + 6 the iterations of a
-// sweep (6 start-up slabs), over hz in [4, nz].
+// hz = 0: the sweep length that minimises rounds * (hz + 7), where a round is
+// one wave of `slots` resident workgroups and hz + 7 the iterations of a
+// sweep (7 start-up slabs), over hz in [4, nz].
 Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty) {
     Tiling3 t{};
     t.tx = tx;
@@ -471,7 +494,7 @@ Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty) 
         hz = nz;
         for (int h = nz < 4 ? nz : 4; h <= nz; ++h) {
             const long long tiles = cols * ((nz + h - 1) / h);
-            const long long cost = ((tiles + slots - 1) / slots) * (h + 6LL);
+            const long long cost = ((tiles + slots - 1) / slots) * (h + 7LL);
             if (best < 0 || cost < best) {
                 best = cost;
                 hz = h;
@@ -488,26 +511,28 @@ Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty) 
 
 hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3& g, const Tiling3& t,
                         const void* coef, hipStream_t s) {
-    if (!tile3_supported(precision, t.tx, t.ty)) return hipErrorInvalidValue;
+    int tx = 0, ty = 0;
+    if (!tile3_shape(precision, t.tx * t.ty, &tx, &ty) || tx != t.tx || ty != t.ty) return hipErrorInvalidValue;
     if (precision == 0) {
         const auto& c = *(const StepCoef3<double>*)coef;
         if (c.gen)
             step3_fused<double, 32, 16, true><<<t.nblocks, 512, 0, s>>>((const double*)fin, (double*)fout, g, t, c);
         else
             step3_fused<double, 32, 16, false><<<t.nblocks, 512, 0, s>>>((const double*)fin, (double*)fout, g, t, c);
+        return hipGetLastError();
+    }
+    const auto& c = *(const StepCoef3<float>*)coef;
+    const float* in = (const float*)fin;
+    float* out = (float*)fout;
+    if (tx == 38) {
+        if (c.gen) step3_fused<float, 38, 26, true><<<t.nblocks, 988, 0, s>>>(in, out, g, t, c);
+        else step3_fused<float, 38, 26, false><<<t.nblocks, 988, 0, s>>>(in, out, g, t, c);
+    } else if (ty == 32) {
+        if (c.gen) step3_fused<float, 32, 32, true><<<t.nblocks, 1024, 0, s>>>(in, out, g, t, c);
+        else step3_fused<float, 32, 32, false><<<t.nblocks, 1024, 0, s>>>(in, out, g, t, c);
     } else {
-        const auto& c = *(const StepCoef3<float>*)coef;
-        if (t.ty == 32) {
-            if (c.gen)
-                step3_fused<float, 32, 32, true><<<t.nblocks, 1024, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
-            else
-                step3_fused<float, 32, 32, false><<<t.nblocks, 1024, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
-        } else {
-            if (c.gen)
-                step3_fused<float, 32, 16, true><<<t.nblocks, 512, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
-            else
-                step3_fused<float, 32, 16, false><<<t.nblocks, 512, 0, s>>>((const float*)fin, (float*)fout, g, t, c);
-        }
+        if (c.gen) step3_fused<float, 32, 16, true><<<t.nblocks, 512, 0, s>>>(in, out, g, t, c);
+        else step3_fused<float, 32, 16, false><<<t.nblocks, 512, 0, s>>>(in, out, g, t, c);
     }
     return hipGetLastError();
 }

@@ -362,11 +362,13 @@ void fill_coef3(const lbch_params* p, StepCoef3<T>& c) {
     c.gen = se != 1.0 || sq != 1.0;
 }
 
-// D3Q15 tiling: block_threads 512 = 32 x 16 lanes, 1024 = 32 x 32 (FP32
-// only); 0 = the default of the precision.  hz = 0: the sweep-length model.
+// D3Q15 tiling: block_threads 512 = 32 x 16 lanes, 1024 = 32 x 32 and
+// 988 = 38 x 26 (FP32 only); 0 = the default of the precision.  hz = 0: the
+// sweep-length model.  block_threads must be one tile3_shape accepts.
 static Tiling3 sim_tiling3(const lbch_sim* s, int block_threads, int hz) {
     if (block_threads == 0) block_threads = s->precision == LBCH_FP32 ? 1024 : 512;
-    const int tx = 32, ty = block_threads / 32;
+    int tx = 32, ty = 16;
+    tile3_shape(s->precision, block_threads, &tx, &ty);
     return make_tiling3(s->g3.nx, s->g3.ny, s->g3.nz, hz,
                         s->cus * step3_blocks_per_cu(s->precision, tx, ty, s->c3d.gen != 0), tx, ty);
 }
@@ -747,9 +749,9 @@ extern "C" lbch_status lbch_set_tiling(lbch_sim* s, int32_t block_threads, int32
     lbch_status st = check_sim(s);
     if (st != LBCH_OK) return st;
     if (s->d3) {
-        if (block_threads != 0 && (block_threads % 32 != 0 || !tile3_supported(s->precision, 32, block_threads / 32)))
+        if (block_threads != 0 && !tile3_shape(s->precision, block_threads, nullptr, nullptr))
             return fail(LBCH_E_INVALID, "D3Q15 block_threads %d not in {0, 512%s}", block_threads,
-                        s->precision == LBCH_FP32 ? ", 1024" : "");
+                        s->precision == LBCH_FP32 ? ", 988, 1024" : "");
         if (rows_per_block < 0) return fail(LBCH_E_INVALID, "rows_per_block %d < 0", rows_per_block);
         s->t3 = sim_tiling3(s, block_threads, rows_per_block);
         return ok();
@@ -802,6 +804,9 @@ namespace {
 
 // D3Q15: every built tile shape x sweep lengths {4, 8, 16, 32, 64, 128, model}
 // (capped at nz), timed like the D2Q9 trials (idle buffer written, state kept).
+// The sweep-length model counts rounds of resident workgroups; measured, the
+// step is closer to bound by the total work (tiles x (hz + 7)), so the trials
+// decide.
 lbch_status autotune3(lbch_sim* s, int steps_per_trial, int32_t* block_threads, int32_t* rows_per_block,
                       double* ms_per_step) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -809,10 +814,10 @@ lbch_status autotune3(lbch_sim* s, int steps_per_trial, int32_t* block_threads, 
     HIP_TRY(hipEventCreate(&b));
     float best = -1.0f;
     Tiling3 best_t = s->t3;
-    const int shapes[2] = {512, 1024};
+    const int shapes[3] = {512, 988, 1024};
     const int hzs[7] = {0, 4, 8, 16, 32, 64, 128};
     for (int bt : shapes) {
-        if (!tile3_supported(s->precision, 32, bt / 32)) continue;
+        if (!tile3_shape(s->precision, bt, nullptr, nullptr)) continue;
         for (int hz : hzs) {
             if (hz > s->g3.nz) continue;
             const Tiling3 t = sim_tiling3(s, bt, hz);
@@ -836,12 +841,21 @@ lbch_status autotune3(lbch_sim* s, int steps_per_trial, int32_t* block_threads, 
             }
         }
     }
+    s->t3 = best_t;
+    // the winner timed once more on its own (as for D2Q9)
+    float ms = 0.0f;
+    hipError_t e = hipEventRecord(a, s->stream);
+    for (int k = 0; e == hipSuccess && k < steps_per_trial; ++k)
+        e = launch_step3(s->precision, s->f[s->cur], s->f[s->cur ^ 1], s->g3, s->t3, coef_ptr(s), s->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    s->t3 = best_t;
+    if (e != hipSuccess) return fail(LBCH_E_DEVICE, "autotune trial failed: %s", hipGetErrorString(e));
     if (block_threads) *block_threads = best_t.tx * best_t.ty;
     if (rows_per_block) *rows_per_block = best_t.hz;
-    if (ms_per_step) *ms_per_step = best / steps_per_trial;
+    if (ms_per_step) *ms_per_step = ms / steps_per_trial;
     return LBCH_OK;
 }
 

@@ -188,7 +188,7 @@ struct StepCoef3 {
 template <typename T>
 void fill_coef3(const lbch_params* p, StepCoef3<T>& c);
 Tiling3 make_tiling3(int nx, int ny, int nz, int hz, int slots, int tx, int ty);
-bool tile3_supported(int precision, int tx, int ty);
+bool tile3_shape(int precision, int block_threads, int* tx, int* ty);
 int step3_blocks_per_cu(int precision, int tx, int ty, bool gen);
 hipError_t launch_step3(int precision, const void* fin, void* fout, const Grid3& g, const Tiling3& t,
                         const void* coef, hipStream_t s);

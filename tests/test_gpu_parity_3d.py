@@ -106,7 +106,7 @@ def test_wavy_layer_trt_fp32_1000_steps():
     p = with_rates(params3(nx, ny, nz, 1, alpha=0.3), L.COLLISION_TRT)
     phi0 = inputs.wavy_slab(nx, ny, nz, 1.5, 6.0, 18.0)
     want = common.oracle_phi3(phi0, p, 1000)
-    for threads in (512, 1024):
+    for threads in (512, 988, 1024):
         print(f"case wavy3 trt threads={threads}", flush=True)
         got = run3(p, phi0, 1000, threads=threads)
         assert np.abs(got - want).max() <= FP32_TOL, threads
@@ -119,7 +119,7 @@ def test_z_sweep_length_is_bitwise_trt(precision):
     p = with_rates(params3(nx, ny, nz, precision, alpha=0.3), s=(1, 1.3, 1.3, 1, 0.8, 1, 0.8, 1.3, 1.3))
     phi0 = inputs.spinodal3(nx, ny, nz, seed=12, amp=0.2)
     ref = run3(p, phi0, 40)
-    shapes = (512, 1024) if precision == 1 else (512,)
+    shapes = (512, 988, 1024) if precision == 1 else (512,)
     for threads in shapes:
         for hz in (1, 4, 19):
             print(f"case rates threads={threads} hz={hz} precision={precision}", flush=True)
@@ -137,7 +137,7 @@ def test_wavy_layer_fp32_1000_steps():
     p = params3(nx, ny, nz, 1, alpha=0.3)
     phi0 = inputs.wavy_slab(nx, ny, nz, 1.5, 6.0, 18.0)
     want = common.oracle_phi3(phi0, p, 1000)
-    for threads in (512, 1024):
+    for threads in (512, 988, 1024):
         got = run3(p, phi0, 1000, threads=threads)
         assert np.abs(got - want).max() <= FP32_TOL, threads
 
@@ -148,7 +148,7 @@ def test_z_sweep_length_is_bitwise(precision):
     p = params3(nx, ny, nz, precision, alpha=0.3)
     phi0 = inputs.spinodal3(nx, ny, nz, seed=11, amp=0.2)
     ref = run3(p, phi0, 40)
-    shapes = (512, 1024) if precision == 1 else (512,)
+    shapes = (512, 988, 1024) if precision == 1 else (512,)
     for threads in shapes:
         for hz in (1, 4, 7, 19):
             print(f"case threads={threads} hz={hz} precision={precision}", flush=True)
@@ -298,7 +298,7 @@ def test_unsupported_options():
         s.init(inputs.spinodal3(30, 12, 8, seed=1))
         ref = s.phi()
         bt, hz, ms = s.autotune(2)                 # trials leave the state untouched
-        assert bt in (512, 1024) and 1 <= hz <= 8 and ms > 0 and s.tiling() == (bt, hz)
+        assert bt in (512, 988, 1024) and 1 <= hz <= 8 and ms > 0 and s.tiling() == (bt, hz)
         assert np.array_equal(s.phi(), ref) and s.nstep == 0
         with pytest.raises(L.LbchError) as ei:
             L.hybrid_advance(s, None, L.hybrid_opts(extrapolate=1), 100)
@@ -307,9 +307,10 @@ def test_unsupported_options():
         L.Batch([p])
     assert ei.value.status == L.E_UNSUPPORTED
     with L.Sim(params3(30, 12, 8, 0)) as s:
-        with pytest.raises(L.LbchError) as ei:
-            s.set_tiling(1024, 0)                  # 32 x 32 lanes exceed the LDS in FP64
-        assert ei.value.status == L.E_INVALID
+        for bad in (988, 1024):                    # 38 x 26 and 32 x 32 lanes exceed the LDS in FP64
+            with pytest.raises(L.LbchError) as ei:
+                s.set_tiling(bad, 0)
+            assert ei.value.status == L.E_INVALID
         assert s.tiling()[0] == 512
 
 
