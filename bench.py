@@ -698,7 +698,8 @@ def surrogate_workload(args):
     """Throughput of the surrogate network's forward and training step on 16 periodic 256 x 256
     patches: the 5-level U-Net (32, 64, 128, 256, 256 channels), inputs phi plus 4 conditioning
     planes, BF16 MFMA with FP32 accumulation.  FLOPs are the network's own 3x3 and 1x1
-    convolutions (2 per multiply-add, real input channels); a training step counts 3x forward."""
+    convolutions (2 per multiply-add, real input channels); a training step counts 3x forward.
+    Also times inference on one whole --n x --n field (the hybrid's jump, default 8192^2)."""
     import torch
 
     from paper_2501_03759_amd import lbsg
@@ -736,6 +737,31 @@ def surrogate_workload(args):
         ms = a.elapsed_time(e) / args.steps
         res[what] = (ms, mult * flops / (ms * 1e-3) / 1e12)
     net.close()
+    # inference on one whole n x n periodic field (the hybrid's jump; weights do not change the time)
+    n = args.n
+    inf_flops = 0.0
+    prev = c_in
+    for l, c in enumerate(chans):
+        inf_flops += 18.0 * (prev * c + c * c) * (n >> l) ** 2
+        prev = c
+    for l in range(len(chans) - 2, -1, -1):
+        inf_flops += 18.0 * ((chans[l + 1] + chans[l]) * chans[l] + chans[l] * chans[l]) * (n >> l) ** 2
+    inf_flops += 2.0 * chans[0] * n * n
+    inf = lbsg.Surrogate(chans, c_in, 1, n, n, train=False, seed=0, stream=stream, out_scale=0.02)
+    phi = torch.empty((n, n), dtype=torch.float32, device="cuda").uniform_(-1, 1, generator=g)
+    o = torch.empty_like(phi)
+    cond = [0.2, 1.0, 0.0, 4.0 / 6.0][: c_in - 1]
+    for _ in range(2):
+        inf.predict(phi.data_ptr(), cond, n, n, o.data_ptr())
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(5):
+        inf.predict(phi.data_ptr(), cond, n, n, o.data_ptr())
+    e.record(stream)
+    e.synchronize()
+    inf_ms = a.elapsed_time(e) / 5
+    inf.close()
+    del phi, o
     fwd_ms, fwd_tf = res["forward"]
     out_line = {
         "metric": "surrogate forward TFLOP/s, 16 x 256^2 patches (1 GPU)", "value": round(fwd_tf, 1),
@@ -747,6 +773,7 @@ def surrogate_workload(args):
         "roofline": {"bound": "mfma", "achieved": round(fwd_tf, 1), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(fwd_tf / 2500.0, 4), "traffic": None, "kernel": "conv3_fwd_k (all layers)"},
         "train_step": {"ms": round(res["train_step"][0], 3), "TFLOP/s": round(res["train_step"][1], 1)},
+        "inference": {"field": [n, n], "ms": round(inf_ms, 2), "TFLOP/s": round(inf_flops / (inf_ms * 1e-3) / 1e12, 1)},
     }
     if not args.no_cpu_baseline:
         out_line["cpu_baseline"] = cpu_baseline_unet(chans, c_in)

@@ -109,7 +109,7 @@ def run_both(levels, chans, hw, bias_shift, seed, B=2, bf16=True, conditioned=Fa
 
 OPS = [(2, 32, 48, 32, 64), (1, 16, 16, 96, 32), (3, 48, 32, 64, 128)]
 # at >= 512 (16 x 16 tile, 64-channel block) pairs the forward takes 64-channel workgroups
-OPS_FWD = OPS + [(2, 256, 256, 32, 64), (1, 256, 512, 64, 128)]
+OPS_FWD = OPS + [(2, 256, 256, 32, 64), (1, 256, 512, 64, 128), (4, 256, 256, 32, 32), (2, 256, 512, 64, 32)]
 
 
 def diag():
@@ -148,7 +148,7 @@ def test_mfma_conv_forward_exact_on_bf16_inputs(n, h, w, ci, co):
 
 # (n, h, w, cu, cs, co): 32- and 64-channel workgroups, one and several chunks per source
 OPS_UPCAT = [(2, 32, 48, 64, 32, 32), (3, 16, 32, 32, 64, 64), (2, 256, 256, 64, 32, 64), (1, 256, 256, 32, 64, 128),
-             (1, 128, 256, 256, 128, 128)]
+             (1, 128, 256, 256, 128, 128), (4, 256, 256, 64, 32, 32)]
 
 
 @pytest.mark.parametrize("n,h,w,cu,cs,co", OPS_UPCAT)
@@ -179,7 +179,7 @@ def test_mfma_conv_of_upsampled_concat_exact_on_bf16_inputs(n, h, w, cu, cs, co)
 
 
 @pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 64),
-                                         (1, 64, 64, 128, 256)])
+                                         (1, 64, 64, 128, 256), (4, 256, 256, 32, 32)])
 def test_mfma_conv_with_fused_pooling_is_bitwise(n, h, w, ci, co):
     # y equals the plain ReLU kernel's output and yp the 2x2 average of it with the pooling
     # kernel's arithmetic: bf16(0.25 ((a + b) + (c + d))) in FP32, bit for bit
@@ -209,7 +209,8 @@ def test_mfma_conv_with_fused_pooling_is_bitwise(n, h, w, ci, co):
 
 @pytest.mark.parametrize("n,h,w,cu,cs,co,masked", [(2, 32, 48, 64, 32, 32, True), (1, 64, 64, 128, 64, 64, True),
                                                      (2, 256, 256, 64, 64, 32, True), (1, 32, 32, 96, 32, 64, True),
-                                                     (1, 32, 64, 64, 32, 32, False)])
+                                                     (1, 32, 64, 64, 32, 32, False),
+                                                     (4, 256, 256, 32, 32, 32, True)])
 def test_data_gradient_through_upsampling_adjoint_is_bitwise(n, h, w, cu, cs, co, masked):
     # the decoder's first convolution: its data gradient's up channels summed over 2x2
     # blocks in the kernel's order ((a + b) + c) + d, its skip channels stored, both masked,
@@ -253,7 +254,7 @@ def test_data_gradient_through_upsampling_adjoint_is_bitwise(n, h, w, cu, cs, co
 # (4, 128, 128, 128, 64): 256 tiles x 2 blocks of 64 output channels reach the 64-channel workgroups
 @pytest.mark.parametrize("n,h,w,ci,co,masked", [(2, 32, 48, 32, 64, True), (1, 64, 64, 64, 128, True),
                                                  (4, 128, 128, 64, 64, True), (1, 16, 32, 96, 32, False),
-                                                 (4, 128, 128, 128, 64, True)])
+                                                 (4, 128, 128, 128, 64, True), (4, 256, 256, 32, 32, True)])
 def test_data_gradient_through_pooling_adjoint_is_bitwise(n, h, w, ci, co, masked):
     # an encoder level's first convolution: its data gradient, spread over the 2x2 children
     # and accumulated into the finer level's gradient as bf16(0.25 dx + old), then masked,
@@ -286,7 +287,8 @@ def test_data_gradient_through_pooling_adjoint_is_bitwise(n, h, w, ci, co, maske
     assert torch.equal(dx2.cpu(), want)
 
 
-@pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 32)])
+@pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 64, 32), (1, 48, 32, 96, 64), (2, 256, 256, 32, 32),
+                                         (4, 256, 256, 32, 32)])
 def test_mfma_conv_with_fused_head(n, h, w, ci, co):
     # the BF16 activations are those of the plain kernel; only the FP32 order of the
     # head's channel sum differs from a sequential dot product
@@ -320,7 +322,7 @@ def test_mfma_conv_with_fused_head(n, h, w, ci, co):
     assert np.all(np.abs(got - ref) <= bound), np.abs(got - ref).max()
 
 
-@pytest.mark.parametrize("n,h,w,ci,co", OPS)
+@pytest.mark.parametrize("n,h,w,ci,co", OPS + [(4, 256, 256, 32, 32)])
 def test_mfma_conv_gradients_exact_on_bf16_inputs(n, h, w, ci, co):
     import torch
     L = diag()
