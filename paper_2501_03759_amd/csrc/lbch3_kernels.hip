@@ -88,6 +88,19 @@ struct Stencil3 {
     }
 };
 
+// phi and the flux sum_i e_i f_i of one node's fifteen populations, in the
+// fixed order both users share (the flux from the four body-diagonal pairs)
+template <typename T>
+__device__ __forceinline__ void moments15(const T (&f)[15], T (&r)[4]) {
+    const T s1 = ((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]);
+    const T s2 = ((f[7] + f[8]) + (f[9] + f[10])) + ((f[11] + f[12]) + (f[13] + f[14]));
+    const T d7 = f[7] - f[8], d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14];
+    r[0] = f[0] + s1 + s2;
+    r[1] = (f[1] - f[2]) + ((d7 + d9) + (d11 - d13));
+    r[2] = (f[3] - f[4]) + ((d7 + d9) - (d11 - d13));
+    r[3] = (f[5] - f[6]) + ((d7 - d9) + (d11 + d13));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
     // needs its planes a and a - 1)
     const int niter = hl + 7;
 
-    T red[U][4];        // phi, j_x, j_y, j_z of the pulled node (A -> D, four iterations later)
+    T red[GEN ? 1 : U][4];  // phi, j_x, j_y, j_z of the pulled node (A -> D, four iterations later)
     T mua[U], tloc[U];  // B -> D (three iterations later), B -> C (two)
     T buf[2][15];       // pulled populations of the next plane in flight
     T fr[GEN ? 15 : 1];  // s_e, s_q != 1: the populations of plane a-4, pulled again
@@ -173,17 +186,15 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                 // ======== phase 1 ========
                 // ---- A: plane a ----
                 if (head) {
-                    const T(&f)[15] = buf[j & 1];
-                    const T s1_ = ((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]);
-                    const T s2_ = ((f[7] + f[8]) + (f[9] + f[10])) + ((f[11] + f[12]) + (f[13] + f[14]));
-                    const T phi = f[0] + s1_ + s2_;
-                    // flux sum_i e_i f_i from the four body-diagonal pairs
-                    const T d7 = f[7] - f[8], d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14];
-                    red[k][0] = phi;
-                    red[k][1] = (f[1] - f[2]) + ((d7 + d9) + (d11 - d13));
-                    red[k][2] = (f[3] - f[4]) + ((d7 + d9) - (d11 - d13));
-                    red[k][3] = (f[5] - f[6]) + ((d7 - d9) + (d11 + d13));
-                    s_phi[s0][ly][lx] = phi;
+                    // the class-rate collision pulls the node again and takes phi and the
+                    // flux from there, so only the unit-rate one keeps them in registers
+                    T r[4];
+                    moments15<T>(buf[j & 1], r);
+                    if constexpr (!GEN) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) red[k][q] = r[q];
+                    }
+                    s_phi[s0][ly][lx] = r[0];
                 }
                 if (j + 2 < niter) issue(z0 - 3 + j + 1, buf[(j + 1) & 1]);
                 // the addresses stage A read four iterations ago
@@ -211,7 +222,9 @@ __global__ __launch_bounds__(TX * TY) void step3_fused(const T* __restrict__ fin
                 if (j >= 7) {
                     const Stencil3<T, RW> ms{s_mb[s0], s_mb[s1], s_mb[s2]};
                     const T gx = ms.gx(ly, lx, c), gy = ms.gy(ly, lx, c), gz = ms.gz(ly, lx, c);
-                    const T(&r)[4] = red[(k + U - 4) % U];
+                    T rg[4];
+                    if constexpr (GEN) moments15<T>(fr, rg);
+                    const T(&r)[4] = GEN ? rg : red[(k + U - 4) % U];
                     const T mu_a = mua[(k + U - 3) % U];
                     // e_i.(j - v g) and e_i.g for every direction
                     const T ax = c.u * (r[1] - c.v * gx), ay = c.u * (r[2] - c.v * gy), az = c.u * (r[3] - c.v * gz);
