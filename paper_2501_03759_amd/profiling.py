@@ -147,18 +147,25 @@ def unet_layers(chans, c_in, batch, side):
     return out
 
 
-def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500.0, peak_gbs=8000.0):
+def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500.0, peak_gbs=8000.0,
+                 after_training=False):
     """Per-layer table of the network's forward convolutions: launch time (kernel trace),
     TFLOP/s, MfmaUtil and HBM traffic (--pmc runs), and each layer's roofline
     min(peak MFMA, arithmetic intensity x peak HBM) on its algorithmic bytes.  Dispatches of
-    conv3_fwd_k before the first weight-gradient dispatch are the forward passes, in layer order."""
+    conv3_fwd_k before the first weight-gradient dispatch are the forward passes, in layer order
+    (with after_training: those after the last weight-gradient dispatch, the inference passes
+    that follow the training steps)."""
     layers = unet_layers(chans, c_in, batch, side)
     n = len(layers)
 
     def fwd_rows(rows, start_key):
         rows = sorted(rows, key=lambda r: int(r[start_key]))
-        first_dw = next((i for i, r in enumerate(rows) if "conv3_dw_k" in r["Kernel_Name"]), len(rows))
-        return [r for r in rows[:first_dw] if "conv3_fwd_k" in r["Kernel_Name"]]
+        dws = [i for i, r in enumerate(rows) if "conv3_dw_k" in r["Kernel_Name"]]
+        if after_training:
+            sel = rows[(dws[-1] + 1 if dws else 0):]
+        else:
+            sel = rows[:(dws[0] if dws else len(rows))]
+        return [r for r in sel if "conv3_fwd_k" in r["Kernel_Name"]]
 
     trace = fwd_rows(list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))))),
                      "Start_Timestamp")
@@ -230,10 +237,13 @@ def main():
                     help="use only the last N dispatches of the kernel (runs that also launch it in other shapes)")
     ap.add_argument("--unet", default="", help="per-layer summary of the network's forward: "
                     "chans,c_in,batch,side (e.g. 32-64-128-256-256,5,16,256); --trace plus --sq runs")
+    ap.add_argument("--unet-inference", action="store_true",
+                    help="take the forward passes after the training steps (the whole-field inference)")
     args = ap.parse_args()
     if args.unet:
         ch, cin, bsz, side = args.unet.split(",")
-        table = unet_profile(args.trace, args.sq, [int(v) for v in ch.split("-")], int(cin), int(bsz), int(side))
+        table = unet_profile(args.trace, args.sq, [int(v) for v in ch.split("-")], int(cin), int(bsz), int(side),
+                             after_training=args.unet_inference)
         lines = [f"# rocprofv3 summary: {args.title or 'network forward, per layer'}", "", "Commands:", ""]
         lines += ["    " + c for c in args.command.split(";;")]
         lines += ["", "Forward 3x3 convolutions in launch order (pooling, upsampling-concatenation and the head "
