@@ -32,6 +32,15 @@ lbch_status lbch_diag_copy(const void* src, void* dst, int64_t bytes, void* hip_
 lbch_status lbsg_diag_conv3(const float* x, const float* w, const float* bias, float* y, int32_t n, int32_t h,
                             int32_t wd, int32_t ci, int32_t co, int32_t relu);
 
+/* The network's first convolution with its K packed (ci <= 8 real input
+ * channels: 12 taps x 8 channels instead of 9 taps x 32): y as
+ * lbsg_diag_conv3 with ReLU for x[N][H][W][ci] (phi NULL), or, with x NULL,
+ * for the input whose channel 0 is phi[N][H][W] and whose channels 1..ci-1
+ * are the constants cond[0..ci-2] (host array); both forms give the same
+ * bits for the same input. */
+lbch_status lbsg_diag_conv3_first(const float* x, const float* phi, const float* cond, const float* w, const float* bias,
+                                  float* y, int32_t n, int32_t h, int32_t wd, int32_t ci, int32_t co);
+
 /* As lbsg_diag_conv3 on the channel concatenation [nearest 2x upsampling of
  * u[N][H/2][W/2][Cu], sk[N][H][W][Cs]] (Ci = Cu + Cs), read by the kernel
  * from its two sources (the decoder's first convolution).  Cu, Cs multiples

@@ -8,7 +8,8 @@ namespace lbsg {
 
 // Segments of the one-launch weight packing (pack_all): per segment the
 // FP32 master W[co][ci][3][3], its BF16 output, and the layout: flip 0 ->
-// out[co][tap][cip] (zero padded ci), flip 1 -> out[ci][8 - tap][co].
+// out[co][tap][cip] (zero padded ci), flip 1 -> out[ci][8 - tap][co],
+// flip 2 -> out[co][12][8] (the K-packed first layer, ci <= 8).
 constexpr int kPackMaxSeg = 64;
 struct PackAll {
     int nseg;
@@ -51,6 +52,12 @@ hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* b
 hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd,
                                int Ci, int Co, const float* hw, const float* hb, const float* xin, int cin, float* out,
                                float scale, hipStream_t s);
+// The first convolution (ci <= 8 real channels) with K = 12 taps x 8
+// channels: input the packed X (channel stride Cs) or, X null, phi[N][H][W]
+// FP32 with the constant values cond[0..ncond) as channels 1..ncond; Wk
+// [Co][12][8] (pack flip 2); bias, ReLU.  Both input forms give the same bits.
+hipError_t conv3_first(const __bf16* X, int Cs, const float* phi, const float* cond, int ncond, const __bf16* Wk,
+                       const float* bias, __bf16* Y, int N, int H, int Wd, int Co, hipStream_t s);
 // Weight-gradient split partials; bpart (nullable, S x Co floats) receives the
 // bias gradient's split partials, reduced beside the weights by wgrad_reduce.
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,

@@ -383,6 +383,111 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 }
 
 // ---------------------------------------------------------------------------
+// The network's first convolution (at most 8 real input channels) with its K
+// packed.  The generic kernel pads the input to 32 channels and runs 9 taps x
+// 32 channels, of which at most 9 x 8 carry data; here K = 12 taps x 8
+// channels (taps 9..11 zero): three matrix-core K-steps instead of nine.  In
+// K-step s, lane group kb holds tap t = 4 s + kb (t = 3 ky + kx) and its 8
+// channels.  Wk is [Co][12][8] BF16 (zero past the real channels and taps).
+// The input is either the packed tensor X (channel stride Cs, its first 8
+// channels read) or, with X null, phi[N][H][W] (FP32) and the constant
+// conditioning values cond[0..ncond) (device), rounded to BF16 as the packing
+// rounds them: both forms give the same bits.  32 output channels per
+// workgroup over a 16-column, TH-row pixel tile (the weights are staged once
+// for it; each wave takes TH / 4 rows, four at a time); bias and ReLU in the
+// epilogue; the result fragment of a lane is as in conv3_fwd_k.
+// ---------------------------------------------------------------------------
+template <int TH>
+__global__ __launch_bounds__(256, 2) void conv3_first_k(const __bf16* __restrict__ X, int Cs,
+                                                       const float* __restrict__ phi, const float* __restrict__ cond,
+                                                       int ncond, const __bf16* __restrict__ Wk,
+                                                       const float* __restrict__ bias, __bf16* __restrict__ Y, int H,
+                                                       int Wd, int Co) {
+    constexpr int CB = 2, RPW = TH / 4;
+    __shared__ __align__(16) __bf16 sx[(TH + 2) * 18 * 8];
+    __shared__ __align__(16) __bf16 sw[32 * 12 * 8];
+    const int tiles_x = Wd / 16, tiles_y = H / TH;
+    int b = blockIdx.x;
+    const int tx0 = (b % tiles_x) * 16;
+    b /= tiles_x;
+    const int ty0 = (b % tiles_y) * TH;
+    const int n = b / tiles_y;
+    const int co0 = blockIdx.y * 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, kb = lane >> 4;
+    for (int q = threadIdx.x; q < (TH + 2) * 18; q += 256) {
+        const int py = q / 18, px = q - py * 18;
+        const int y = wrap(ty0 - 1 + py, H), x = wrap(tx0 - 1 + px, Wd);
+        const size_t p = ((size_t)n * H + y) * Wd + x;
+        bf16x8 v;
+        if (X) {
+            v = *reinterpret_cast<const bf16x8*>(X + p * Cs);
+        } else {
+            v[0] = (__bf16)phi[p];
+#pragma unroll
+            for (int c = 1; c < 8; ++c) v[c] = (__bf16)(c <= ncond ? cond[c - 1] : 0.f);
+        }
+        *reinterpret_cast<bf16x8*>(sx + q * 8) = v;
+    }
+    for (int q = threadIdx.x; q < 32 * 12; q += 256)
+        *reinterpret_cast<bf16x8*>(sw + q * 8) = *reinterpret_cast<const bf16x8*>(Wk + ((size_t)co0 * 12 + q) * 8);
+    __syncthreads();
+    // the lane's A fragments of the three K-steps, and its bias values
+    bf16x8 a[3][CB];
+    float bv[CB][4];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            a[s][c] = *reinterpret_cast<const bf16x8*>(sw + ((c * 16 + l16) * 12 + 4 * s + kb) * 8);
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[c][j] = bias ? bias[co0 + c * 16 + kb * 4 + j] : 0.f;
+    for (int g = 0; g < RPW / 4; ++g) {
+        const int r0 = wave * RPW + g * 4;    // first of the four rows (tile coordinates)
+        f32x4 acc[4][CB];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int t = 4 * s + kb;
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            bf16x8 bq[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (t < 9) {
+                    bq[r] = *reinterpret_cast<const bf16x8*>(sx + ((r0 + r + ky) * 18 + l16 + kx) * 8);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) bq[r][c] = (__bf16)0.f;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(a[s][c], bq[r], acc[r][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = ty0 + r0 + r, x = tx0 + l16;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                bf16x4 o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float v = acc[r][c][j] + bv[c][j];
+                    o[j] = (__bf16)(v > 0.f ? v : 0.f);
+                }
+                *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co0 + c * 16 + kb * 4) = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient of the 3x3 convolution on the matrix cores:
 //   P[s][co][tap][ci] = sum over the pixels of split s of dY[p][co] X[p + tap][ci]
 // GEMM per tap: M = co, N = ci, K = pixels.  Per 16x16 pixel tile the
@@ -680,7 +785,11 @@ __global__ void pack_all_k(const PackAll t) {
     for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
          j += (long long)gridDim.x * blockDim.x) {
         const int Co = t.co[sg], Ci = t.ci[sg];
-        if (!t.flip[sg]) {
+        if (t.flip[sg] == 2) {
+            // first layer, K packed: out[co][t][c], 12 taps x 8 channels, zero past the real ones
+            const int c = (int)(j % 8), tp = (int)((j / 8) % 12), co = (int)(j / 96);
+            t.out[sg][j] = (__bf16)(tp < 9 && c < Ci ? t.W[sg][((size_t)co * Ci + c) * 9 + tp] : 0.f);
+        } else if (!t.flip[sg]) {
             const int Cip = t.cip[sg];
             const int ci = (int)(j % Cip), tap = (int)((j / Cip) % 9), co = (int)(j / (9LL * Cip));
             t.out[sg][j] = (__bf16)(ci < Ci ? t.W[sg][((size_t)co * Ci + ci) * 9 + tap] : 0.f);
@@ -950,6 +1059,20 @@ hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* b
         conv3_fwd_k<32, true, false, false, true><<<dim3(tiles, Co / 32), 256, 0, s>>>(X, nullptr, 0, Wt, bias, Y, H,
                                                                                       Wd, Ci, Co, HeadArgs{}, Yp);
     }
+    return hipGetLastError();
+}
+
+hipError_t conv3_first(const __bf16* X, int Cs, const float* phi, const float* cond, int ncond, const __bf16* Wk,
+                       const float* bias, __bf16* Y, int N, int H, int Wd, int Co, hipStream_t s) {
+    if (H % 16 || Wd % 16 || Co % 32 || ncond < 0 || ncond > 7 || (X ? (Cs < 8 || Cs % 8) : (!phi || (ncond && !cond))))
+        return hipErrorInvalidValue;
+    // 64-row tiles where H allows (the weights staged once per 1024 pixels), else 16
+    if (H % 64 == 0)
+        conv3_first_k<64><<<dim3(N * (H / 64) * (Wd / 16), Co / 32), 256, 0, s>>>(X, Cs, phi, cond, ncond, Wk, bias,
+                                                                               Y, H, Wd, Co);
+    else
+        conv3_first_k<16><<<dim3(N * (H / 16) * (Wd / 16), Co / 32), 256, 0, s>>>(X, Cs, phi, cond, ncond, Wk, bias,
+                                                                               Y, H, Wd, Co);
     return hipGetLastError();
 }
 

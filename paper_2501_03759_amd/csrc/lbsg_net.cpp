@@ -31,6 +31,7 @@ struct Layer {
     long long offW, offB;
     __bf16* wt = nullptr;     // [co][9][ci_pad]
     __bf16* wf = nullptr;     // [ci_pad][9][co] flipped (data gradient), not for the first layer
+    __bf16* wk = nullptr;     // [co][12][8] K-packed (the first layer with at most 8 input channels)
 };
 
 struct Level {
@@ -106,7 +107,7 @@ lbch_status repack(lbsg_net* n) {
     long long end = 0;
     auto add = [&](const Layer& L, __bf16* out, int flip) {
         const int sg = t.nseg++;
-        end += flip ? (long long)L.ci_real * 9 * L.co : (long long)L.co * 9 * L.ci_pad;
+        end += flip == 2 ? (long long)L.co * 96 : flip ? (long long)L.ci_real * 9 * L.co : (long long)L.co * 9 * L.ci_pad;
         t.end[sg] = end;
         t.W[sg] = n->w + L.offW;
         t.out[sg] = out;
@@ -117,9 +118,10 @@ lbch_status repack(lbsg_net* n) {
     };
     for (const Layer& L : n->layers) {
         if (L.k != 3) continue;
-        if (t.nseg + 2 > lbsg::kPackMaxSeg) return fail(LBCH_E_INVALID, "too many layers to pack");
+        if (t.nseg + 3 > lbsg::kPackMaxSeg) return fail(LBCH_E_INVALID, "too many layers to pack");
         add(L, L.wt, 0);
         if (L.wf) add(L, L.wf, 1);
+        if (L.wk) add(L, L.wk, 2);
     }
     HIP_TRY(lbsg::pack_all(t, n->stream));
     return ok();
@@ -173,8 +175,10 @@ lbch_status check_shape(const lbsg_net* n, int B, int H, int W) {
     return ok();
 }
 
-// everything after the packed input (z_0) is in place
-lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, int cres) {
+// everything after the packed input (z_0) is in place; with phi (not null) the
+// first convolution reads phi and the conditioning values n->cond (in_ch - 1
+// of them) directly instead (z_0 is then not formed)
+lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, int cres, const float* phi = nullptr) {
     const int Lv = n->arch.levels;
     const int* C = n->arch.chans;
     int li = 0;
@@ -183,7 +187,11 @@ lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, in
         Level& lv = n->lv[l];
         const Layer& La = n->layers[li++];
         const Layer& Lb = n->layers[li++];
-        HIP_TRY(lbsg::conv3_fwd(lv.z, La.wt, n->w + La.offB, lv.a, B, h, w, La.ci_pad, La.co, true, n->stream));
+        if (La.wk)   // the first layer, its at most 8 input channels packed into K
+            HIP_TRY(lbsg::conv3_first(phi ? nullptr : lv.z, 32, phi, n->cond, n->arch.in_ch - 1, La.wk,
+                                      n->w + La.offB, lv.a, B, h, w, La.co, n->stream));
+        else
+            HIP_TRY(lbsg::conv3_fwd(lv.z, La.wt, n->w + La.offB, lv.a, B, h, w, La.ci_pad, La.co, true, n->stream));
         if (l + 1 < Lv)   // the next level's input, pooled in the epilogue
             HIP_TRY(lbsg::conv3_fwd_relu_pool(lv.a, Lb.wt, n->w + Lb.offB, lv.e, n->lv[l + 1].z, B, h, w, Lb.ci_pad,
                                               Lb.co, n->stream));
@@ -353,6 +361,7 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
         L.wt = A.get<__bf16>((size_t)L.co * 9 * L.ci_pad);
         if (n->train && &L != &n->layers[0]) L.wf = A.get<__bf16>((size_t)L.co * 9 * L.ci_pad);
     }
+    if (arch->in_ch <= 8) n->layers[0].wk = A.get<__bf16>((size_t)n->layers[0].co * 96);
     n->out = A.get<float>(P0);
     n->xin1 = A.get<float>(P0);
     n->cond = A.get<float>(32);
@@ -499,8 +508,14 @@ extern "C" lbch_status lbsg_predict(lbsg_net* n, const float* phi, const float* 
     if (st != LBCH_OK) return st;
     if (ncond > 0) HIP_TRY(hipMemcpyAsync(n->cond, cond, ncond * sizeof(float), hipMemcpyHostToDevice, n->stream));
     const long long P0 = (long long)H * W;
-    HIP_TRY(lbsg::pack_phi_cond(phi, n->cond, ncond, n->lv[0].z, n->xin1, P0, 32, n->stream));
-    st = forward_body(n, 1, H, W, n->xin1, 1);
+    if (!n->train && n->layers[0].wk) {
+        // inference only: the first convolution reads phi itself (no packed copy; a
+        // training net keeps the packed input, which its backward pass reads)
+        st = forward_body(n, 1, H, W, phi, 1, phi);
+    } else {
+        HIP_TRY(lbsg::pack_phi_cond(phi, n->cond, ncond, n->lv[0].z, n->xin1, P0, 32, n->stream));
+        st = forward_body(n, 1, H, W, n->xin1, 1);
+    }
     if (st != LBCH_OK) return st;
     HIP_TRY(hipMemcpyAsync(phi_out, n->out, P0 * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
     HIP_TRY(hipStreamSynchronize(n->stream));     // cond is a host array the copy reads
@@ -546,6 +561,39 @@ extern "C" lbch_status lbsg_diag_conv3(const float* x, const float* w, const flo
     HIP_TRY(lbsg::pack_input(x, xb, P, ci, ci, nullptr));
     HIP_TRY(lbsg::pack_w(w, wt, co, ci, ci, nullptr));
     HIP_TRY(lbsg::conv3_fwd(xb, wt, bias, yb, n, h, wd, ci, co, relu != 0, nullptr));
+    HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return LBCH_OK;
+}
+
+extern "C" lbch_status lbsg_diag_conv3_first(const float* x, const float* phi, const float* cond, const float* w,
+                                             const float* bias, float* y, int32_t n, int32_t h, int32_t wd, int32_t ci,
+                                             int32_t co) {
+    if ((x == nullptr) == (phi == nullptr) || !w || !y || (phi && ci > 1 && !cond))
+        return fail(LBCH_E_INVALID, "exactly one of x and phi, and w, y (and cond with phi) are needed");
+    if (ci < 1 || ci > 8) return fail(LBCH_E_INVALID, "ci = %d not in 1..8", ci);
+    lbch_status st = diag_shape(n, h, wd, 32, co);
+    if (st != LBCH_OK) return st;
+    Scratch S;
+    const long long P = (long long)n * h * wd;
+    __bf16* xb = x ? S.get<__bf16>(P * 32) : nullptr;
+    __bf16* wk = S.get<__bf16>((size_t)co * 96);
+    __bf16* yb = S.get<__bf16>(P * co);
+    float* cd = S.get<float>(8);
+    if ((x && !xb) || !wk || !yb || !cd) return fail(LBCH_E_OOM, "scratch allocation failed");
+    if (x) HIP_TRY(lbsg::pack_input(x, xb, P, ci, 32, nullptr));
+    if (phi && ci > 1) HIP_TRY(hipMemcpy(cd, cond, (ci - 1) * sizeof(float), hipMemcpyHostToDevice));
+    lbsg::PackAll t{};
+    t.nseg = 1;
+    t.end[0] = (long long)co * 96;
+    t.W[0] = w;
+    t.out[0] = wk;
+    t.co[0] = co;
+    t.ci[0] = ci;
+    t.cip[0] = 8;
+    t.flip[0] = 2;
+    HIP_TRY(lbsg::pack_all(t, nullptr));
+    HIP_TRY(lbsg::conv3_first(xb, 32, phi, cd, ci - 1, wk, bias, yb, n, h, wd, co, nullptr));
     HIP_TRY(lbsg::widen(yb, y, P * co, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return LBCH_OK;

@@ -146,6 +146,43 @@ def test_mfma_conv_forward_exact_on_bf16_inputs(n, h, w, ci, co):
         assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n,h,w,ci,co", [(2, 32, 48, 5, 32), (1, 64, 64, 1, 64), (4, 256, 256, 5, 32),
+                                         (1, 48, 32, 8, 32)])
+def test_first_layer_with_packed_k_exact_and_phi_form_bitwise(n, h, w, ci, co):
+    # the first convolution with its <= 8 input channels packed into K (12 taps x 8): exact on
+    # BF16 inputs; fed phi and constant conditioning values directly, it gives the bits it gives
+    # on the packed input holding them
+    import ctypes
+    import torch
+    L = diag()
+    fn = L.lbsg_diag_conv3_first
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int32] * 5
+    rng = np.random.default_rng(ci * 31 + co)
+    x = bf16_round(rng.normal(size=(n, h, w, ci)))
+    W = bf16_round(rng.normal(size=(co, ci, 3, 3)) * 0.3)
+    b = rng.normal(size=co) * 0.1
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    xt, wt, bt = dev(x), dev(W), dev(b)
+    y = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    print(f"case first layer {(n, h, w, ci, co)}", flush=True)
+    assert fn(xt.data_ptr(), None, None, wt.data_ptr(), bt.data_ptr(), y.data_ptr(), n, h, w, ci, co) == 0
+    ref = np.maximum(unet.conv3(x, W, b.astype(np.float32).astype(np.float64)), 0)
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+    # constant planes 1..ci-1: the packed form against the phi form
+    cond = (np.arange(1, ci) * 0.37 - 0.9).astype(np.float32)
+    xc = x.copy()
+    xc[..., 1:] = bf16_round(cond.astype(np.float64))
+    yc = torch.empty_like(y)
+    yp = torch.empty_like(y)
+    assert fn(dev(xc).data_ptr(), None, None, wt.data_ptr(), bt.data_ptr(), yc.data_ptr(), n, h, w, ci, co) == 0
+    pt = dev(x[..., 0])
+    cp = cond.ctypes.data_as(ctypes.c_void_p) if ci > 1 else None
+    assert fn(None, pt.data_ptr(), cp, wt.data_ptr(), bt.data_ptr(), yp.data_ptr(), n, h, w, ci, co) == 0
+    assert torch.equal(yc.cpu(), yp.cpu())
+
+
 # (n, h, w, cu, cs, co): 32- and 64-channel workgroups, one and several chunks per source
 OPS_UPCAT = [(2, 32, 48, 64, 32, 32), (3, 16, 32, 32, 64, 64), (2, 256, 256, 64, 32, 64), (1, 256, 256, 32, 64, 128),
              (1, 128, 256, 256, 128, 128), (4, 256, 256, 64, 32, 32)]
