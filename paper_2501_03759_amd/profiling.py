@@ -135,7 +135,7 @@ def unet_layers(chans, c_in, batch, side):
     for l in range(L):
         px = batch * (side >> l) ** 2
         ci = c_in if l == 0 else chans[l - 1]
-        cin_stored = 32 if l == 0 else chans[l - 1]
+        cin_stored = c_in if l == 0 else chans[l - 1]   # the first layer reads only the real channels
         out.append((f"enc{l}a", px, ci, chans[l], 2 * px * (cin_stored + chans[l])))
         pooled = px // 4 * chans[l] if l + 1 < L else 0
         out.append((f"enc{l}b", px, chans[l], chans[l], 2 * (px * 2 * chans[l] + pooled)))
@@ -152,7 +152,8 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
     """Per-layer table of the network's forward convolutions: launch time (kernel trace),
     TFLOP/s, MfmaUtil and HBM traffic (--pmc runs), and each layer's roofline
     min(peak MFMA, arithmetic intensity x peak HBM) on its algorithmic bytes.  Dispatches of
-    conv3_fwd_k before the first weight-gradient dispatch are the forward passes, in layer order
+    conv3_first_k and conv3_fwd_k before the first weight-gradient dispatch are the forward
+    passes, in layer order
     (with after_training: those after the last weight-gradient dispatch, the inference passes
     that follow the training steps)."""
     layers = unet_layers(chans, c_in, batch, side)
@@ -165,7 +166,7 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
             sel = rows[(dws[-1] + 1 if dws else 0):]
         else:
             sel = rows[:(dws[0] if dws else len(rows))]
-        return [r for r in sel if "conv3_fwd_k" in r["Kernel_Name"]]
+        return [r for r in sel if "conv3_fwd_k" in r["Kernel_Name"] or "conv3_first_k" in r["Kernel_Name"]]
 
     trace = fwd_rows(list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))))),
                      "Start_Timestamp")

@@ -75,13 +75,25 @@ def test_unet_layer_table_from_a_synthetic_trace(tmp_path):
         t += 10
         for i in range(6):
             dur = 1000 * (i + 1) * (2 if g == 0 else 1)
-            rows.append([f"void lbsg::conv3_fwd_k<32, true, false>", t, t + dur])
+            name = "void lbsg::conv3_first_k<64>" if i == 0 else "void lbsg::conv3_fwd_k<32, true, false>"
+            rows.append([name, t, t + dur])
             t += dur + 10
     rows.append(["void lbsg::conv3_dw_k<64>", t, t + 100])
-    rows.append(["void lbsg::conv3_fwd_k<32, true, false>", t + 200, t + 99999])
+    t += 200
+    # after the training step: two inference passes (the first a warm-up)
+    for g in range(2):
+        for i in range(6):
+            dur = 3000 * (i + 1) * (2 if g == 0 else 1)
+            name = "void lbsg::conv3_first_k<64>" if i == 0 else "void lbsg::conv3_fwd_k<32, true, false>"
+            rows.append([name, t, t + dur])
+            t += dur + 10
     _write_csv(str(tmp_path / "tr" / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
     table = profiling.unet_profile(str(tmp_path / "tr"), [], (32, 64), 5, 2, 32)
     assert [round(r["us"], 3) for r in table] == [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
     r0 = table[0]
     assert r0["gflop"] == 18.0 * 2 * 32 * 32 * 5 * 32 / 1e9
+    # the first layer's algorithmic bytes: its 5 real input channels and 32 output channels, BF16
+    assert r0["ai"] == r0["gflop"] * 1e9 / (2 * 2 * 32 * 32 * (5 + 32))
     assert r0["roofline_tflops"] == min(2500.0, r0["ai"] * 8.0)
+    inf = profiling.unet_profile(str(tmp_path / "tr"), [], (32, 64), 5, 2, 32, after_training=True)
+    assert [round(r["us"], 3) for r in inf] == [3.0, 6.0, 9.0, 12.0, 15.0, 18.0]
