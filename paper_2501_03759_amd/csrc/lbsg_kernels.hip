@@ -493,11 +493,11 @@ __global__ __launch_bounds__(256, 2) void conv3_first_k(const __bf16* __restrict
 // GEMM per tap: M = co, N = ci, K = pixels.  Per 16x16 pixel tile the
 // workgroup copies, channels-last as in HBM, the tile's dY (TCO channels) and
 // the X halo (18 x 18 pixels, 16 channels of the ci block) into LDS with
-// 16-byte stores.  The operands need 8 consecutive pixels of one channel per
-// lane; gfx950's transposing LDS read (ds_read_b64_tr_b16) delivers them: in a
-// group of 16 lanes, lane m reads 4 channels (4 (m & 3) ..) of pixel pb + m/4,
-// and lane i receives channel i of pixels pb .. pb + 3.  Two such reads give
-// one operand.  The A operand (dY) of a K step serves all nine taps.  The next
+// 16-byte stores.  The operands need 8 pixels of one channel per lane;
+// gfx950's transposing LDS read (ds_read_b64_tr_b16) delivers them: in a group
+// of 16 lanes, lane m reads 4 channels (4 (m & 3) ..) of pixel pb + m/4, and
+// lane i receives channel i of pixels pb .. pb + 3.  Two such reads (four
+// pixels of a row, then the same four of the next row) give one operand.  The A operand (dY) of a K step serves all nine taps.  The next
 // tile's global loads are in flight during the MFMAs.  Wave w owns output
 // channels 16w..16w+15 and all 9 taps of a 16-channel ci block.  Splits are
 // reduced by wgrad_reduce_k (fixed order: deterministic).  With bpart, the
@@ -527,10 +527,11 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
                                                       const __bf16* __restrict__ X2, int Cu) {
     constexpr int NT = TCO * 4;          // 64 threads (one wave) per 16 output channels
     // LDS strides (bf16) of one dY pixel and one X halo pixel, chosen by
-    // measurement (SQ_LDS_BANK_CONFLICT): the 16-byte stores are conflict-free
-    // at 72 / 32 / 16, and the transposing reads cost their minimum there (a
-    // 64-element dY stride doubles their cost)
-    constexpr int SP = TCO == 64 ? 72 : 32;
+    // measurement (SQ_LDS_BANK_CONFLICT per LDS-active cycle): with the K steps
+    // over row spans, 80 / 16 leave the 64-channel kernel without conflicts
+    // (72: 0.12) and 32 / 16 the 32-channel one at 0.11 (48: 0.21); the time
+    // differs by about 1 % between these (before the row spans: 0.43)
+    constexpr int SP = TCO == 64 ? 80 : 32;
     constexpr int SXP = 16;
     constexpr int NYQ = 256 * TCO / 8, NYI = NYQ / NT;           // dY 16-byte chunks (NYI = 8 per thread)
     constexpr int NXQ = 18 * 18 * 2, NXI = (NXQ + NT - 1) / NT;  // X halo chunks, the last item guarded
@@ -605,16 +606,18 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
         __syncthreads();
         if (tile + S < ntiles) load_tile(tile + S);
 #pragma unroll
-        for (int k0 = 0; k0 < 256; k0 += 32) {
-            // this lane group's 8 pixels k0 + 8 kb .. + 7: tile row py, columns px0 .. px0 + 7
-            const int k = k0 + kb * 8, py = k >> 4, px0 = k & 15;
-            const __bf16* pa = sdy + (k + mp) * SP + wave * 16 + mc;
-            const bf16x8 a = cat8(lds_read_tr(pa), lds_read_tr(pa + 4 * SP));
+        for (int py = 0; py < 16; py += 2) {
+            // a K step is the 32 pixels of tile rows py and py + 1; lane group kb takes
+            // columns 4 kb .. 4 kb + 3 of both rows, so that each transposing read of a
+            // wave covers 16 consecutive pixels of one row (one contiguous span of the
+            // halo tile: free of bank conflicts)
+            const __bf16* pa = sdy + (py * 16 + kb * 4 + mp) * SP + wave * 16 + mc;
+            const bf16x8 a = cat8(lds_read_tr(pa), lds_read_tr(pa + 16 * SP));
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                const __bf16* pb = sx + ((py + 1 + dy) * 18 + px0 + 1 + dx + mp) * SXP + mc;
-                const bf16x8 bb = cat8(lds_read_tr(pb), lds_read_tr(pb + 4 * SXP));
+                const __bf16* pb = sx + ((py + 1 + dy) * 18 + kb * 4 + 1 + dx + mp) * SXP + mc;
+                const bf16x8 bb = cat8(lds_read_tr(pb), lds_read_tr(pb + 18 * SXP));
                 acc[tap] = mfma16(a, bb, acc[tap]);
             }
         }
