@@ -58,6 +58,12 @@ hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* b
 // [Co][12][8] (pack flip 2); bias, ReLU.  Both input forms give the same bits.
 hipError_t conv3_first(const __bf16* X, int Cs, const float* phi, const float* cond, int ncond, const __bf16* Wk,
                        const float* bias, __bf16* Y, int N, int H, int Wd, int Co, hipStream_t s);
+// Inference: the first encoder block at 32 channels in one launch, a =
+// relu(conv3_first(phi, cond) + b1) kept in LDS, E = relu(conv3(a) + b2) and
+// P (N x H/2 x Wd/2 x 32) its 2x2 average; W1k as conv3_first, W2 [32][9][32].
+// Bitwise the same E and P as conv3_first followed by conv3_fwd_relu_pool.
+hipError_t conv3_pair0(const float* phi, const float* cond, int ncond, const __bf16* W1k, const float* b1,
+                       const __bf16* W2, const float* b2, __bf16* E, __bf16* P, int N, int H, int Wd, hipStream_t s);
 // Weight-gradient split partials; bpart (nullable, S x Co floats) receives the
 // bias gradient's split partials, reduced beside the weights by wgrad_reduce.
 hipError_t conv3_dw(const __bf16* X, const __bf16* dY, float* part, int S, int N, int H, int Wd, int Ci, int Co,

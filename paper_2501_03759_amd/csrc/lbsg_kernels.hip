@@ -488,6 +488,193 @@ __global__ __launch_bounds__(256, 2) void conv3_first_k(const __bf16* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// The first encoder block at 32 channels, fused for inference:
+//   a = relu(conv3_first(phi, cond) + b1)   (the K-packed first convolution)
+//   E = relu(conv3(a) + b2), P = its 2x2 average
+// with a kept in LDS.  A workgroup stages both layers' weights once and then
+// takes NT 16 x 16 output tiles stacked in y, one after the other: per tile, a
+// is formed over the tile and its 1-pixel halo (18 x 18: each row as two
+// 16-pixel segments, columns 0..15 and 2..17, the second storing only 16 and
+// 17) from a 20 x 20 tile of phi (loaded into registers while the previous
+// tile's second convolution runs), then the second convolution runs on it as
+// conv3_fwd_k does on its staged input (taps in the same order, one 32-channel
+// chunk) with the pooling epilogue.  Every value is formed with the same
+// operations in the same order as the two separate launches, so E and P are
+// bitwise theirs; the block's intermediate a never reaches HBM.
+// W1k: [32][12][8] (pack flip 2), W2: [32][9][32] (the generic packed layout).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict__ phi, const float* __restrict__ cond,
+                                                       int ncond, const __bf16* __restrict__ W1k,
+                                                       const float* __restrict__ b1, const __bf16* __restrict__ W2,
+                                                       const float* __restrict__ b2, __bf16* __restrict__ E,
+                                                       __bf16* __restrict__ P, int H, int Wd) {
+    constexpr int CB = 2;
+    constexpr int NPQ = (20 * 20 + 255) / 256;   // phi values per thread and tile
+    __shared__ __align__(16) __bf16 sphi[20 * 20 * 8];
+    __shared__ __align__(16) __bf16 sa[18 * 18 * 32];
+    __shared__ __align__(16) __bf16 sw1[32 * 12 * 8];
+    __shared__ __align__(16) __bf16 sw2[9 * 32 * 32];
+    const int tiles_x = Wd / 16, groups_y = H / (16 * NT);
+    int b = blockIdx.x;
+    const int tx0 = (b % tiles_x) * 16;
+    b /= tiles_x;
+    const int gy0 = (b % groups_y) * 16 * NT;
+    const int n = b / groups_y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, kb = lane >> 4;
+    float pv[NPQ];
+    auto load_phi = [&](int ty0) {
+#pragma unroll
+        for (int i = 0; i < NPQ; ++i) {
+            const int q = (int)threadIdx.x + i * 256;
+            if (q < 20 * 20) {
+                const int py = q / 20, px = q - py * 20;
+                const int y = wrap(ty0 - 2 + py, H), x = wrap(tx0 - 2 + px, Wd);
+                pv[i] = phi[((size_t)n * H + y) * Wd + x];
+            }
+        }
+    };
+    load_phi(gy0);
+    for (int q = threadIdx.x; q < 32 * 12; q += 256)
+        *reinterpret_cast<bf16x8*>(sw1 + q * 8) = *reinterpret_cast<const bf16x8*>(W1k + (size_t)q * 8);
+    // second convolution's weights as conv3_fwd_k stages them: row tap * 32 + co
+    for (int q = threadIdx.x; q < 9 * 32 * 4; q += 256) {
+        const int row = q >> 2, part = q & 3;
+        const int tap = row / 32, co = row - tap * 32;
+        *reinterpret_cast<bf16x8*>(sw2 + lds_part(row, part)) =
+            *reinterpret_cast<const bf16x8*>(W2 + ((size_t)co * 9 + tap) * 32 + part * 8);
+    }
+    // the first layer's input vector of a pixel: bf16(phi), the conditioning values, zeros
+    bf16x8 cv;
+    cv[0] = (__bf16)0.f;
+#pragma unroll
+    for (int c = 1; c < 8; ++c) cv[c] = (__bf16)(c <= ncond ? cond[c - 1] : 0.f);
+    __syncthreads();
+    bf16x8 a1[3][CB], aq2[9][CB];
+    float bv1[CB][4], bv[CB][4];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            a1[s][c] = *reinterpret_cast<const bf16x8*>(sw1 + ((c * 16 + l16) * 12 + 4 * s + kb) * 8);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int kx = t / 3, ky = t % 3;
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            aq2[t][c] = *reinterpret_cast<const bf16x8*>(sw2 + lds_part((ky * 3 + kx) * 32 + c * 16 + l16, kb));
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            bv1[c][j] = b1 ? b1[c * 16 + kb * 4 + j] : 0.f;
+            bv[c][j] = b2 ? b2[c * 16 + kb * 4 + j] : 0.f;
+        }
+    for (int it = 0; it < NT; ++it) {
+        const int ty0 = gy0 + 16 * it;
+        if (it > 0) __syncthreads();              // every wave is done with the previous tile's sphi, sa
+#pragma unroll
+        for (int i = 0; i < NPQ; ++i) {
+            const int q = (int)threadIdx.x + i * 256;
+            if (q < 20 * 20) {
+                bf16x8 v = cv;
+                v[0] = (__bf16)pv[i];
+                *reinterpret_cast<bf16x8*>(sphi + q * 8) = v;
+            }
+        }
+        __syncthreads();
+        if (it + 1 < NT) load_phi(ty0 + 16);   // the next tile's phi in flight during this one
+        // ---- stage 1: a over the 18 x 18 halo tile (36 row segments, 9 per wave) ----
+        for (int rt = wave; rt < 36; rt += 4) {
+            const int r = rt >> 1, c0 = (rt & 1) * 2;   // halo row, first column of the segment
+            f32x4 acc[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int t = 4 * s + kb;
+                const int ky = t / 3, kx = t - 3 * (t / 3);
+                bf16x8 bq;
+                if (t < 9) {
+                    bq = *reinterpret_cast<const bf16x8*>(sphi + ((r + ky) * 20 + c0 + l16 + kx) * 8);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) bq[c] = (__bf16)0.f;
+                }
+#pragma unroll
+                for (int c = 0; c < CB; ++c) acc[c] = mfma16(a1[s][c], bq, acc[c]);
+            }
+            const int col = c0 + l16;
+            if (c0 == 0 || col >= 16) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    bf16x4 o;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float v = acc[c][j] + bv1[c][j];
+                        o[j] = (__bf16)(v > 0.f ? v : 0.f);
+                    }
+                    // channels c * 16 + 4 kb .. + 3: 16-byte part 2 c + kb / 2, half kb & 1
+                    *reinterpret_cast<bf16x4*>(sa + lds_part(r * 18 + col, 2 * c + (kb >> 1)) + (kb & 1) * 4) = o;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- stage 2: the second convolution over the output tile, taps t = 3 kx + ky ----
+        f32x4 acc[4][CB];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int kx = t / 3, ky = t % 3;
+            bf16x8 bq[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                bq[r] = *reinterpret_cast<const bf16x8*>(sa + lds_part((wave * 4 + ky + r) * 18 + l16 + kx, kb));
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq2[t][c], bq[r], acc[r][c]);
+        }
+        bf16x4 prev[CB];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = ty0 + wave * 4 + r, x = tx0 + l16;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int co = c * 16 + kb * 4;
+                bf16x4 o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v = acc[r][c][j] + bv[c][j];
+                    v = v > 0.f ? v : 0.f;
+                    o[j] = (__bf16)v;
+                }
+                *reinterpret_cast<bf16x4*>(E + (((size_t)n * H + y) * Wd + x) * 32 + co) = o;
+                if ((r & 1) == 0) {
+                    prev[c] = o;
+                } else {
+                    // even lanes: ((a + b) + (c + d)) with a, b the upper row, c, d this one
+                    bf16x4 q;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float up = (float)prev[c][j], lo = (float)o[j];
+                        q[j] = (__bf16)(0.25f * ((up + lane_xor1(up)) + (lo + lane_xor1(lo))));
+                    }
+                    if ((l16 & 1) == 0)
+                        *reinterpret_cast<bf16x4*>(P + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * 32 + co) =
+                            q;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient of the 3x3 convolution on the matrix cores:
 //   P[s][co][tap][ci] = sum over the pixels of split s of dY[p][co] X[p + tap][ci]
 // GEMM per tap: M = co, N = ci, K = pixels.  Per 16x16 pixel tile the
@@ -1076,6 +1263,18 @@ hipError_t conv3_first(const __bf16* X, int Cs, const float* phi, const float* c
     else
         conv3_first_k<16><<<dim3(N * (H / 16) * (Wd / 16), Co / 32), 256, 0, s>>>(X, Cs, phi, cond, ncond, Wk, bias,
                                                                                Y, H, Wd, Co);
+    return hipGetLastError();
+}
+
+hipError_t conv3_pair0(const float* phi, const float* cond, int ncond, const __bf16* W1k, const float* b1,
+                       const __bf16* W2, const float* b2, __bf16* E, __bf16* P, int N, int H, int Wd, hipStream_t s) {
+    if (H % 16 || Wd % 16 || ncond < 0 || ncond > 7 || !phi || (ncond && !cond) || !E || !P)
+        return hipErrorInvalidValue;
+    // four tiles per workgroup where H allows (the weights staged once per 1024 pixels)
+    if (H % 64 == 0)
+        conv3_pair0_k<4><<<dim3(N * (H / 64) * (Wd / 16)), 256, 0, s>>>(phi, cond, ncond, W1k, b1, W2, b2, E, P, H, Wd);
+    else
+        conv3_pair0_k<1><<<dim3(N * (H / 16) * (Wd / 16)), 256, 0, s>>>(phi, cond, ncond, W1k, b1, W2, b2, E, P, H, Wd);
     return hipGetLastError();
 }
 

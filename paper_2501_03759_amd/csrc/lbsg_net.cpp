@@ -187,6 +187,12 @@ lbch_status forward_body(lbsg_net* n, int B, int H, int W, const float* xres, in
         Level& lv = n->lv[l];
         const Layer& La = n->layers[li++];
         const Layer& Lb = n->layers[li++];
+        if (l == 0 && phi && La.wk && La.co == 32 && Lv > 1) {
+            // inference: the whole first block in one launch, its intermediate kept on chip
+            HIP_TRY(lbsg::conv3_pair0(phi, n->cond, n->arch.in_ch - 1, La.wk, n->w + La.offB, Lb.wt, n->w + Lb.offB,
+                                      lv.e, n->lv[1].z, B, h, w, n->stream));
+            continue;
+        }
         if (La.wk)   // the first layer, its at most 8 input channels packed into K
             HIP_TRY(lbsg::conv3_first(phi ? nullptr : lv.z, 32, phi, n->cond, n->arch.in_ch - 1, La.wk,
                                       n->w + La.offB, lv.a, B, h, w, La.co, n->stream));
