@@ -157,7 +157,7 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
     (with after_training: those after the last weight-gradient dispatch, the inference passes
     that follow the training steps)."""
     layers = unet_layers(chans, c_in, batch, side)
-    n = len(layers)
+    conv_names = ("conv3_fwd_k", "conv3_first_k", "conv3_pair0_k")
 
     def fwd_rows(rows, start_key):
         rows = sorted(rows, key=lambda r: int(r[start_key]))
@@ -166,10 +166,17 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
             sel = rows[(dws[-1] + 1 if dws else 0):]
         else:
             sel = rows[:(dws[0] if dws else len(rows))]
-        return [r for r in sel if "conv3_fwd_k" in r["Kernel_Name"] or "conv3_first_k" in r["Kernel_Name"]]
+        return [r for r in sel if any(c in r["Kernel_Name"] for c in conv_names)]
 
     trace = fwd_rows(list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))))),
                      "Start_Timestamp")
+    if any("conv3_pair0_k" in r["Kernel_Name"] for r in trace):
+        # the first block in one launch: one row for both convolutions, whose algorithmic
+        # bytes are the block's input and its outputs (the intermediate stays on chip)
+        (na, px, ci, co, ba), (nb, _, cib, cob, bb) = layers[0], layers[1]
+        inter = 2 * px * co
+        layers = [("enc0a+b", px, ci, co, ba + bb - 2 * inter, 18.0 * px * (ci * co + cib * cob))] + layers[2:]
+    n = len(layers)
     groups = len(trace) // n
     if groups < 2:
         raise ValueError(f"{len(trace)} forward convolutions in the trace, not several passes of {n}")
@@ -189,9 +196,10 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
                 if vals:
                     ctr[i][cname] = statistics.mean(vals)
     table = []
-    for i, (name, px, ci, co, abytes) in enumerate(layers):
+    for i, lay in enumerate(layers):
+        name, px, ci, co, abytes = lay[:5]
         ns = statistics.mean(durs[i])
-        flop = 18.0 * px * ci * co
+        flop = lay[5] if len(lay) > 5 else 18.0 * px * ci * co
         ai = flop / abytes
         roof = min(peak_tflops, ai * peak_gbs / 1e3)
         tf = flop / (ns * 1e-9) / 1e12

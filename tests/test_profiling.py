@@ -97,3 +97,25 @@ def test_unet_layer_table_from_a_synthetic_trace(tmp_path):
     assert r0["roofline_tflops"] == min(2500.0, r0["ai"] * 8.0)
     inf = profiling.unet_profile(str(tmp_path / "tr"), [], (32, 64), 5, 2, 32, after_training=True)
     assert [round(r["us"], 3) for r in inf] == [3.0, 6.0, 9.0, 12.0, 15.0, 18.0]
+
+
+def test_unet_inference_table_with_the_fused_first_block(tmp_path):
+    # inference passes whose first block is one launch (conv3_pair0_k): one row for both
+    # convolutions, with the block's input and outputs as its bytes (no intermediate)
+    from paper_2501_03759_amd import profiling
+    rows, t = [], 0
+    rows.append(["void lbsg::conv3_dw_k<64>", t, t + 100])
+    t += 200
+    for g in range(3):
+        names = ["lbsg::conv3_pair0_k<4>"] + ["void lbsg::conv3_fwd_k<32, true, false>"] * 4
+        for i, name in enumerate(names):
+            dur = 1000 * (i + 1)
+            rows.append([name, t, t + dur])
+            t += dur + 10
+    _write_csv(str(tmp_path / "tr" / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    table = profiling.unet_profile(str(tmp_path / "tr"), [], (32, 64), 5, 1, 64, after_training=True)
+    assert [r["layer"] for r in table] == ["enc0a+b", "enc1a", "enc1b", "dec0a", "dec0b"]
+    assert [round(r["us"], 3) for r in table] == [1.0, 2.0, 3.0, 4.0, 5.0]
+    px = 64 * 64
+    assert table[0]["gflop"] == 18.0 * px * (5 * 32 + 32 * 32) / 1e9
+    assert table[0]["alg_bytes"] == 2 * px * (5 + 32) + 2 * (px // 4) * 32
