@@ -816,7 +816,7 @@ def main():
     ap.add_argument("--c4-hybrid", action="store_true", help="learned: also the time-to-t with the network's jump")
     ap.add_argument("--c4-correct", type=int, default=10, help="learned hybrid: correction steps per jump")
     ap.add_argument("--c4-hybrid-inner", type=str, default="0,0")
-    ap.add_argument("--time-to-t-plain", type=int, default=20000,
+    ap.add_argument("--time-to-t-plain", type=int, default=15000,
                     help="default line: plain steps of the hybrid run before its first jump (the spinodal "
                          "growth amplifies early jump errors)")
     ap.add_argument("--time-to-t-steps", type=int, default=200000,
