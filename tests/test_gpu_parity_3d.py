@@ -201,18 +201,26 @@ def test_mass_energy_and_checkpoint_layout():
 
 
 def test_full_size_sampled():
-    # the 256^3 FP32 box that the benchmark times, two steps, sampled against windowed oracle runs
+    # the 256^3 FP32 box that the benchmark times, two steps, sampled against windowed oracle
+    # runs, at the default launch shape and at the one the benchmark's autotuner picks there
+    # (32 x 32 lanes, 128 z slabs), which must agree bit for bit
     n = 256
     p = params3(n, n, n, 1, alpha=0.2)
     phi0 = inputs.spinodal3(n, n, n, seed=5, amp=0.05)
-    with lb().Sim(p) as s:
-        s.init(phi0)
-        s.step(2)
-        got = s.phi()
     rng = np.random.default_rng(0)
     pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 9, 250)] + [tuple(rng.integers(0, n, 3)) for _ in range(5)]
     want = common.sampled_oracle_phi3(phi0, p, 2, pts)
-    assert np.abs(np.array([got[q] for q in pts]) - want).max() <= 1e-6
+    runs = []
+    for tiling in (None, (1024, 128)):
+        print(f"case 256^3 tiling={tiling}", flush=True)
+        with lb().Sim(p) as s:
+            if tiling:
+                s.set_tiling(*tiling)
+            s.init(phi0)
+            s.step(2)
+            runs.append(s.phi())
+        assert np.abs(np.array([runs[-1][q] for q in pts]) - want).max() <= 1e-6
+    assert np.array_equal(runs[0], runs[1])
 
 
 @pytest.mark.parametrize("alpha", [0.1, 0.3])
