@@ -102,7 +102,7 @@ struct HeadArgs {
 
 template <int TC, bool RELU, bool UPCAT, bool HEAD = false, bool POOL = false, bool UPADJ = false,
           bool POOLADJ = false>
-__global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
+__global__ __launch_bounds__(256, TC == 32 ? 3 : 2) void conv3_fwd_k(const __bf16* __restrict__ X, const __bf16* __restrict__ X2, int Cu,
                                                    const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                    __bf16* __restrict__ Y, int H, int Wd, int Ci, int Co,
                                                    const HeadArgs hd = HeadArgs{}, __bf16* __restrict__ Yp = nullptr,
@@ -130,21 +130,27 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
         for (int c = 0; c < CB; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // per-thread source offsets (chunk-independent parts); indices past the
-    // end are clamped to the last chunk (loaded, never stored)
+    // end are clamped to the last chunk (loaded, never stored).  Pixel indices
+    // are 32-bit (the launchers require N H W < 2^31), widened by one multiply;
+    // weight offsets are 32-bit.
     long long xoff[RX];
     long long xoff2[UPCAT ? RX : 1];
-    long long woff[RW];
+    unsigned woff[RW];
 #pragma unroll
     for (int i = 0; i < RX; ++i) {
         const int q = min((int)threadIdx.x + i * 256, NXQ - 1);
-        const int px = q >> 2, part = q & 3;
+        const int px = q >> 2;
+        const unsigned part8 = (unsigned)(q & 3) * 8u;
         const int py = px / 18, pxx = px - py * 18;
         const int y = wrap(ty0 - 1 + py, H), x = wrap(tx0 - 1 + pxx, Wd);
         if constexpr (UPCAT) {
-            xoff[i] = (((long long)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + part * 8;
-            xoff2[i] = (((long long)n * H + y) * Wd + x) * (Ci - Cu) + part * 8;
+            const unsigned pu = (unsigned)(n * (H / 2) + (y >> 1)) * (unsigned)(Wd / 2) + (unsigned)(x >> 1);
+            const unsigned ps = (unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x;
+            xoff[i] = (long long)((unsigned long long)pu * (unsigned)Cu + part8);
+            xoff2[i] = (long long)((unsigned long long)ps * (unsigned)(Ci - Cu) + part8);
         } else {
-            xoff[i] = (((long long)n * H + y) * Wd + x) * Ci + part * 8;
+            const unsigned ps = (unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x;
+            xoff[i] = (long long)((unsigned long long)ps * (unsigned)Ci + part8);
         }
     }
 #pragma unroll
@@ -152,8 +158,19 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
         const int q = min((int)threadIdx.x + i * 256, NWQ - 1);
         const int row = q >> 2, part = q & 3;
         const int tap = row / TC, co = row - tap * TC;
-        woff[i] = ((long long)(co0 + co) * 9 + tap) * Ci + part * 8;
+        woff[i] = ((unsigned)(co0 + co) * 9u + (unsigned)tap) * (unsigned)Ci + (unsigned)part * 8u;
     }
+    // LDS element offsets.  Staging: chunk q = threadIdx.x + 256 i goes to
+    // lds_part(q / 4, q % 4); its swizzle term ((q / 4) >> 1) & 3 does not
+    // depend on i, so the offsets are ls + 2048 i.  A reads: row tap TC + 16 c
+    // + l16 has the swizzle term of row l16.  B reads: row P0 + l16 with
+    // P0 = 72 wave + 18 j + kx has the swizzle term ((r + l16) >> 1) & 3,
+    // r = P0 mod 8 = (18 j + kx) mod 8, so eight lane bases serve every (j, kx).
+    const int ls = lds_part((int)threadIdx.x >> 2, (int)threadIdx.x & 3);
+    const int la = lds_part(l16, kb);
+    int lbb[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lbb[r] = (wave * 72 + l16) * 32 + ((kb ^ (((r + l16) >> 1) & 3)) << 3);
     bf16x8 rx[RX], rw[RW];
     // pixel-tile chunk starting at input channel cc
     auto load_x = [&](int cc) {
@@ -176,18 +193,18 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 #pragma unroll
         for (int i = 0; i < RX; ++i) {
             const int q = (int)threadIdx.x + i * 256;
-            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + lds_part(q >> 2, q & 3)) = rx[i];
+            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + ls + 2048 * i) = rx[i];
         }
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             const int q = (int)threadIdx.x + i * 256;
-            if (q < NWQ) *reinterpret_cast<bf16x8*>(sw + lds_part(q >> 2, q & 3)) = rw[i];
+            if (q < NWQ) *reinterpret_cast<bf16x8*>(sw + ls + 2048 * i) = rw[i];
         }
         __syncthreads();
         if (cc + 32 < Ci) {                       // next chunk in flight during the MFMAs
             load_x(cc + 32);
 #pragma unroll
-            for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + woff[i] + cc + 32);
+            for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + (woff[i] + (unsigned)(cc + 32)));
         }
         // Taps in kx-major order t = 3 kx + ky.  B rows wave * 4 + j (j = 0..5) at
         // column l16 + kx live in bq[kx & 1][j] (tap (kx, ky) uses rows ky..ky+3);
@@ -195,12 +212,12 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
         // read from LDS while the MFMAs of tap t run.
         bf16x8 bq[2][6], aq[2][CB];
         auto ld_b = [&](int kx, int j, bf16x8& v) {
-            v = *reinterpret_cast<const bf16x8*>(sx + lds_part((wave * 4 + j) * 18 + l16 + kx, kb));
+            v = *reinterpret_cast<const bf16x8*>(sx + lbb[(18 * j + kx) & 7] + (18 * j + kx) * 32);
         };
         auto ld_a = [&](int kx, int ky, bf16x8 (&a)[CB]) {
 #pragma unroll
             for (int c = 0; c < CB; ++c)
-                a[c] = *reinterpret_cast<const bf16x8*>(sw + lds_part((ky * 3 + kx) * TC + c * 16 + l16, kb));
+                a[c] = *reinterpret_cast<const bf16x8*>(sw + la + ((ky * 3 + kx) * TC + c * 16) * 32);
         };
 #pragma unroll
         for (int j = 0; j < 4; ++j) ld_b(0, j, bq[0][j]);
@@ -254,7 +271,7 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
             for (int j = 0; j < 4; ++j) hv[c][j] = hd.w[co0 + c * 16 + kb * 4 + j];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            xr[r] = hd.xin[(((size_t)n * H + ty0 + wave * 4 + r) * Wd + tx0 + l16) * hd.cin];
+            xr[r] = hd.xin[(size_t)((unsigned)(n * H + ty0 + wave * 4 + r) * (unsigned)Wd + (unsigned)(tx0 + l16)) * hd.cin];
         hb0 = hd.b[0];
     }
     bf16x4 prev[POOL || UPADJ ? CB : 1];   // row r - 1 of the 2x2 block (POOL, UPADJ)
@@ -288,12 +305,14 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
                     mk[r][c] = *reinterpret_cast<const bf16x4*>(
-                        Mask + (((size_t)n * H + ty0 + wave * 4 + r) * Wd + tx0 + l16) * Co + co0 + c * 16 + kb * 4);
+                        Mask + (size_t)((unsigned)(n * H + ty0 + wave * 4 + r) * (unsigned)Wd + (unsigned)(tx0 + l16)) *
+                                   Co + co0 + c * 16 + kb * 4);
         }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int y = ty0 + wave * 4 + r, x = tx0 + l16;
+        const size_t pix = (unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x;   // N H W < 2^31
         float part = 0.f;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
@@ -356,7 +375,7 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
                 }
                 continue;
             }
-            if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + (((size_t)n * H + y) * Wd + x) * Co + co) = o;
+            if (!HEAD || Y) *reinterpret_cast<bf16x4*>(Y + pix * Co + co) = o;
             if constexpr (POOL) {
                 if ((r & 1) == 0) {
                     prev[c] = o;
@@ -377,7 +396,7 @@ __global__ __launch_bounds__(256, TC == 32 && !UPCAT ? 3 : 2) void conv3_fwd_k(c
             // lanes l16, l16 + 16, l16 + 32, l16 + 48 hold the four channel groups of one pixel
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
-            if (kb == 0) hd.out[((size_t)n * H + y) * Wd + x] = xr[r] + hd.scale * (hb0 + part);
+            if (kb == 0) hd.out[pix] = xr[r] + hd.scale * (hb0 + part);
         }
     }
 }
@@ -1159,6 +1178,9 @@ __global__ void widen_k(const __bf16* __restrict__ a, float* __restrict__ b, lon
 
 // ----------------------------------------------------------------- launchers
 namespace {
+// the forward kernel forms pixel indices in 32 bits
+bool pix_over(int N, int H, int Wd) { return (long long)N * H * Wd >= (1LL << 31); }
+
 int grid_for(long long n) {
     long long b = (n + 255) / 256;
     return (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
@@ -1187,12 +1209,14 @@ hipError_t conv3_fwd_any(const __bf16* X, const __bf16* X2, int Cu, const __bf16
 
 hipError_t conv3_fwd(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd, int Ci,
                      int Co, bool relu, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Ci % 32 || Co % 32) return hipErrorInvalidValue;
     return conv3_fwd_any<false>(X, nullptr, 0, Wt, bias, Y, N, H, Wd, Ci, Co, relu, s);
 }
 
 hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mask, __bf16* Y, int N, int H, int Wd,
                             int Ci, int Co, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Ci % 32 || Co % 32 || !Mask) return hipErrorInvalidValue;
     const int tiles = N * (H / 16) * (Wd / 16);
     if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512)
@@ -1206,6 +1230,7 @@ hipError_t conv3_fwd_masked(const __bf16* X, const __bf16* Wt, const __bf16* Mas
 
 hipError_t conv3_fwd_upadj(const __bf16* X, const __bf16* Wt, __bf16* dU, __bf16* dS, const __bf16* mask_u,
                            const __bf16* mask_s, int N, int H, int Wd, int Ci, int Cu, int Cs, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Ci % 32 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || !dU || !dS)
         return hipErrorInvalidValue;
     const int tiles = N * (H / 16) * (Wd / 16);
@@ -1221,6 +1246,7 @@ hipError_t conv3_fwd_upadj(const __bf16* X, const __bf16* Wt, __bf16* dU, __bf16
 
 hipError_t conv3_fwd_pooladj(const __bf16* X, const __bf16* Wt, __bf16* dX2, const __bf16* mask, int N, int H, int Wd,
                             int Ci, int Co, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Ci % 32 || Co % 32 || !dX2) return hipErrorInvalidValue;
     const int tiles = N * (H / 16) * (Wd / 16);
     if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512)
@@ -1234,12 +1260,14 @@ hipError_t conv3_fwd_pooladj(const __bf16* X, const __bf16* Wt, __bf16* dX2, con
 
 hipError_t conv3_fwd_upcat(const __bf16* U, const __bf16* Sk, const __bf16* Wt, const float* bias, __bf16* Y, int N,
                            int H, int Wd, int Cu, int Cs, int Co, bool relu, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Cu < 32 || Cu % 32 || Cs < 32 || Cs % 32 || Co % 32) return hipErrorInvalidValue;
     return conv3_fwd_any<true>(U, Sk, Cu, Wt, bias, Y, N, H, Wd, Cu + Cs, Co, relu, s);
 }
 
 hipError_t conv3_fwd_relu_pool(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, __bf16* Yp, int N, int H,
                                int Wd, int Ci, int Co, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Ci % 32 || Co % 32 || !Y || !Yp) return hipErrorInvalidValue;
     const int tiles = N * (H / 16) * (Wd / 16);
     if (Co % 64 == 0 && (long long)tiles * (Co / 64) >= 512) {
@@ -1281,6 +1309,7 @@ hipError_t conv3_pair0(const float* phi, const float* cond, int ncond, const __b
 hipError_t conv3_fwd_relu_head(const __bf16* X, const __bf16* Wt, const float* bias, __bf16* Y, int N, int H, int Wd,
                                int Ci, int Co, const float* hw, const float* hb, const float* xin, int cin, float* out,
                                float scale, hipStream_t s) {
+    if (pix_over(N, H, Wd)) return hipErrorInvalidValue;
     if (H % 16 || Wd % 16 || Ci % 32 || (Co != 32 && Co != 64) || !hw || !hb || !xin || !out || cin < 1)
         return hipErrorInvalidValue;
     const HeadArgs hd{hw, hb, xin, cin, out, scale};
