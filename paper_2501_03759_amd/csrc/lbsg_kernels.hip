@@ -550,7 +550,7 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
             if (q < 20 * 20) {
                 const int py = q / 20, px = q - py * 20;
                 const int y = wrap(ty0 - 2 + py, H), x = wrap(tx0 - 2 + px, Wd);
-                pv[i] = phi[((size_t)n * H + y) * Wd + x];
+                pv[i] = phi[(unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x];   // N H W < 2^31
             }
         }
     };
@@ -591,6 +591,36 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
             bv1[c][j] = b1 ? b1[c * 16 + kb * 4 + j] : 0.f;
             bv[c][j] = b2 ? b2[c * 16 + kb * 4 + j] : 0.f;
         }
+    // Stage 1 work of a wave: halo rows r = wave / 2 + 2 i (i = 0..8), column
+    // segment c0 = 2 (wave & 1) of width 16 (the two segments of a row overlap
+    // in columns 2..15; the second stores only columns 16, 17).  Its sphi reads
+    // (tap t = 4 s + kb of the packed K) sit at fixed offsets from the lane's
+    // base; its sa row p = (wave / 2 + 2 i) 18 + c0 + l16 has the swizzle term
+    // ((p0 >> 1) + 2 i) & 3 with p0 the row at i = 0, so two lane bases serve
+    // the nine rows.  Stage 2 reads rows P0 + l16, P0 = 72 wave + 18 j + kx,
+    // whose swizzle term is fixed by (18 j + kx) mod 8: eight lane bases.
+    const int c0 = (wave & 1) * 2, r0 = wave >> 1;
+    int sp[3];
+    bool tz[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int t = 4 * s + kb, ky = t / 3, kx = t - 3 * (t / 3);
+        tz[s] = t >= 9;
+        sp[s] = ((r0 + (t < 9 ? ky : 0)) * 20 + c0 + l16 + (t < 9 ? kx : 0)) * 8;
+    }
+    const int col = c0 + l16;
+    const bool st1 = c0 == 0 || col >= 16;
+    int sab[CB][2];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p0 = r0 * 18 + col, part = 2 * c + (kb >> 1);
+            sab[c][h] = p0 * 32 + ((part ^ (((p0 >> 1) + 2 * h) & 3)) << 3) + (kb & 1) * 4;
+        }
+    int lbb[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lbb[r] = (wave * 72 + l16) * 32 + ((kb ^ (((r + l16) >> 1) & 3)) << 3);
     for (int it = 0; it < NT; ++it) {
         const int ty0 = gy0 + 16 * it;
         if (it > 0) __syncthreads();              // every wave is done with the previous tile's sphi, sa
@@ -606,27 +636,22 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
         __syncthreads();
         if (it + 1 < NT) load_phi(ty0 + 16);   // the next tile's phi in flight during this one
         // ---- stage 1: a over the 18 x 18 halo tile (36 row segments, 9 per wave) ----
-        for (int rt = wave; rt < 36; rt += 4) {
-            const int r = rt >> 1, c0 = (rt & 1) * 2;   // halo row, first column of the segment
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
             f32x4 acc[CB];
 #pragma unroll
             for (int c = 0; c < CB; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                const int t = 4 * s + kb;
-                const int ky = t / 3, kx = t - 3 * (t / 3);
-                bf16x8 bq;
-                if (t < 9) {
-                    bq = *reinterpret_cast<const bf16x8*>(sphi + ((r + ky) * 20 + c0 + l16 + kx) * 8);
-                } else {
+                bf16x8 bq = *reinterpret_cast<const bf16x8*>(sphi + sp[s] + i * 2 * 20 * 8);
+                if (s == 2 && tz[2]) {   // taps 9..11 exist only in K-step 2
 #pragma unroll
                     for (int c = 0; c < 8; ++c) bq[c] = (__bf16)0.f;
                 }
 #pragma unroll
                 for (int c = 0; c < CB; ++c) acc[c] = mfma16(a1[s][c], bq, acc[c]);
             }
-            const int col = c0 + l16;
-            if (c0 == 0 || col >= 16) {
+            if (st1) {
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
                     bf16x4 o;
@@ -636,7 +661,7 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
                         o[j] = (__bf16)(v > 0.f ? v : 0.f);
                     }
                     // channels c * 16 + 4 kb .. + 3: 16-byte part 2 c + kb / 2, half kb & 1
-                    *reinterpret_cast<bf16x4*>(sa + lds_part(r * 18 + col, 2 * c + (kb >> 1)) + (kb & 1) * 4) = o;
+                    *reinterpret_cast<bf16x4*>(sa + sab[c][i & 1] + i * 36 * 32) = o;
                 }
             }
         }
@@ -648,21 +673,23 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
 #pragma unroll
             for (int c = 0; c < CB; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int kx = t / 3, ky = t % 3;
-            bf16x8 bq[4];
+        for (int kx = 0; kx < 3; ++kx) {
+            bf16x8 bq[6];   // rows wave * 4 + j at column l16 + kx; tap (kx, ky) uses rows ky..ky+3
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                bq[r] = *reinterpret_cast<const bf16x8*>(sa + lds_part((wave * 4 + ky + r) * 18 + l16 + kx, kb));
+            for (int j = 0; j < 6; ++j)
+                bq[j] = *reinterpret_cast<const bf16x8*>(sa + lbb[(18 * j + kx) & 7] + (18 * j + kx) * 32);
 #pragma unroll
-            for (int c = 0; c < CB; ++c)
+            for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq2[t][c], bq[r], acc[r][c]);
+                for (int c = 0; c < CB; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq2[3 * kx + ky][c], bq[ky + r], acc[r][c]);
         }
         bf16x4 prev[CB];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int y = ty0 + wave * 4 + r, x = tx0 + l16;
+            const size_t pix = (unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const int co = c * 16 + kb * 4;
@@ -673,7 +700,7 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
                     v = v > 0.f ? v : 0.f;
                     o[j] = (__bf16)v;
                 }
-                *reinterpret_cast<bf16x4*>(E + (((size_t)n * H + y) * Wd + x) * 32 + co) = o;
+                *reinterpret_cast<bf16x4*>(E + pix * 32 + co) = o;
                 if ((r & 1) == 0) {
                     prev[c] = o;
                 } else {
@@ -685,8 +712,9 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
                         q[j] = (__bf16)(0.25f * ((up + lane_xor1(up)) + (lo + lane_xor1(lo))));
                     }
                     if ((l16 & 1) == 0)
-                        *reinterpret_cast<bf16x4*>(P + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * 32 + co) =
-                            q;
+                        *reinterpret_cast<bf16x4*>(
+                            P + (size_t)((unsigned)(n * (H / 2) + y / 2) * (unsigned)(Wd / 2) + (unsigned)(x / 2)) * 32 +
+                            co) = q;
                 }
             }
         }
@@ -1296,7 +1324,7 @@ hipError_t conv3_first(const __bf16* X, int Cs, const float* phi, const float* c
 
 hipError_t conv3_pair0(const float* phi, const float* cond, int ncond, const __bf16* W1k, const float* b1,
                        const __bf16* W2, const float* b2, __bf16* E, __bf16* P, int N, int H, int Wd, hipStream_t s) {
-    if (H % 16 || Wd % 16 || ncond < 0 || ncond > 7 || !phi || (ncond && !cond) || !E || !P)
+    if (pix_over(N, H, Wd) || H % 16 || Wd % 16 || ncond < 0 || ncond > 7 || !phi || (ncond && !cond) || !E || !P)
         return hipErrorInvalidValue;
     // four tiles per workgroup where H allows (the weights staged once per 1024 pixels)
     if (H % 64 == 0)
