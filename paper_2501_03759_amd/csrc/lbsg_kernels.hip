@@ -783,19 +783,22 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
     bf16x8 ry[NYI], rx[NXI];
     const bool bsum = bpart != nullptr && blockIdx.z == 0;
     float csum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // channels co0 + 8 (tid % (TCO / 8)) + e
+    // dY chunk q = threadIdx.x + NT i is pixel q / (TCO / 8) of the tile (row
+    // dyr + 2 i, column dyc) and channels 8 (q % (TCO / 8)): a lane-constant
+    // offset from the tile's first pixel plus i rows of two.  Pixel indices
+    // are 32-bit (the launcher requires N H W < 2^31).
+    const int dyr = (int)threadIdx.x / (16 * TCO / 8), dyc = ((int)threadIdx.x / (TCO / 8)) & 15;
+    const unsigned dych = co0 + ((int)threadIdx.x % (TCO / 8)) * 8;
     auto load_tile = [&](int tile) {
         int b = tile;
         const int tx0 = (b % tiles_x) * 16;
         b /= tiles_x;
         const int ty0 = (b % tiles_y) * 16;
         const int n = b / tiles_y;
+        const __bf16* py0 = dY + (size_t)((unsigned)(n * H + ty0 + dyr) * (unsigned)Wd + (unsigned)(tx0 + dyc)) * Co + dych;
 #pragma unroll
-        for (int i = 0; i < NYI; ++i) {
-            const int q = (int)threadIdx.x + i * NT;
-            const int px = q / (TCO / 8), ch = q % (TCO / 8);
-            ry[i] = *reinterpret_cast<const bf16x8*>(
-                dY + (((size_t)n * H + ty0 + (px >> 4)) * Wd + tx0 + (px & 15)) * Co + co0 + ch * 8);
-        }
+        for (int i = 0; i < NYI; ++i)
+            ry[i] = *reinterpret_cast<const bf16x8*>(py0 + (size_t)i * 2 * Wd * Co);
 #pragma unroll
         for (int i = 0; i < NXI; ++i) {
             const int q = (int)threadIdx.x + i * NT;
@@ -804,10 +807,12 @@ __global__ __launch_bounds__(TCO * 4) void conv3_dw_k(const __bf16* __restrict__
                 const int y = wrap(ty0 - 1 + hp / 18, H), x = wrap(tx0 - 1 + hp % 18, Wd);
                 const __bf16* src;
                 if constexpr (UPCAT) {
-                    src = ci0 < Cu ? X + (((size_t)n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * Cu + ci0 + ch * 8
-                                   : X2 + (((size_t)n * H + y) * Wd + x) * (Ci - Cu) + (ci0 - Cu) + ch * 8;
+                    src = ci0 < Cu ? X + (size_t)((unsigned)(n * (H / 2) + (y >> 1)) * (unsigned)(Wd / 2) +
+                                                  (unsigned)(x >> 1)) * Cu + ci0 + ch * 8
+                                   : X2 + (size_t)((unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x) * (Ci - Cu) +
+                                         (ci0 - Cu) + ch * 8;
                 } else {
-                    src = X + (((size_t)n * H + y) * Wd + x) * Ci + ci0 + ch * 8;
+                    src = X + (size_t)((unsigned)(n * H + y) * (unsigned)Wd + (unsigned)x) * Ci + ci0 + ch * 8;
                 }
                 rx[i] = *reinterpret_cast<const bf16x8*>(src);
             }
@@ -1353,7 +1358,8 @@ namespace {
 template <bool UPCAT>
 hipError_t conv3_dw_any(const __bf16* X, const __bf16* X2, int Cu, const __bf16* dY, float* part, int S, int N, int H,
                         int Wd, int Ci, int Co, hipStream_t s, float* bpart) {
-    if (H % 16 || Wd % 16 || Ci % 16 || Co % 32 || S < 1 || S > N * (H / 16) * (Wd / 16)) return hipErrorInvalidValue;
+    if (pix_over(N, H, Wd) || H % 16 || Wd % 16 || Ci % 16 || Co % 32 || S < 1 || S > N * (H / 16) * (Wd / 16))
+        return hipErrorInvalidValue;
     if (Co % 64 == 0) {
         dim3 grid(S, Co / 64, Ci / 16);
         conv3_dw_k<64, UPCAT><<<grid, 256, 0, s>>>(X, dY, part, N, H, Wd, Ci, Co, S, bpart, X2, Cu);
