@@ -9,6 +9,7 @@
 namespace lbsg {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -171,40 +172,41 @@ __global__ __launch_bounds__(256, TC == 32 ? 3 : 2) void conv3_fwd_k(const __bf1
     int lbb[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) lbb[r] = (wave * 72 + l16) * 32 + ((kb ^ (((r + l16) >> 1) & 3)) << 3);
-    bf16x8 rx[RX], rw[RW];
+    // staged chunks are held as plain 32-bit words (moved, never computed on)
+    u32x4 rx[RX], rw[RW];
     // pixel-tile chunk starting at input channel cc
     auto load_x = [&](int cc) {
         if constexpr (UPCAT) {
             if (cc >= Cu) {
 #pragma unroll
-                for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X2 + xoff2[i] + (cc - Cu));
+                for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const u32x4*>(X2 + xoff2[i] + (cc - Cu));
                 return;
             }
         }
 #pragma unroll
-        for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const bf16x8*>(X + xoff[i] + cc);
+        for (int i = 0; i < RX; ++i) rx[i] = *reinterpret_cast<const u32x4*>(X + xoff[i] + cc);
     };
     load_x(0);
 #pragma unroll
-    for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + woff[i]);
+    for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const u32x4*>(Wt + woff[i]);
 
     for (int cc = 0; cc < Ci; cc += 32) {
         __syncthreads();                          // every wave is done with the previous chunk
 #pragma unroll
         for (int i = 0; i < RX; ++i) {
             const int q = (int)threadIdx.x + i * 256;
-            if (q < NXQ) *reinterpret_cast<bf16x8*>(sx + ls + 2048 * i) = rx[i];
+            if (q < NXQ) *reinterpret_cast<u32x4*>(sx + ls + 2048 * i) = rx[i];
         }
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             const int q = (int)threadIdx.x + i * 256;
-            if (q < NWQ) *reinterpret_cast<bf16x8*>(sw + ls + 2048 * i) = rw[i];
+            if (q < NWQ) *reinterpret_cast<u32x4*>(sw + ls + 2048 * i) = rw[i];
         }
         __syncthreads();
         if (cc + 32 < Ci) {                       // next chunk in flight during the MFMAs
             load_x(cc + 32);
 #pragma unroll
-            for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const bf16x8*>(Wt + (woff[i] + (unsigned)(cc + 32)));
+            for (int i = 0; i < RW; ++i) rw[i] = *reinterpret_cast<const u32x4*>(Wt + (woff[i] + (unsigned)(cc + 32)));
         }
         // Taps in kx-major order t = 3 kx + ky.  B rows wave * 4 + j (j = 0..5) at
         // column l16 + kx live in bq[kx & 1][j] (tap (kx, ky) uses rows ky..ky+3);
@@ -271,9 +273,12 @@ __global__ __launch_bounds__(256, TC == 32 ? 3 : 2) void conv3_fwd_k(const __bf1
             for (int j = 0; j < 4; ++j) hv[c][j] = hd.w[co0 + c * 16 + kb * 4 + j];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            xr[r] = hd.xin[(size_t)((unsigned)(n * H + ty0 + wave * 4 + r) * (unsigned)Wd + (unsigned)(tx0 + l16)) * hd.cin];
+            xr[r] = hd.xin[(size_t)((unsigned)(n * H + ty0 + wave * 4 + r) * (unsigned)Wd + (unsigned)(tx0 + l16)) *
+                           (unsigned)hd.cin];
         hb0 = hd.b[0];
     }
+    // byte addresses of lanes lane ^ 16 and lane ^ 32 (the head's channel-group sum)
+    const int bp16 = (lane ^ 16) << 2, bp32 = (lane ^ 32) << 2;
     bf16x4 prev[POOL || UPADJ ? CB : 1];   // row r - 1 of the 2x2 block (POOL, UPADJ)
     // the mask of the lane's outputs, loaded at once (data-gradient use)
     constexpr bool MASKABLE = !RELU && !HEAD && !POOL && !UPADJ && !POOLADJ;
@@ -394,8 +399,8 @@ __global__ __launch_bounds__(256, TC == 32 ? 3 : 2) void conv3_fwd_k(const __bf1
         }
         if constexpr (HEAD) {
             // lanes l16, l16 + 16, l16 + 32, l16 + 48 hold the four channel groups of one pixel
-            part += __shfl_xor(part, 16);
-            part += __shfl_xor(part, 32);
+            part += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(bp16, __builtin_bit_cast(int, part)));
+            part += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(bp32, __builtin_bit_cast(int, part)));
             if (kb == 0) hd.out[pix] = xr[r] + hd.scale * (hb0 + part);
         }
     }
