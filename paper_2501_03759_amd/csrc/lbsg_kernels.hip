@@ -528,7 +528,7 @@ __global__ __launch_bounds__(256, 2) void conv3_first_k(const __bf16* __restrict
 // W1k: [32][12][8] (pack flip 2), W2: [32][9][32] (the generic packed layout).
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict__ phi, const float* __restrict__ cond,
+__global__ __launch_bounds__(256, 3) void conv3_pair0_k(const float* __restrict__ phi, const float* __restrict__ cond,
                                                        int ncond, const __bf16* __restrict__ W1k,
                                                        const float* __restrict__ b1, const __bf16* __restrict__ W2,
                                                        const float* __restrict__ b2, __bf16* __restrict__ E,
@@ -575,20 +575,14 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
 #pragma unroll
     for (int c = 1; c < 8; ++c) cv[c] = (__bf16)(c <= ncond ? cond[c - 1] : 0.f);
     __syncthreads();
-    bf16x8 a1[3][CB], aq2[9][CB];
+    bf16x8 a1[3][CB];
     float bv1[CB][4], bv[CB][4];
 #pragma unroll
     for (int s = 0; s < 3; ++s)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
             a1[s][c] = *reinterpret_cast<const bf16x8*>(sw1 + ((c * 16 + l16) * 12 + 4 * s + kb) * 8);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int kx = t / 3, ky = t % 3;
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            aq2[t][c] = *reinterpret_cast<const bf16x8*>(sw2 + lds_part((ky * 3 + kx) * 32 + c * 16 + l16, kb));
-    }
+    const int la = lds_part(l16, kb);   // A row tap * 32 + 16 c + l16 has the swizzle term of row l16
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
@@ -684,11 +678,16 @@ __global__ __launch_bounds__(256, 2) void conv3_pair0_k(const float* __restrict_
             for (int j = 0; j < 6; ++j)
                 bq[j] = *reinterpret_cast<const bf16x8*>(sa + lbb[(18 * j + kx) & 7] + (18 * j + kx) * 32);
 #pragma unroll
-            for (int ky = 0; ky < 3; ++ky)
+            for (int ky = 0; ky < 3; ++ky) {
+                bf16x8 aq[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    aq[c] = *reinterpret_cast<const bf16x8*>(sw2 + la + ((ky * 3 + kx) * 32 + c * 16) * 32);
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq2[3 * kx + ky][c], bq[ky + r], acc[r][c]);
+                    for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq[c], bq[ky + r], acc[r][c]);
+            }
         }
         bf16x4 prev[CB];
 #pragma unroll
