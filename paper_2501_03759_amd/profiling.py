@@ -207,6 +207,8 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
                "tflops": tf, "alg_bytes": abytes, "ai": ai, "roofline_tflops": roof, "frac_of_roofline": tf / roof}
         if "MfmaUtil" in ctr[i]:
             row["mfma_util_pct"] = ctr[i]["MfmaUtil"]
+        if "VALUBusy" in ctr[i]:
+            row["valu_busy_pct"] = ctr[i]["VALUBusy"]
         if "FETCH_SIZE" in ctr[i] or "WRITE_SIZE" in ctr[i]:
             row["traffic_kib"] = ctr[i].get("FETCH_SIZE", 0.0) + ctr[i].get("WRITE_SIZE", 0.0)
         table.append(row)
@@ -214,15 +216,21 @@ def unet_profile(trace_dir, pmc_dirs, chans, c_in, batch, side, peak_tflops=2500
 
 
 def unet_lines(table):
-    lines = ["| layer | pixels | c_in → c_out | GFLOP | µs | TFLOP/s | roofline TFLOP/s (AI flop/B) | of roofline | MfmaUtil % |",
-             "|---|---|---|---|---|---|---|---|---|"]
+    """Markdown rows of the per-layer table; a VALUBusy column when a run collected it (the
+    vector ALU's share of the cycles: issue-bound layers show it high beside a low MfmaUtil)."""
+    valu = any("valu_busy_pct" in r for r in table)
+    head = "| layer | pixels | c_in → c_out | GFLOP | µs | TFLOP/s | roofline TFLOP/s (AI flop/B) | of roofline | MfmaUtil %"
+    lines = [head + (" | VALUBusy % |" if valu else " |"), "|---|---|---|---|---|---|---|---|---|" + ("---|" if valu else "")]
     for r in table:
         mu = f"{r['mfma_util_pct']:.1f}" if "mfma_util_pct" in r else "—"
+        vb = (f" {r['valu_busy_pct']:.1f} |" if "valu_busy_pct" in r else " — |") if valu else ""
         lines.append(f"| {r['layer']} | {r['pixels']} | {r['c_in']} → {r['c_out']} | {r['gflop']:.1f} | {r['us']:.1f} | "
-                     f"{r['tflops']:.0f} | {r['roofline_tflops']:.0f} ({r['ai']:.0f}) | {r['frac_of_roofline']:.2f} | {mu} |")
+                     f"{r['tflops']:.0f} | {r['roofline_tflops']:.0f} ({r['ai']:.0f}) | {r['frac_of_roofline']:.2f} | {mu} |"
+                     + vb)
     tot_f = sum(r["gflop"] for r in table)
     tot_us = sum(r["us"] for r in table)
-    lines.append(f"| all 3x3 convolutions | | | {tot_f:.0f} | {tot_us:.0f} | {tot_f / tot_us * 1e3:.0f} | | | |")
+    lines.append(f"| all 3x3 convolutions | | | {tot_f:.0f} | {tot_us:.0f} | {tot_f / tot_us * 1e3:.0f} | | | |"
+                 + (" |" if valu else ""))
     return lines
 
 

@@ -119,3 +119,28 @@ def test_unet_inference_table_with_the_fused_first_block(tmp_path):
     px = 64 * 64
     assert table[0]["gflop"] == 18.0 * px * (5 * 32 + 32 * 32) / 1e9
     assert table[0]["alg_bytes"] == 2 * px * (5 + 32) + 2 * (px // 4) * 32
+
+
+def test_unet_table_shows_valu_busy_beside_mfma_util(tmp_path):
+    # a --pmc run with MfmaUtil and VALUBusy per dispatch: the table takes the mean over the
+    # passes after the warm-up, per layer, and prints a VALUBusy column only when collected
+    from paper_2501_03759_amd import profiling
+    rows, ctr, t, did = [], [], 0, 0
+    for g in range(3):
+        for i in range(6):
+            name = "void lbsg::conv3_first_k<64>" if i == 0 else "void lbsg::conv3_fwd_k<32, true, false>"
+            rows.append([name, t, t + 1000])
+            t += 1010
+            did += 1
+            ctr.append([did, name, "MfmaUtil", 10.0 * (i + 1) + g])
+            ctr.append([did, name, "VALUBusy", 80.0 - i + g])
+    _write_csv(str(tmp_path / "tr" / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    _write_csv(str(tmp_path / "pmc" / "run_counter_collection.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], ctr)
+    table = profiling.unet_profile(str(tmp_path / "tr"), [str(tmp_path / "pmc")], (32, 64), 5, 2, 32)
+    assert [r["mfma_util_pct"] for r in table] == [10.0 * (i + 1) + 1.5 for i in range(6)]
+    assert [r["valu_busy_pct"] for r in table] == [80.0 - i + 1.5 for i in range(6)]
+    lines = profiling.unet_lines(table)
+    assert lines[0].endswith("| MfmaUtil % | VALUBusy % |") and lines[2].endswith("| 11.5 | 81.5 |")
+    plain = profiling.unet_lines([{k: v for k, v in r.items() if k != "valu_busy_pct"} for r in table])
+    assert plain[0].endswith("| MfmaUtil % |") and "VALUBusy" not in "".join(plain)
