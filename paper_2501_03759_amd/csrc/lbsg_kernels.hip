@@ -1215,7 +1215,7 @@ __global__ void widen_k(const __bf16* __restrict__ a, float* __restrict__ b, lon
 
 // ----------------------------------------------------------------- launchers
 namespace {
-// the forward kernel forms pixel indices in 32 bits
+// the convolution kernels form pixel indices in 32 bits
 bool pix_over(int N, int H, int Wd) { return (long long)N * H * Wd >= (1LL << 31); }
 
 int grid_for(long long n) {
