@@ -40,7 +40,10 @@ typedef struct lbsg_net lbsg_net;
 
 /* Allocates parameters (initialised He-normal from `seed`) and activation
  * buffers for up to max_batch images of max_h x max_w; with train != 0 also
- * gradient, Adam and backward buffers. */
+ * gradient, Adam and backward buffers.  max_h and max_w are multiples of
+ * 16 * 2^(levels - 1) and max_batch x max_h x max_w is below 2^31 pixels (the
+ * kernels index pixels in 32 bits); otherwise LBCH_E_INVALID before any device
+ * work. */
 lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int32_t max_h, int32_t max_w, int32_t train,
                         uint64_t seed, void* hip_stream, lbsg_net** out);
 lbch_status lbsg_destroy(lbsg_net* net);

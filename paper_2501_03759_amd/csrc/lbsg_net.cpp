@@ -303,6 +303,10 @@ extern "C" lbch_status lbsg_create(const lbsg_arch* arch, int32_t max_batch, int
     const int unit = 16 << (Lv - 1);
     if (max_batch < 1 || max_h < unit || max_w < unit || max_h % unit || max_w % unit)
         return fail(LBCH_E_INVALID, "max sizes must be positive multiples of %d", unit);
+    // the convolution kernels index pixels in 32 bits
+    if ((long long)max_batch * max_h * max_w >= (1LL << 31))
+        return fail(LBCH_E_INVALID, "max_batch x max_h x max_w = %lld pixels, at most 2^31 - 1",
+                    (long long)max_batch * max_h * max_w);
     lbsg_net* n = new (std::nothrow) lbsg_net();
     if (!n) return fail(LBCH_E_OOM, "host allocation failed");
     n->arch = *arch;

@@ -113,6 +113,19 @@ def test_create_rejects_invalid_without_gpu():
     assert ei.value.status == lbch.E_INVALID
 
 
+def test_network_create_rejects_sizes_past_the_pixel_index_range_without_gpu():
+    # the convolution kernels index pixels in 32 bits: 2 x 32768^2 = 2^31 pixels is refused
+    # before any device call; a bad level count likewise
+    from paper_2501_03759_amd import lbsg
+    L = lbsg._bind()
+    arch = lbsg.make_arch((32, 64), 5)
+    h = ctypes.c_void_p()
+    assert L.lbsg_create(ctypes.byref(arch), 2, 32768, 32768, 0, 0, None, ctypes.byref(h)) == lbch.E_INVALID
+    bad = lbsg.make_arch((32, 64), 5)
+    bad.levels = 1
+    assert L.lbsg_create(ctypes.byref(bad), 1, 64, 64, 0, 0, None, ctypes.byref(h)) == lbch.E_INVALID
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("nz", 0, lbch.E_INVALID),
     ("nz", 40, lbch.OK),
