@@ -210,9 +210,11 @@ __global__ __launch_bounds__(256, TC == 32 ? 3 : 2) void conv3_fwd_k(const __bf1
         }
         // Taps in kx-major order t = 3 kx + ky.  B rows wave * 4 + j (j = 0..5) at
         // column l16 + kx live in bq[kx & 1][j] (tap (kx, ky) uses rows ky..ky+3);
-        // the A fragments of tap t in aq[t & 1].  The operands of tap t + 1 are
-        // read from LDS while the MFMAs of tap t run.
-        bf16x8 bq[2][6], aq[2][CB];
+        // the A fragments of tap t in aq[t % 3].  The operands of tap t + 2 are
+        // read from LDS while the MFMAs of tap t run (two B buffers suffice: the
+        // tap column changes every three taps, so a two-tap lead never writes
+        // rows that tap t or t + 1 reads).
+        bf16x8 bq[2][6], aq[3][CB];
         auto ld_b = [&](int kx, int j, bf16x8& v) {
             v = *reinterpret_cast<const bf16x8*>(sx + lbb[(18 * j + kx) & 7] + (18 * j + kx) * 32);
         };
@@ -224,23 +226,25 @@ __global__ __launch_bounds__(256, TC == 32 ? 3 : 2) void conv3_fwd_k(const __bf1
 #pragma unroll
         for (int j = 0; j < 4; ++j) ld_b(0, j, bq[0][j]);
         ld_a(0, 0, aq[0]);
+        ld_b(0, 4, bq[0][4]);
+        ld_a(0, 1, aq[1]);
         auto tap = [&](auto tc) {
             constexpr int t = decltype(tc)::value, kx = t / 3, ky = t % 3;
-            constexpr int t1 = t + 1, kx1 = t1 / 3, ky1 = t1 % 3;
-            constexpr int nl = t1 < 9 ? (ky1 == 0 ? 4 : 1) + CB : 0;
-            if constexpr (t1 < 9) {
-                ld_a(kx1, ky1, aq[t1 & 1]);   // first: tap t1's first MFMAs need only these
-                if constexpr (ky1 == 0) {
+            constexpr int t2 = t + 2, kx2 = t2 / 3, ky2 = t2 % 3;
+            constexpr int nl = t2 < 9 ? (ky2 == 0 ? 4 : 1) + CB : 0;
+            if constexpr (t2 < 9) {
+                ld_a(kx2, ky2, aq[t2 % 3]);
+                if constexpr (ky2 == 0) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) ld_b(kx1, j, bq[kx1 & 1][j]);
+                    for (int j = 0; j < 4; ++j) ld_b(kx2, j, bq[kx2 & 1][j]);
                 } else {
-                    ld_b(kx1, ky1 + 3, bq[kx1 & 1][ky1 + 3]);
+                    ld_b(kx2, ky2 + 3, bq[kx2 & 1][ky2 + 3]);
                 }
             }
 #pragma unroll
             for (int c = 0; c < CB; ++c)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq[t & 1][c], bq[kx & 1][ky + r], acc[r][c]);
+                for (int r = 0; r < 4; ++r) acc[r][c] = mfma16(aq[t % 3][c], bq[kx & 1][ky + r], acc[r][c]);
             interleave_ds_mfma<nl, 4 * CB>();
         };
         tap(std::integral_constant<int, 0>{});
